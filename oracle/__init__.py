@@ -1,0 +1,196 @@
+"""FP64 CPU oracle of differentiable polarized path tracing -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this package.
+It wraps ``ppt_oracle.cpp`` (plain C++, double precision, OpenMP over pixel rows), which
+shares no code with the GPU library; it never imports the product package.
+
+Modes of :func:`OracleScene.run` (paper Sec. 3.2, 4.1, 4.3, 5.1):
+  0 render            Monte Carlo Stokes image (Eq. 2 in Mueller-Stokes calculus)
+  1 conventional AD   one stored tape per path with detached sampling ("Conv. AD")
+  2 cached replay     per-vertex cache + backward fold + local-AD replay (Sec. 4.3)
+  3 basic P-PRB       suffix recovered by Mueller inversion (Alg. 2), negative control
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "ppt_oracle.cpp")
+LIB_PATH = os.path.join(_HERE, "libppt_oracle.so")
+
+MODE_RENDER, MODE_TAPE_AD, MODE_CACHED_PRB, MODE_BASIC_PRB = 0, 1, 2, 3
+FLAG_NO_NEE = 1
+FLAG_GAUGE = 1 << 16
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (OpenMP); returns the library path."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-fopenmp", "-std=c++17", "-shared", "-fPIC", "-o", tmp, SRC])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, c_int, c_u64, c_dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
+        L.ppto_scene_load.restype = vp
+        L.ppto_scene_load.argtypes = [vp, ctypes.c_size_t, ctypes.c_char_p, c_int]
+        L.ppto_scene_free.argtypes = [vp]
+        L.ppto_scene_counts.argtypes = [vp, c_int, vp]
+        L.ppto_run.restype = c_int
+        L.ppto_run.argtypes = [vp, vp, vp, c_int, vp, c_int, c_int, ctypes.c_uint32, c_u64, c_int,
+                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int]
+        L.ppto_philox.argtypes = [c_u64, vp, vp]
+        L.ppto_fresnel.argtypes = [c_dbl, c_dbl, c_dbl, vp, vp]
+        L.ppto_polarizer.argtypes = [c_dbl, vp]
+        L.ppto_retarder.argtypes = [c_dbl, vp]
+        L.ppto_rotator.argtypes = [vp, vp, vp, vp]
+        L.ppto_canon_x.argtypes = [vp, vp]
+        L.ppto_ggx_eval.argtypes = [vp, vp, vp, c_dbl, c_dbl, c_dbl, vp]
+        L.ppto_trace.restype = c_int
+        L.ppto_trace.argtypes = [vp, c_int, vp, vp, c_dbl, c_int, c_int, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ptr_array(arrs):
+    """ctypes array of double* (None -> NULL); keeps the arrays referenced by the caller."""
+    t = (ctypes.c_void_p * len(arrs))()
+    for i, a in enumerate(arrs):
+        t[i] = None if a is None else a.ctypes.data
+    return t
+
+
+class OracleScene:
+    def __init__(self, blob: bytes, slot_numel):
+        self._blob = blob
+        self.slot_numel = [int(n) for n in slot_numel]
+        err = ctypes.create_string_buffer(256)
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self.h = lib().ppto_scene_load(buf, len(blob), err, 256)
+        if not self.h:
+            raise ValueError("oracle scene load failed: " + err.value.decode())
+
+    @classmethod
+    def from_scene(cls, scene):
+        return cls(scene.to_blob(), [v.size for v in scene.slot_values])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().ppto_scene_free(self.h)
+            self.h = None
+
+    def counts(self, world=0):
+        out = np.zeros(4, np.int32)
+        lib().ppto_scene_counts(self.h, world, _ptr(out))
+        return out
+
+    def run(self, params, views, max_depth, seed, flags=0, mode=MODE_RENDER, d_image=None, params_val=None,
+            grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0):
+        """Run the oracle.  ``params`` (and ``params_val``) are per-slot arrays (converted to float64).
+
+        Returns a dict with ``image`` (float64, [V][A][h][w][3][4] flattened per view),
+        ``grads`` (list per slot, None where not requested), ``sig`` (uint64 per path),
+        ``n_vertices`` and ``n_paths``.
+        """
+        from scenegen import VIEW_DTYPE, image_numel  # input-layout helpers only
+
+        views = np.ascontiguousarray(views, VIEW_DTYPE)
+        pp = [np.ascontiguousarray(p, np.float64) for p in params]
+        pv = pp if params_val is None else [np.ascontiguousarray(p, np.float64) for p in params_val]
+        n_img = image_numel(views)
+        n_paths = int(np.sum(views["crop_w"].astype(np.int64) * views["crop_h"] * views["spp"]))
+        image = np.zeros(n_img, np.float64) if want_image else None
+        grads = [None] * len(pp)
+        if mode != MODE_RENDER:
+            want = range(len(pp)) if grad_slots is None else grad_slots
+            for s in want:
+                grads[s] = np.zeros(self.slot_numel[s], np.float64)
+            d_image = np.ascontiguousarray(d_image, np.float64)
+            assert d_image.size == n_img
+        sig = np.zeros(n_paths, np.uint64) if want_sig else None
+        mk = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+        stats = np.zeros(2, np.int64)
+        err = ctypes.create_string_buffer(256)
+        ptp, ptv, pg = _ptr_array(pp), _ptr_array(pv), _ptr_array(grads)
+        rc = lib().ppto_run(self.h, ptp, ptv, len(pp), _ptr(views), len(views), int(max_depth), int(flags),
+                            int(seed) & (2 ** 64 - 1), int(mode),
+                            None if d_image is None else _ptr(d_image),
+                            None if image is None else _ptr(image), pg,
+                            None if sig is None else _ptr(sig), None if mk is None else _ptr(mk),
+                            _ptr(stats), int(nthreads), err, 256)
+        if rc != 0:
+            raise ValueError("oracle run failed: " + err.value.decode())
+        return {"image": image, "grads": grads, "sig": sig, "n_vertices": int(stats[0]), "n_paths": int(stats[1])}
+
+
+# ---- unit-level helpers for the pin tests
+def philox(seed, ctr):
+    c = np.asarray(ctr, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().ppto_philox(int(seed), _ptr(c), _ptr(o))
+    return o
+
+
+def fresnel(cos_i, m):
+    m = complex(m)
+    R = np.zeros(16); T = np.zeros(16)
+    lib().ppto_fresnel(float(cos_i), m.real, m.imag, _ptr(R), _ptr(T))
+    return R.reshape(4, 4), T.reshape(4, 4)
+
+
+def polarizer(theta):
+    M = np.zeros(16)
+    lib().ppto_polarizer(float(theta), _ptr(M))
+    return M.reshape(4, 4)
+
+
+def retarder(delta):
+    M = np.zeros(16)
+    lib().ppto_retarder(float(delta), _ptr(M))
+    return M.reshape(4, 4)
+
+
+def rotator(k, x_from, x_to):
+    M = np.zeros(16)
+    a = [np.ascontiguousarray(v, np.float64) for v in (k, x_from, x_to)]
+    lib().ppto_rotator(_ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(M))
+    return M.reshape(4, 4)
+
+
+def canon_x(k):
+    k = np.ascontiguousarray(k, np.float64)
+    x = np.zeros(3)
+    lib().ppto_canon_x(_ptr(k), _ptr(x))
+    return x
+
+
+def ggx_eval(ns, wi, wo, alpha, m):
+    m = complex(m)
+    f = np.zeros(16)
+    a = [np.ascontiguousarray(v, np.float64) for v in (ns, wi, wo)]
+    lib().ppto_ggx_eval(_ptr(a[0]), _ptr(a[1]), _ptr(a[2]), float(alpha), m.real, m.imag, _ptr(f))
+    return f.reshape(4, 4)
+
+
+def trace(scene: OracleScene, o, d, tmax=1e30, any_hit=False, brute=False, world=0):
+    o = np.ascontiguousarray(o, np.float64); d = np.ascontiguousarray(d, np.float64)
+    t = np.zeros(1)
+    prim = lib().ppto_trace(scene.h, world, _ptr(o), _ptr(d), float(tmax), int(any_hit), int(brute), _ptr(t))
+    return prim, float(t[0])
