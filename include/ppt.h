@@ -1,0 +1,146 @@
+/* ppt.h -- C ABI of the MI355X (gfx950) differentiable polarized path tracer.
+ *
+ * The library renders Stokes images with Monte Carlo path tracing in Mueller-Stokes
+ * calculus and computes reverse-mode gradients of them with path replay backpropagation
+ * using cached suffix radiance, so no Mueller matrix is ever inverted (paper: Sec. 3.1
+ * problem statement and Eq. 1-2; Sec. 3.2 path replay; Sec. 3.3 Mueller-Stokes calculus;
+ * Sec. 4.3 and Fig. 2 cached suffix replay).  All arithmetic runs in hand-written HIP
+ * kernels for gfx950 in FP32 (gradients are accumulated in FP64).
+ *
+ * Conventions for every entry point
+ *   - Return value: PPT_OK (0) or a negative PPT_E* code; ppt_last_error() then holds a
+ *     message (thread-local).  Nothing aborts and no C++ exception crosses the ABI.
+ *   - "device" pointers are HIP device memory owned by the caller (e.g. torch tensors);
+ *     "host" pointers are ordinary host memory owned by the caller and only read during
+ *     the call.  Objects created by the library (scene, plan) own their device memory
+ *     until destroyed.
+ *   - `stream` is a hipStream_t passed as void*; work is enqueued on it and no call
+ *     synchronizes the host except where stated.  Entry points that enqueue work contain
+ *     only kernel launches, so they can be captured in a HIP graph.
+ *   - A scene and a plan may be used concurrently on different streams provided each call
+ *     gets its own workspace.
+ */
+#ifndef PPT_H
+#define PPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PPT_OK 0
+#define PPT_EINVAL (-1)       /* invalid argument, size or layout */
+#define PPT_ENOMEM (-2)       /* device allocation failed */
+#define PPT_EDEVICE (-3)      /* HIP runtime or launch error */
+#define PPT_EUNSUPPORTED (-4) /* valid request outside the compiled limits */
+
+/* flags of ppt_plan_create */
+#define PPT_FLAG_NO_NEE 1u    /* pure BSDF sampling: every emitter hit counts, no light sampling */
+
+/* sensor types of ppt_view.sensor */
+#define PPT_SENSOR_NONE 0      /* full Stokes vector in the sensor frame */
+#define PPT_SENSOR_POLARIZER 1 /* ideal linear polarizer at angle theta (a parameter, radians) */
+#define PPT_SENSOR_ANALYZER4 2 /* polarizers at 0, 45, 90 degrees and QWP(0) followed by 45 degrees */
+
+/* One camera view (88 bytes, host memory).  The image is width x height pixels; only the
+ * window [crop_x0, crop_x0 + crop_w) x [crop_y0, crop_y0 + crop_h) is rendered.  The
+ * random stream of a path is keyed by (pixel index in the full image, sample, view_id),
+ * so a window or a batch renders exactly the same paths as the full single view.
+ * The sensor frame for light arriving along k = -ray has x = right vector projected
+ * perpendicular to k and y = k x x; polarizer angles are measured from x toward y. */
+typedef struct ppt_view {
+    int32_t world;                       /* world index inside the scene */
+    int32_t width, height, spp;          /* image size and samples per pixel (>= 1) */
+    int32_t crop_x0, crop_y0, crop_w, crop_h;
+    float origin[3], target[3], up[3];   /* pinhole camera */
+    float fov_y_deg;                     /* vertical field of view */
+    int32_t sensor;                      /* PPT_SENSOR_* */
+    int32_t theta_slot, theta_off;       /* parameter element holding theta (POLARIZER only) */
+    uint32_t view_id;                    /* random-stream index of the view (< 2^24) */
+} ppt_view;
+
+typedef struct ppt_plan_opts {
+    int32_t samples_per_item; /* samples of one pixel tile processed by one work item; 0 = auto */
+    int32_t grid_waves;       /* resident wavefronts of the persistent launch; 0 = from occupancy */
+} ppt_plan_opts;
+
+typedef struct ppt_scene ppt_scene;
+typedef struct ppt_plan ppt_plan;
+
+/* Parse a binary scene blob (format: DESIGN.md, "Scene blob"), build one SAH bounding
+ * volume hierarchy per world on the host and upload everything to the current device.
+ * blob/nbytes: host memory.  *out receives a library-owned handle.
+ * Errors: PPT_EINVAL for a malformed blob (truncated, bad magic, indices out of range),
+ * PPT_ENOMEM / PPT_EDEVICE for device failures. */
+int ppt_scene_create(const void* blob, size_t nbytes, ppt_scene** out);
+void ppt_scene_destroy(ppt_scene* scene);
+
+/* Number of parameter slots; if numel_out is not NULL it receives min(cap, n) element counts. */
+int ppt_scene_slots(const ppt_scene* scene, int32_t* n_slots, int64_t* numel_out, int32_t cap);
+
+/* Fix the views, the maximum path depth (1..64 surface interactions) and the flags of a
+ * family of calls: uploads the view table and the work queue (tiles of 8x8 pixels times
+ * sample chunks, one item per wavefront).  views: host array of n_views records. */
+int ppt_plan_create(const ppt_scene* scene, const ppt_view* views, int32_t n_views, int32_t max_depth,
+                    uint32_t flags, const ppt_plan_opts* opts, ppt_plan** out);
+void ppt_plan_destroy(ppt_plan* plan);
+
+/* Output layout: the concatenation over views of [A][crop_h][crop_w][3][4] float32 (A = 4 for
+ * PPT_SENSOR_ANALYZER4, else 1; 3 RGB channels; Stokes s0..s3).  Paths are numbered
+ * (view, crop row, crop column, sample). */
+int64_t ppt_plan_image_numel(const ppt_plan* plan);
+int64_t ppt_plan_num_paths(const ppt_plan* plan);
+
+/* Device workspace bytes needed by ppt_render (op = 0) or ppt_backward (op = 1).  The
+ * backward workspace holds the per-vertex cache of every resident lane (constant in the
+ * number of paths) and the FP64 gradient accumulators. */
+size_t ppt_plan_workspace_bytes(const ppt_plan* plan, int32_t op);
+
+/* Optional per-path mask (device, one byte per path, NULL = all paths).  A path whose byte is
+ * zero contributes nothing to images or gradients.  The buffer must outlive its use. */
+int ppt_plan_set_path_mask(ppt_plan* plan, const uint8_t* mask);
+
+/* Render (Sec. 3.1, Eq. 2): every pixel is the mean over its samples of S(theta) sum_b beta_b E_b
+ * in Mueller-Stokes calculus.  params: host array of n_params device pointers, one per scene
+ * slot, each float32 with the slot's element count.  stokes_out: device, image_numel floats,
+ * overwritten.  ws: device workspace of at least ppt_plan_workspace_bytes(plan, 0) bytes. */
+int ppt_render(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
+               float* stokes_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse-mode gradient by path replay with cached suffix radiance (Sec. 3.2, 4.3, Fig. 2):
+ * grads[k] = d(sum d_stokes . I) / d params[k] for the estimator I of ppt_render with the same
+ * seed (a different seed gives the decorrelated replay of Sec. 3.2).  Sampling is detached:
+ * positions, directions, lobe choices and pdfs are constants; Mueller/BSDF values, emission
+ * and the sensor Mueller matrix are differentiated.  d_stokes: device, image layout.
+ * grads: host array of n_params device pointers (float32, slot sizes); NULL entries are
+ * skipped, the others are overwritten.  ws: at least ppt_plan_workspace_bytes(plan, 1). */
+int ppt_backward(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
+                 const float* d_stokes, float* const* grads, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-path 64-bit signatures (FNV-1a over primitive id, light-sample state and lobe of every
+ * vertex) used to detect paths whose discrete decisions differ from another implementation.
+ * sig_out: device, num_paths uint64.  ws as for ppt_render. */
+int ppt_signatures(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
+                   uint64_t* sig_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Counters accumulated in a workspace by every render/backward call since its last setup:
+ * out[0] path vertices, [1] paths, [2] BVH nodes visited, [3] primitive tests, [4] shadow rays.
+ * Synchronizes the stream.  ws: device workspace; out: host, 5 entries. */
+int ppt_read_stats(const void* ws, int64_t* out, void* stream);
+
+/* Philox4x32-10 (Salmon et al. 2011) on n counters: ctr and out are device arrays of n x 4
+ * uint32; key = (seed low 32 bits, seed high 32 bits). */
+int ppt_debug_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, void* stream);
+
+/* Number of compute units and resident wavefronts the persistent kernels launch with. */
+int ppt_plan_launch_info(const ppt_plan* plan, int32_t* grid_waves_render, int32_t* grid_waves_backward,
+                         int32_t* n_items);
+
+const char* ppt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPT_H */

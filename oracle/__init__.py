@@ -51,8 +51,9 @@ def lib():
         L.ppto_scene_counts.argtypes = [vp, c_int, vp]
         L.ppto_run.restype = c_int
         L.ppto_run.argtypes = [vp, vp, vp, c_int, vp, c_int, c_int, ctypes.c_uint32, c_u64, c_int,
-                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int]
+                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp]
         L.ppto_philox.argtypes = [c_u64, vp, vp]
+        L.ppto_philox_n.argtypes = [c_u64, vp, vp, ctypes.c_int64]
         L.ppto_fresnel.argtypes = [c_dbl, c_dbl, c_dbl, vp, vp]
         L.ppto_polarizer.argtypes = [c_dbl, vp]
         L.ppto_retarder.argtypes = [c_dbl, vp]
@@ -92,8 +93,8 @@ class OracleScene:
         return cls(scene.to_blob(), [v.size for v in scene.slot_values])
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().ppto_scene_free(self.h)
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ppto_scene_free(self.h)
             self.h = None
 
     def counts(self, world=0):
@@ -102,12 +103,13 @@ class OracleScene:
         return out
 
     def run(self, params, views, max_depth, seed, flags=0, mode=MODE_RENDER, d_image=None, params_val=None,
-            grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0):
+            grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0, pixel_grad_slot=None):
         """Run the oracle.  ``params`` (and ``params_val``) are per-slot arrays (converted to float64).
 
         Returns a dict with ``image`` (float64, [V][A][h][w][3][4] flattened per view),
         ``grads`` (list per slot, None where not requested), ``sig`` (uint64 per path),
-        ``n_vertices`` and ``n_paths``.
+        ``n_vertices`` and ``n_paths``; with ``pixel_grad_slot`` also ``pixel_grad``: that slot's
+        gradient split by pixel (the gradient image of Sec. 5.1), one value per (view, crop pixel).
         """
         from scenegen import VIEW_DTYPE, image_numel  # input-layout helpers only
 
@@ -127,17 +129,21 @@ class OracleScene:
         sig = np.zeros(n_paths, np.uint64) if want_sig else None
         mk = None if mask is None else np.ascontiguousarray(mask, np.uint8)
         stats = np.zeros(2, np.int64)
+        n_pix = int(np.sum(views["crop_w"].astype(np.int64) * views["crop_h"]))
+        pg = np.zeros(n_pix) if pixel_grad_slot is not None else None
         err = ctypes.create_string_buffer(256)
-        ptp, ptv, pg = _ptr_array(pp), _ptr_array(pv), _ptr_array(grads)
+        ptp, ptv, pgr = _ptr_array(pp), _ptr_array(pv), _ptr_array(grads)
         rc = lib().ppto_run(self.h, ptp, ptv, len(pp), _ptr(views), len(views), int(max_depth), int(flags),
                             int(seed) & (2 ** 64 - 1), int(mode),
                             None if d_image is None else _ptr(d_image),
-                            None if image is None else _ptr(image), pg,
+                            None if image is None else _ptr(image), pgr,
                             None if sig is None else _ptr(sig), None if mk is None else _ptr(mk),
-                            _ptr(stats), int(nthreads), err, 256)
+                            _ptr(stats), int(nthreads), err, 256,
+                            -1 if pixel_grad_slot is None else int(pixel_grad_slot), None if pg is None else _ptr(pg))
         if rc != 0:
             raise ValueError("oracle run failed: " + err.value.decode())
-        return {"image": image, "grads": grads, "sig": sig, "n_vertices": int(stats[0]), "n_paths": int(stats[1])}
+        return {"image": image, "grads": grads, "sig": sig, "n_vertices": int(stats[0]), "n_paths": int(stats[1]),
+                "pixel_grad": pg}
 
 
 # ---- unit-level helpers for the pin tests
@@ -145,6 +151,13 @@ def philox(seed, ctr):
     c = np.asarray(ctr, np.uint32)
     o = np.zeros(4, np.uint32)
     lib().ppto_philox(int(seed), _ptr(c), _ptr(o))
+    return o
+
+
+def philox_n(seed, ctr):
+    c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    o = np.zeros_like(c)
+    lib().ppto_philox_n(int(seed), _ptr(c), _ptr(o), c.shape[0])
     return o
 
 

@@ -974,6 +974,8 @@ struct RunArgs {
 struct ThreadAcc {
     std::vector<std::vector<double>> g;
     int64_t n_vert = 0, n_path = 0;
+    int pix_slot = -1;      // slot whose per-pixel gradient image is requested
+    double pix_g = 0.0;     // that slot's gradient from the current pixel
 };
 
 static void collect(const PAcc<Var>& PV, const std::vector<double>& adj, ThreadAcc& acc) {
@@ -981,6 +983,7 @@ static void collect(const PAcc<Var>& PV, const std::vector<double>& adj, ThreadA
         int s = (int)(kv.first >> 40);
         uint32_t i = (uint32_t)(kv.first & ((1ll << 40) - 1));
         if (!acc.g[s].empty()) acc.g[s][i] += adj[kv.second.i];
+        if (s == acc.pix_slot) acc.pix_g += adj[kv.second.i];
     }
 }
 
@@ -1187,7 +1190,8 @@ int ppto_scene_counts(void* s, int world, int* out4) {
 int ppto_run(void* scene, const double* const* params_path, const double* const* params_val, int n_slots,
              const void* views_, int n_views, int max_depth, uint32_t flags, uint64_t seed, int mode,
              const double* d_image, double* image_out, double* const* grads_out, uint64_t* sig_out,
-             const uint8_t* path_mask, int64_t* stats, int nthreads, char* err, int errlen) {
+             const uint8_t* path_mask, int64_t* stats, int nthreads, char* err, int errlen, int pix_slot,
+             double* pix_grad) {
     Scene* sc = (Scene*)scene;
     const View* views = (const View*)views_;
     if (!sc || n_slots != (int)sc->slot_numel.size()) { set_err(err, errlen, "slot count mismatch"); return -1; }
@@ -1212,6 +1216,10 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
     g_gauge = (flags & FLAG_GAUGE) ? 1 : 0;
     RunArgs A{sc, params_path, params_val ? params_val : params_path, views, n_views, max_depth, flags, seed, mode,
               d_image, image_out, sig_out, path_mask};
+    // per-pixel index (view, crop row, crop column) for the gradient-image output
+    std::vector<int64_t> pix_off(n_views + 1, 0);
+    for (int v = 0; v < n_views; ++v) pix_off[v + 1] = pix_off[v] + (int64_t)views[v].crop_w * views[v].crop_h;
+    auto pix_index = [&](int v, int lx, int ly) { return pix_off[v] + (int64_t)ly * views[v].crop_w + lx; };
     // work items: (view, crop row)
     std::vector<std::pair<int, int>> items;
     for (int v = 0; v < n_views; ++v)
@@ -1223,6 +1231,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
 #endif
     std::vector<ThreadAcc> accs(nt);
     for (auto& a : accs) {
+        a.pix_slot = pix_grad ? pix_slot : -1;
         a.g.resize(n_slots);
         if (mode > 0)
             for (int s = 0; s < n_slots; ++s)
@@ -1255,6 +1264,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
                     for (int a = 0; a < na; ++a)
                         for (int k = 0; k < 12; ++k) dC[a * 12 + k] = d_image[pix_img + a * a_stride + k] / vw.spp;
                 double sum[4][3][4] = {};
+                acc.pix_g = 0.0;
                 for (int s = 0; s < vw.spp; ++s) {
                     int64_t pidx = path_off[v] + ((int64_t)ly * vw.crop_w + lx) * vw.spp + s;
                     if (path_mask && !path_mask[pidx]) { if (sig_out) sig_out[pidx] = 0; continue; }
@@ -1264,6 +1274,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
                         for (int c = 0; c < 3; ++c)
                             for (int k = 0; k < 4; ++k) sum[a][c][k] += C[a][c][k];
                 }
+                if (pix_grad && mode > 0) pix_grad[pix_index(v, lx, ly)] = acc.pix_g;
                 if (image_out)
                     for (int a = 0; a < na; ++a)
                         for (int c = 0; c < 3; ++c)
@@ -1325,3 +1336,7 @@ int ppto_trace(void* scene, int world, const double* o, const double* d, double 
 }
 
 }  // extern "C"
+
+extern "C" void ppto_philox_n(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) ora::philox(ctr + 4 * i, seed, out + 4 * i);
+}

@@ -1,0 +1,167 @@
+"""Scene / plan objects over the C ABI.  PyTorch provides device memory and streams only:
+every step of rendering and differentiation runs in the HIP kernels of libppt.so."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import PlanOpts, PPTError, check, lib, ptr_table
+
+FLAG_NO_NEE = 1
+
+VIEW_DTYPE = np.dtype([
+    ("world", "<i4"), ("width", "<i4"), ("height", "<i4"), ("spp", "<i4"),
+    ("crop_x0", "<i4"), ("crop_y0", "<i4"), ("crop_w", "<i4"), ("crop_h", "<i4"),
+    ("origin", "<f4", 3), ("target", "<f4", 3), ("up", "<f4", 3), ("fov_y_deg", "<f4"),
+    ("sensor", "<i4"), ("theta_slot", "<i4"), ("theta_off", "<i4"), ("view_id", "<u4"),
+])
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Scene:
+    """A parsed scene blob resident on the current device (BVH built on the host)."""
+
+    def __init__(self, blob: bytes):
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().ppt_scene_create(buf, len(blob), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int32()
+        check(lib().ppt_scene_slots(h, ctypes.byref(n), None, 0))
+        numel = (ctypes.c_int64 * max(n.value, 1))()
+        check(lib().ppt_scene_slots(h, None, numel, n.value))
+        self.slot_numel = [int(numel[i]) for i in range(n.value)]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().ppt_scene_destroy(h)
+            self._h = None
+
+
+class Plan:
+    """Views + max depth + flags, with the uploaded work queue of the persistent kernels."""
+
+    def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, samples_per_item: int = 0,
+                 grid_waves: int = 0):
+        self.scene = scene
+        self.views = np.ascontiguousarray(views, VIEW_DTYPE)
+        self.max_depth = int(max_depth)
+        self.flags = int(flags)
+        opts = PlanOpts(int(samples_per_item), int(grid_waves))
+        h = ctypes.c_void_p()
+        check(lib().ppt_plan_create(scene.handle, self.views.ctypes.data_as(ctypes.c_void_p), len(self.views),
+                                    self.max_depth, self.flags, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.image_numel = int(lib().ppt_plan_image_numel(h))
+        self.num_paths = int(lib().ppt_plan_num_paths(h))
+        self._ws = {}
+        self._mask = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().ppt_plan_destroy(h)
+            self._h = None
+
+    def launch_info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().ppt_plan_launch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"grid_waves_render": a.value, "grid_waves_backward": b.value, "n_items": c.value}
+
+    def workspace_bytes(self, op: int) -> int:
+        return int(lib().ppt_plan_workspace_bytes(self._h, op))
+
+    def workspace(self, op: int, device=None):
+        """A cached device workspace for op (0 render, 1 backward)."""
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        key = (op, str(dev))
+        ws = self._ws.get(key)
+        n = self.workspace_bytes(op)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(n + 256, dtype=torch.uint8, device=dev)
+            self._ws[key] = ws
+        return ws
+
+    @staticmethod
+    def _ws_ptr(ws):
+        p = ws.data_ptr()
+        return p + ((-p) % 256)
+
+    def set_path_mask(self, mask):
+        """Optional per-path mask (uint8 device tensor of num_paths entries) or None."""
+        if mask is not None:
+            assert mask.dtype == torch.uint8 and mask.is_cuda and mask.numel() == self.num_paths
+            mask = mask.contiguous()
+        self._mask = mask
+        check(lib().ppt_plan_set_path_mask(self._h, None if mask is None else ctypes.c_void_p(mask.data_ptr())))
+
+    def _params(self, params):
+        if len(params) != len(self.scene.slot_numel):
+            raise PPTError(f"expected {len(self.scene.slot_numel)} parameter tensors, got {len(params)}")
+        out = []
+        for p, n in zip(params, self.scene.slot_numel):
+            if p.dtype != torch.float32 or not p.is_cuda or p.numel() != n or not p.is_contiguous():
+                raise PPTError("parameters must be contiguous float32 device tensors of the slot sizes")
+            out.append(p)
+        return out
+
+    def render(self, params, seed: int, out=None, ws=None, stream=None):
+        params = self._params(params)
+        if out is None:
+            out = torch.empty(self.image_numel, dtype=torch.float32, device=params[0].device)
+        ws = self.workspace(0, params[0].device) if ws is None else ws
+        pt = ptr_table(params)
+        check(lib().ppt_render(self._h, pt, len(params), int(seed) & (2**64 - 1), ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(self._ws_ptr(ws)), ws.numel() - 256, _stream(stream)))
+        return out
+
+    def backward(self, params, seed: int, d_stokes, want=None, grads=None, ws=None, stream=None):
+        params = self._params(params)
+        d_stokes = d_stokes.contiguous()
+        if d_stokes.dtype != torch.float32 or d_stokes.numel() != self.image_numel:
+            raise PPTError("d_stokes must be float32 with image_numel entries")
+        if grads is None:
+            want = [True] * len(params) if want is None else list(want)
+            grads = [torch.empty_like(p) if w else None for p, w in zip(params, want)]
+        ws = self.workspace(1, params[0].device) if ws is None else ws
+        pt, gt = ptr_table(params), ptr_table(grads)
+        check(lib().ppt_backward(self._h, pt, len(params), int(seed) & (2**64 - 1),
+                                 ctypes.c_void_p(d_stokes.data_ptr()), gt, ctypes.c_void_p(self._ws_ptr(ws)),
+                                 ws.numel() - 256, _stream(stream)))
+        return grads
+
+    def signatures(self, params, seed: int, ws=None, stream=None):
+        params = self._params(params)
+        sig = torch.empty(self.num_paths, dtype=torch.int64, device=params[0].device)
+        ws = self.workspace(0, params[0].device) if ws is None else ws
+        check(lib().ppt_signatures(self._h, ptr_table(params), len(params), int(seed) & (2**64 - 1),
+                                   ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(self._ws_ptr(ws)),
+                                   ws.numel() - 256, _stream(stream)))
+        return sig
+
+    def stats(self, op: int, stream=None):
+        ws = self._ws[(op, str(torch.device("cuda", torch.cuda.current_device())))]
+        out = (ctypes.c_int64 * 5)()
+        check(lib().ppt_read_stats(ctypes.c_void_p(self._ws_ptr(ws)), out, _stream(stream)))
+        keys = ("vertices", "paths", "nodes", "prim_tests", "shadow_rays")
+        return {k: int(out[i]) for i, k in enumerate(keys)}
+
+
+def debug_rng(seed: int, ctr):
+    """Philox4x32-10 of the GPU library on a (n, 4) uint32 counter tensor (stored as int32)."""
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    check(lib().ppt_debug_rng(int(seed) & (2**64 - 1), ctypes.c_void_p(ctr.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()), ctr.shape[0], _stream()))
+    return out

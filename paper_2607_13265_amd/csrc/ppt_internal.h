@@ -1,0 +1,110 @@
+// ppt_internal.h -- device-side data layout shared by the host plan builder and the HIP kernels.
+// Not part of the public ABI (see include/ppt.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ppt {
+
+constexpr int MAX_SLOTS = 64;   // parameter tensors per scene
+constexpr int TILE = 8;         // an 8x8 pixel tile is one 64-lane wavefront
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;      // 4 wavefronts per workgroup; each fetches its own work items
+constexpr int MAX_DEPTH = 64;
+constexpr int STACK = 64;       // BVH traversal stack entries per lane
+
+// per-vertex cache record of the backward pass (32-bit words, lane-interleaved in memory)
+constexpr int CW_W = 0;         // 11 words: compact Mueller weight (rgb[3], a, b, c, d, Cin, Sin, Cout, Sout)
+constexpr int CW_E = 11;        // 12 words: E_b per channel, overwritten by the suffix L[b] in the fold
+constexpr int CW_HIT = 23;      // 3 words: prim | flags, barycentric u (or t), barycentric v
+constexpr int CACHE_WORDS = 26;
+
+enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
+                         MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };
+enum SensorType : int32_t { SENSOR_NONE = 0, SENSOR_POLARIZER = 1, SENSOR_ANALYZER4 = 2 };
+enum Lobe : int32_t { LOBE_NONE = 0, LOBE_REFLECT = 1, LOBE_TRANSMIT = 2, LOBE_DIFFUSE = 3, LOBE_GLOSSY = 4,
+                      LOBE_SHEET = 5, LOBE_INVALID = 6 };
+
+struct DevMaterial {
+    int32_t type;
+    int32_t alb_slot, alb_off, alb_tw, alb_th;
+    int32_t alpha_slot, alpha_off, alpha_tw, alpha_th;
+    int32_t eta_slot, eta_off;
+    int32_t kap_slot, kap_off;
+    int32_t emit_slot, emit_off;
+    float axis[3];
+    float blend;
+};
+
+struct DevLight {
+    float p0[3], eu[3], ev[3], n[3];
+    float area;
+    int32_t le_slot, le_off;
+};
+
+// BVH2 node: both children's boxes in one 64-byte record (Aila & Laine 2009 layout).
+//   q0 = (L.lo.x, L.hi.x, L.lo.y, L.hi.y), q1 = (R.lo.x, R.hi.x, R.lo.y, R.hi.y),
+//   q2 = (L.lo.z, L.hi.z, R.lo.z, R.hi.z), q3 = (ref L, ref R, -, -) as int bits.
+// A reference >= 0 is an inner node; < 0 is a leaf: ~ref = first << 3 | (count - 1).
+// Primitive records (3 x float4, BVH order): triangle (v0, orig), (e1, 0), (e2, 0);
+// sphere (c, orig), (r, 1, 0, 0), unused.
+struct DevWorld {
+    const float4* nodes;
+    const float4* prims;
+    const int32_t* prim_mat;     // by original primitive id
+    const float* tri_uv;         // 6 per original triangle
+    const DevMaterial* mats;
+    const DevLight* lights;
+    int32_t n_tris, n_prims, n_lights, root;  // root: node reference (may be a leaf reference)
+};
+
+struct DevView {
+    int32_t world, width, height, spp;
+    int32_t crop_x0, crop_y0, crop_w, crop_h;
+    float o[3], f[3], r[3], u[3];
+    float tan_h, aspect;
+    int32_t sensor, theta_slot, theta_off, n_analyzers;
+    uint32_t view_id, pad;
+    int64_t out_off;             // float offset of this view in the output image
+    int64_t path_off;            // index of its first path (view, crop row, crop column, sample)
+    int32_t tiles_x, tiles_y;
+};
+
+struct WorkItem { int32_t view, tile, s0, s1; };
+
+// Per-call device table written by the setup kernel (kernel arguments cannot be indexed
+// per lane without spilling): parameter pointers and gradient accumulator offsets.
+struct CallTable {
+    const float* p[MAX_SLOTS];
+    int64_t goff[MAX_SLOTS];     // element offset into the FP64 gradient accumulator, -1 = not requested
+    float* gout[MAX_SLOTS];      // user gradient tensors (finalize kernel)
+    int64_t numel[MAX_SLOTS];
+};
+
+struct Stats {                  // accumulated by every launch (64-bit counters)
+    unsigned long long vertices, paths, nodes, prims, shadow_rays;
+};
+
+struct KArgs {
+    const DevWorld* worlds;
+    const DevView* views;
+    const WorkItem* items;
+    int32_t n_items;
+    int32_t max_depth;
+    uint32_t flags;
+    uint32_t pad0;
+    uint64_t seed;
+    CallTable* table;            // in the workspace
+    int* queue;                  // work-queue head (workspace)
+    Stats* stats;                // workspace
+    float* out;                  // render: Stokes image
+    const float* dout;           // backward: dL/dStokes
+    double* gacc;                // backward: FP64 gradient accumulator
+    float* cache;                // backward: per-lane vertex cache
+    uint64_t* sig;               // optional per-path signature output
+    const uint8_t* mask;         // optional per-path mask
+};
+
+constexpr uint32_t FLAG_NO_NEE = 1u;
+
+}  // namespace ppt
