@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark: Mpath-vertices/s of forward + PRB adjoint (render + backward) on one MI355X.
+
+Workload (the batched configuration the metric names): the seeded 20.5k-triangle scene of
+16 icospheres + ground + one area light, 4 camera poses on a ring x 32 polarizer angles
+theta_k = k pi / 32 = 128 views, 128 x 128 pixels, 32 spp, max depth 6, random dL/dStokes
+~ N(0, 1).  One step = one batched persistent render launch + one batched persistent
+backward launch over all 128 views, replayed from a captured HIP graph.  The plain
+per-view form (128 render + 128 backward launches) is timed beside it on identical paths.
+
+A path vertex is one surface interaction of a camera path, counted in-kernel; the value is
+vertices / (render + backward time).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpath-vertices/s fwd+PRB adjoint; batched vs per-view launch, grad rel.err≤1e-3"
+
+# Algorithmic FP32 operations (an FMA counts 2) per unit of work, read off the kernel source;
+# see the design notes for the itemisation.
+FLOP_NODE = 47      # one two-box BVH node test
+FLOP_PRIM = 52      # one Moller-Trumbore triangle test
+FLOP_VERT_FWD = 450     # shading of one vertex in the render kernel
+FLOP_VERT_BWD = 1400    # primal shading + cache + fold + replay with vector-Jacobian products
+PEAK_FP32_TFLOPS = 157.3  # MI355X fp32 vector peak (256 CU x 2.4 GHz x 64 lanes x FMA x packed)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--per-view-steps", type=int, default=2)
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-paths", type=int, default=40000, help="paths in the oracle sample")
+    ap.add_argument("--res", type=int, default=128)
+    ap.add_argument("--spp", type=int, default=32)
+    ap.add_argument("--chunk-paths", type=int, default=0)
+    ap.add_argument("--json-out", default="")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2607_13265_amd as ppt
+    import scenegen as sg
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = sg.config3(res=args.res, spp=args.spp)
+    log(f"[bench] workload {wl.name}: {len(wl.views)} views {args.res}^2 x {args.spp} spp, depth {wl.max_depth}")
+    scene = ppt.Scene(wl.scene.to_blob())
+    plan = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, chunk_paths=args.chunk_paths)
+    info = plan.launch_info()
+    params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
+    rng = np.random.default_rng(wl.meta["delta_seed"])
+    d = torch.from_numpy(rng.standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
+    want = [n in wl.grad_slots for n in wl.scene.slot_names]
+    out = torch.empty(plan.image_numel, dtype=torch.float32, device=dev)
+    grads = [torch.empty_like(p) if w else None for p, w in zip(params, want)]
+    ws_r, ws_b = plan.workspace(0), plan.workspace(1)
+
+    def step():
+        plan.render(params, wl.seed, out=out, ws=ws_r)
+        plan.backward(params, wl.seed, d, grads=grads, ws=ws_b)
+
+    # eager warm-up, counters, and per-kernel timing with events on the launch stream
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    st_r, st_b = plan.stats(0), plan.stats(1)
+    verts = st_r["vertices"]
+    plan.set_stats(False)  # counters are not needed in the timed region
+    log(f"[bench] vertices/step {verts}, paths {st_r['paths']}, grid {info}")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_r, t_b = [], []
+    for _ in range(max(3, args.steps // 2)):
+        ev[0].record()
+        plan.render(params, wl.seed, out=out, ws=ws_r)
+        ev[1].record()
+        plan.backward(params, wl.seed, d, grads=grads, ws=ws_b)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_r.append(ev[0].elapsed_time(ev[1]))
+        t_b.append(ev[1].elapsed_time(ev[2]))
+    ms_r, ms_b = float(np.median(t_r)), float(np.median(t_b))
+    log(f"[bench] eager: render {ms_r:.2f} ms, backward {ms_b:.2f} ms")
+
+    # batched step captured in a HIP graph
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = verts / (ms_step * 1e-3) / 1e6
+    log(f"[bench] graph: {ms_step:.2f} ms/step, {value:.1f} Mpath-vertices/s (wall {wall:.2f} s)")
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpath-vertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), "
+                               f"{args.res}x{args.res}, {args.spp} spp, depth {wl.max_depth}, 20.5k-triangle "
+                               "icosphere scene, render + PRB backward, HIP-graph replay",
+                   "views": len(wl.views), "resolution": args.res, "spp": args.spp, "max_depth": wl.max_depth,
+                   "vertices_per_step": verts, "paths_per_step": st_r["paths"],
+                   "chunk_paths": info["chunk_paths"], "chunks": info["n_chunks"]},
+    }
+
+    # per-view launches on the same paths (view_id keeps the random streams identical)
+    if not args.no_per_view:
+        plans = []
+        for v in range(len(wl.views)):
+            pv = ppt.Plan(scene, wl.views[v:v + 1], wl.max_depth, wl.flags, chunk_paths=args.chunk_paths)
+            plans.append(pv)
+        outs = [torch.empty(p.image_numel, dtype=torch.float32, device=dev) for p in plans]
+        offs = sg.view_offsets(wl.views)
+        ds = [d[int(offs[v]):int(offs[v]) + plans[v].image_numel] for v in range(len(plans))]
+
+        def step_pv():
+            for v, pv in enumerate(plans):
+                pv.render(params, wl.seed, out=outs[v], ws=ws_r)
+                pv.backward(params, wl.seed, ds[v], grads=grads, ws=ws_b)
+
+        step_pv()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.per_view_steps):
+            step_pv()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_pv = e0.elapsed_time(e1) / args.per_view_steps
+        plan.render(params, wl.seed, out=out, ws=ws_r)
+        torch.cuda.synchronize()
+        img_pv = torch.cat(outs)
+        img_rel = float((img_pv - out).norm() / out.norm())
+        result["per_view"] = {"value": round(verts / (ms_pv * 1e-3) / 1e6, 2), "ms_per_step": round(ms_pv, 3),
+                              "launches_per_step": 2 * len(plans), "image_rel_diff_vs_batched": img_rel}
+        result["speedup_batched_vs_per_view"] = round(ms_pv / ms_step, 3)
+        log(f"[bench] per-view: {ms_pv:.2f} ms/step, image rel diff {img_rel:.2e}")
+
+    # roofline of the dominant kernel (backward), algorithmic FLOPs from in-kernel counters
+    flops_b = FLOP_NODE * st_b["nodes"] + FLOP_PRIM * st_b["prim_tests"] + FLOP_VERT_BWD * st_b["vertices"]
+    flops_r = FLOP_NODE * st_r["nodes"] + FLOP_PRIM * st_r["prim_tests"] + FLOP_VERT_FWD * st_r["vertices"]
+    ach_b = flops_b / (ms_b * 1e-3) / 1e12
+    result["roofline"] = {"kernel": "k_backward", "bound": "alu", "achieved": round(ach_b, 3),
+                          "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(ach_b / PEAK_FP32_TFLOPS, 4),
+                          "traffic": None, "kernel_ms": round(ms_b, 3), "algorithmic_tflop_per_launch":
+                          round(flops_b / 1e12, 4),
+                          "render": {"achieved": round(flops_r / (ms_r * 1e-3) / 1e12, 3), "kernel_ms": round(ms_r, 3)},
+                          "counters_backward": st_b}
+
+    # CPU baseline: the FP64 oracle (render + cached-suffix replay) on a bounded sample
+    if not args.no_cpu:
+        import oracle
+        nthreads = os.cpu_count() or 1
+        sample_views = sg.crop_views(wl.views[:4], 0, 0, args.res, args.res)
+        npix = max(1, args.cpu_paths // (4 * args.spp))
+        side = max(1, int(np.sqrt(npix)))
+        sample_views = sg.crop_views(wl.views[:4], args.res // 2 - side // 2, args.res // 2 - side // 2, side, side)
+        osc = oracle.OracleScene.from_scene(wl.scene)
+        p64 = [p.astype(np.float64) for p in wl.scene.params()]
+        dd = np.random.default_rng(1).standard_normal(sg.image_numel(sample_views))
+        t0 = time.perf_counter()
+        r = osc.run(p64, sample_views, wl.max_depth, wl.seed, nthreads=nthreads)
+        r2 = osc.run(p64, sample_views, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=dd,
+                     want_image=False, nthreads=nthreads)
+        tc = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(r["n_vertices"] / tc / 1e6, 4), "unit": "Mpath-vertices/s",
+                                  "cores": nthreads, "kind": "oracle",
+                                  "sample": f"4 views x {side}x{side} central pixels x {args.spp} spp, depth "
+                                            f"{wl.max_depth} ({r['n_paths']} paths, {r['n_vertices']} vertices), "
+                                            f"FP64 render + cached-suffix replay, {tc:.1f} s"}
+        log(f"[bench] cpu oracle: {result['cpu_baseline']}")
+
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -62,15 +62,33 @@ typedef struct ppt_view {
 } ppt_view;
 
 typedef struct ppt_plan_opts {
-    int32_t samples_per_item; /* samples of one pixel tile processed by one work item; 0 = auto */
-    int32_t grid_waves;       /* resident wavefronts of the persistent launch; 0 = from occupancy */
+    int64_t chunk_paths;      /* paths in flight per chunk (path-state capacity); 0 = min(all, 16M) */
+    int64_t reserved;         /* must be 0 */
 } ppt_plan_opts;
 
 typedef struct ppt_scene ppt_scene;
 typedef struct ppt_plan ppt_plan;
 
-/* Parse a binary scene blob (format: DESIGN.md, "Scene blob"), build one SAH bounding
- * volume hierarchy per world on the host and upload everything to the current device.
+/* Scene blob (little-endian, 32-bit words unless stated):
+ *   header     magic 0x31545050 ('PPT1'), version 1, n_slots (<= 64), n_worlds
+ *   slots      n_slots element counts (the float32 parameter tensors of every call)
+ *   per world  n_tris, n_spheres, n_materials, n_lights, then
+ *              triangles: n_tris x 9 floats (v0, v1, v2), n_tris x 6 floats (uv0, uv1, uv2),
+ *                         n_tris material indices;
+ *              spheres:   n_spheres x 4 floats (centre, signed radius: < 0 = inward normal),
+ *                         n_spheres material indices;
+ *              materials: 88-byte records {type; albedo slot, offset, texture width, height;
+ *                         roughness slot, offset, width, height; eta slot, offset; kappa slot,
+ *                         offset; emission slot, offset; sheet axis[3]; blend; 3 reserved}
+ *                         (slot -1 = absent, width 0 = constant, texture layout [h][w][ch]);
+ *              lights:    48-byte records {p0[3], eu[3], ev[3]; radiance slot, offset; pad},
+ *                         one-sided rectangles emitting along eu x ev (their geometry is also
+ *                         present as two triangles with an emitter material).
+ *   Material types: 0 Lambertian, 1 smooth dielectric, 2 GGX dielectric (reflection),
+ *   3 GGX conductor (complex IOR eta + i kappa), 4 linear polarizer sheet, 5 emitter,
+ *   6 Lambertian/GGX-dielectric blend (lobe probability = blend).
+ * ppt_scene_create parses and validates a blob, builds one SAH bounding volume hierarchy per
+ * world on the host and uploads everything to the current device.
  * blob/nbytes: host memory.  *out receives a library-owned handle.
  * Errors: PPT_EINVAL for a malformed blob (truncated, bad magic, indices out of range),
  * PPT_ENOMEM / PPT_EDEVICE for device failures. */
@@ -81,8 +99,9 @@ void ppt_scene_destroy(ppt_scene* scene);
 int ppt_scene_slots(const ppt_scene* scene, int32_t* n_slots, int64_t* numel_out, int32_t cap);
 
 /* Fix the views, the maximum path depth (1..64 surface interactions) and the flags of a
- * family of calls: uploads the view table and the work queue (tiles of 8x8 pixels times
- * sample chunks, one item per wavefront).  views: host array of n_views records. */
+ * family of calls.  All paths of all views form one index space that is processed in chunks
+ * of chunk_paths paths (one launch sequence covers the whole batch of views, also views of
+ * different worlds, resolutions and sample counts).  views: host array of n_views records. */
 int ppt_plan_create(const ppt_scene* scene, const ppt_view* views, int32_t n_views, int32_t max_depth,
                     uint32_t flags, const ppt_plan_opts* opts, ppt_plan** out);
 void ppt_plan_destroy(ppt_plan* plan);
@@ -93,9 +112,10 @@ void ppt_plan_destroy(ppt_plan* plan);
 int64_t ppt_plan_image_numel(const ppt_plan* plan);
 int64_t ppt_plan_num_paths(const ppt_plan* plan);
 
-/* Device workspace bytes needed by ppt_render (op = 0) or ppt_backward (op = 1).  The
- * backward workspace holds the per-vertex cache of every resident lane (constant in the
- * number of paths) and the FP64 gradient accumulators. */
+/* Device workspace bytes needed by ppt_render (op = 0) or ppt_backward (op = 1): the
+ * structure-of-arrays state of one chunk of paths (for the backward pass including the
+ * per-vertex cache of max_depth records per path of the chunk), independent of the total
+ * number of paths, and the FP64 gradient accumulators. */
 size_t ppt_plan_workspace_bytes(const ppt_plan* plan, int32_t op);
 
 /* Optional per-path mask (device, one byte per path, NULL = all paths).  A path whose byte is
@@ -125,18 +145,19 @@ int ppt_backward(const ppt_plan* plan, const float* const* params, int32_t n_par
 int ppt_signatures(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
                    uint64_t* sig_out, void* ws, size_t ws_bytes, void* stream);
 
-/* Counters accumulated in a workspace by every render/backward call since its last setup:
- * out[0] path vertices, [1] paths, [2] BVH nodes visited, [3] primitive tests, [4] shadow rays.
+/* Work counters of the last render/backward call made with a workspace: out[0] path vertices,
+ * [1] paths, [2] BVH nodes visited, [3] primitive tests, [4] shadow rays.  Collected while the
+ * plan's counters are enabled (the default; ppt_plan_set_stats), else left at zero.
  * Synchronizes the stream.  ws: device workspace; out: host, 5 entries. */
+int ppt_plan_set_stats(ppt_plan* plan, int32_t enabled);
 int ppt_read_stats(const void* ws, int64_t* out, void* stream);
 
 /* Philox4x32-10 (Salmon et al. 2011) on n counters: ctr and out are device arrays of n x 4
  * uint32; key = (seed low 32 bits, seed high 32 bits). */
 int ppt_debug_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, void* stream);
 
-/* Number of compute units and resident wavefronts the persistent kernels launch with. */
-int ppt_plan_launch_info(const ppt_plan* plan, int32_t* grid_waves_render, int32_t* grid_waves_backward,
-                         int32_t* n_items);
+/* Chunking of the plan: paths per chunk, number of chunks, traversal stack entries per thread. */
+int ppt_plan_launch_info(const ppt_plan* plan, int64_t* chunk_paths, int32_t* n_chunks, int32_t* stack_entries);
 
 const char* ppt_last_error(void);
 

@@ -782,7 +782,7 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
             default:
                 x.lobe = LOBE_INVALID;
         }
-        sig.add((uint32_t)x.prim); sig.add((uint32_t)x.nee); sig.add((uint32_t)x.lobe);
+        sig.add((uint32_t)x.prim); sig.add((uint32_t)x.lobe); sig.add((uint32_t)x.nee);
         g.v.push_back(x);
         if (x.lobe == LOBE_INVALID) break;
         prev_delta = is_delta(m.type);

@@ -25,6 +25,7 @@ SIGNATURES = {
     "ppt_plan_num_paths": (_i64, [_vp]),
     "ppt_plan_workspace_bytes": (_sz, [_vp, _i32]),
     "ppt_plan_set_path_mask": (_i32, [_vp, _vp]),
+    "ppt_plan_set_stats": (_i32, [_vp, _i32]),
     "ppt_render": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),
     "ppt_backward": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _vp, _sz, _vp]),
     "ppt_signatures": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),
@@ -40,7 +41,7 @@ class PPTError(RuntimeError):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("samples_per_item", ctypes.c_int32), ("grid_waves", ctypes.c_int32)]
+    _fields_ = [("chunk_paths", ctypes.c_int64), ("reserved", ctypes.c_int64)]
 
 
 _lib = None

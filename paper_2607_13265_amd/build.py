@@ -9,6 +9,8 @@ SOURCES = [os.path.join(CSRC, "ppt_kernels.hip"), os.path.join(CSRC, "ppt_host.c
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # hardware float atomics (device memory here is coarse-grained)
+    "-munsafe-fp-atomics",
     # packed FP32 instructions are disabled for every HIP compile in this project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -50,15 +50,14 @@ class Scene:
 
 
 class Plan:
-    """Views + max depth + flags, with the uploaded work queue of the persistent kernels."""
+    """Views + max depth + flags; paths of all views are processed in chunks of chunk_paths."""
 
-    def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, samples_per_item: int = 0,
-                 grid_waves: int = 0):
+    def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, chunk_paths: int = 0):
         self.scene = scene
         self.views = np.ascontiguousarray(views, VIEW_DTYPE)
         self.max_depth = int(max_depth)
         self.flags = int(flags)
-        opts = PlanOpts(int(samples_per_item), int(grid_waves))
+        opts = PlanOpts(int(chunk_paths), 0)
         h = ctypes.c_void_p()
         check(lib().ppt_plan_create(scene.handle, self.views.ctypes.data_as(ctypes.c_void_p), len(self.views),
                                     self.max_depth, self.flags, ctypes.byref(opts), ctypes.byref(h)))
@@ -75,9 +74,9 @@ class Plan:
             self._h = None
 
     def launch_info(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        a, b, c = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().ppt_plan_launch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"grid_waves_render": a.value, "grid_waves_backward": b.value, "n_items": c.value}
+        return {"chunk_paths": a.value, "n_chunks": b.value, "stack_entries": c.value}
 
     def workspace_bytes(self, op: int) -> int:
         return int(lib().ppt_plan_workspace_bytes(self._h, op))
@@ -97,6 +96,10 @@ class Plan:
     def _ws_ptr(ws):
         p = ws.data_ptr()
         return p + ((-p) % 256)
+
+    def set_stats(self, enabled: bool):
+        """Enable/disable the in-kernel work counters (on by default)."""
+        check(lib().ppt_plan_set_stats(self._h, 1 if enabled else 0))
 
     def set_path_mask(self, mask):
         """Optional per-path mask (uint8 device tensor of num_paths entries) or None."""

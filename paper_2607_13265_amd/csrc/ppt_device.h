@@ -1,0 +1,869 @@
+// ppt_device.h -- device-side library of the polarized path tracer (gfx950): vector and
+// complex arithmetic, Philox RNG, Stokes frames, Fresnel amplitudes and their adjoints,
+// GGX microfacet terms, parameter/texture access, BVH traversal, path-vertex sampling and the
+// per-vertex Mueller weights with their vector-Jacobian products.
+#pragma once
+#include "ppt_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ppt {
+
+#define DEV __device__ __forceinline__
+
+constexpr float PI_F = 3.14159265358979323846f;
+
+// ============================================================================ vectors
+struct v3 { float x, y, z; };
+DEV v3 mk(float x, float y, float z) { return {x, y, z}; }
+DEV v3 operator+(v3 a, v3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+DEV v3 operator-(v3 a, v3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+DEV v3 operator-(v3 a) { return {-a.x, -a.y, -a.z}; }
+DEV v3 operator*(v3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+DEV float dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+DEV v3 cross(v3 a, v3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+DEV v3 normalize(v3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+DEV v3 ld3(const float* p) { return {p[0], p[1], p[2]}; }
+
+// ============================================================================ complex
+struct cf { float re, im; };
+DEV cf cadd(cf a, cf b) { return {a.re + b.re, a.im + b.im}; }
+DEV cf csub(cf a, cf b) { return {a.re - b.re, a.im - b.im}; }
+DEV cf cmul(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+DEV cf cscale(cf a, float s) { return {a.re * s, a.im * s}; }
+DEV cf cconj(cf a) { return {a.re, -a.im}; }
+DEV float cabs2(cf a) { return a.re * a.re + a.im * a.im; }
+DEV cf cdiv(cf a, cf b) {
+    float d = 1.0f / cabs2(b);
+    return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
+}
+// principal square root; a zero imaginary part counts as +0
+DEV cf csqrt(cf z) {
+    float r = hypotf(z.re, z.im);
+    if (r == 0.0f) return {0.0f, 0.0f};
+    if (z.re >= 0.0f) {
+        float t = sqrtf(0.5f * (r + z.re));
+        return {t, z.im / (2.0f * t)};
+    }
+    float t = sqrtf(0.5f * (r - z.re));
+    return {fabsf(z.im) / (2.0f * t), z.im < 0.0f ? -t : t};
+}
+
+// ============================================================================ RNG
+// Philox4x32-10 (Salmon et al., SC'11).  Counter (pixel, sample, view << 8 | bounce, call).
+DEV void philox(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+}
+DEV float u01(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }  // exact: 24 bits / 2^24
+DEV void uniforms(uint64_t seed, uint32_t pix, uint32_t smp, uint32_t view, uint32_t bounce, uint32_t call,
+                  float u[4]) {
+    uint32_t c0 = pix, c1 = smp, c2 = (view << 8) | (bounce & 0xffu), c3 = call;
+    philox(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    u[0] = u01(c0); u[1] = u01(c1); u[2] = u01(c2); u[3] = u01(c3);
+}
+
+// ============================================================================ wave helpers
+DEV int lane_id() { return threadIdx.x & (WAVE - 1); }
+DEV float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+DEV uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// ============================================================================ frames
+// Orthonormal basis (x, y, n) of Duff et al. 2017.
+DEV void onb(v3 n, v3& x, v3& y) {
+    float sg = copysignf(1.0f, n.z);
+    float a = -1.0f / (sg + n.z);
+    float b = n.x * n.y * a;
+    x = mk(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
+    y = mk(b, sg + n.y * n.y * a, -n.y);
+}
+// canonical transverse basis vector of the Stokes frame of light travelling along k
+DEV v3 canon_x(v3 k) {
+    v3 x, y;
+    onb(k, x, y);
+    return x;
+}
+// Stokes rotator between transverse bases x_from -> x_to about k: (cos 2phi, sin 2phi)
+DEV void rot_cs(v3 k, v3 x_from, v3 x_to, float& C, float& S) {
+    float c = dot(x_from, x_to), s = dot(cross(k, x_from), x_to);
+    C = c * c - s * s;
+    S = 2.0f * c * s;
+}
+// s-axis of a specular event for incident propagation k_in and normal n_inc on the incident side
+DEV v3 s_axis(v3 k_in, v3 n_inc) {
+    v3 s = cross(k_in, n_inc);
+    float l2 = dot(s, s);
+    if (l2 < 1e-16f) return canon_x(k_in);
+    return s * (1.0f / sqrtf(l2));
+}
+
+// ============================================================================ Fresnel
+struct Fres { cf rs, rp, ts, tp, ct; float kappa, st2r; };
+// Born & Wolf amplitudes for incidence cosine ci and relative index m = n2 / n1.
+DEV void fresnel_amp(float ci, cf m, Fres& F, bool trans) {
+    cf m2 = cmul(m, m);
+    cf st2 = cdiv(cf{1.0f - ci * ci, 0.0f}, m2);
+    F.ct = csqrt(csub(cf{1.0f, 0.0f}, st2));
+    cf mct = cmul(m, F.ct), mci = cscale(m, ci);
+    cf c{ci, 0.0f};
+    F.rs = cdiv(csub(c, mct), cadd(c, mct));
+    F.rp = cdiv(csub(mci, F.ct), cadd(mci, F.ct));
+    if (trans) {
+        F.ts = cdiv(cf{2.0f * ci, 0.0f}, cadd(c, mct));
+        F.tp = cdiv(cf{2.0f * ci, 0.0f}, cadd(mci, F.ct));
+        F.kappa = mct.re / ci;
+    }
+}
+// Mueller entries (a, b, c, d) of a Jones matrix diag(as, ap)
+DEV void jones_abcd(cf as, cf ap, float& a, float& b, float& c, float& d) {
+    float A = cabs2(as), B = cabs2(ap);
+    cf z = cmul(as, cconj(ap));
+    a = 0.5f * (A + B); b = 0.5f * (A - B); c = z.re; d = z.im;
+}
+DEV void fresnel_R(float ci, cf m, float& a, float& b, float& c, float& d) {
+    Fres F;
+    fresnel_amp(ci, m, F, false);
+    jones_abcd(F.rs, F.rp, a, b, c, d);
+}
+DEV void fresnel_T(float ci, cf m, float& a, float& b, float& c, float& d) {
+    Fres F;
+    fresnel_amp(ci, m, F, true);
+    jones_abcd(F.ts, F.tp, a, b, c, d);
+    a *= F.kappa; b *= F.kappa; c *= F.kappa; d *= F.kappa;
+}
+// Adjoint of jones_abcd: gradients (conjugate convention d/dRe + i d/dIm) of the amplitudes.
+DEV void jones_abcd_vjp(cf as, cf ap, float ga, float gb, float gc, float gd, cf& g_as, cf& g_ap) {
+    float gA = 0.5f * (ga + gb), gB = 0.5f * (ga - gb);
+    cf gz{gc, gd}, gzc{gc, -gd};
+    g_as = cadd(cscale(as, 2.0f * gA), cmul(gz, ap));
+    g_ap = cadd(cscale(ap, 2.0f * gB), cmul(gzc, as));
+}
+// d(loss)/dm (conjugate convention) of the reflection entries; the amplitudes are holomorphic
+// in m with d(m ct)/dm = 1/ct and d ct/dm = st2 / (m ct).
+DEV cf fresnel_R_vjp(float ci, cf m, float ga, float gb, float gc, float gd) {
+    Fres F;
+    fresnel_amp(ci, m, F, false);
+    cf g_rs, g_rp;
+    jones_abcd_vjp(F.rs, F.rp, ga, gb, gc, gd, g_rs, g_rp);
+    cf m2 = cmul(m, m);
+    cf st2 = cdiv(cf{1.0f - ci * ci, 0.0f}, m2);
+    cf u = cmul(m, F.ct), v = cscale(m, ci);
+    cf cu = cadd(cf{ci, 0.0f}, u), cv = cadd(v, F.ct);
+    cf drs = cdiv(cf{-2.0f * ci, 0.0f}, cmul(cmul(cu, cu), F.ct));
+    cf drp = cdiv(cscale(csub(cmul(F.ct, F.ct), st2), 2.0f * ci), cmul(F.ct, cmul(cv, cv)));
+    return cadd(cmul(g_rs, cconj(drs)), cmul(g_rp, cconj(drp)));
+}
+DEV cf fresnel_T_vjp(float ci, cf m, float ga, float gb, float gc, float gd) {
+    Fres F;
+    fresnel_amp(ci, m, F, true);
+    float a, b, c, d;
+    jones_abcd(F.ts, F.tp, a, b, c, d);
+    float gk = ga * a + gb * b + gc * c + gd * d;
+    cf g_ts, g_tp;
+    jones_abcd_vjp(F.ts, F.tp, F.kappa * ga, F.kappa * gb, F.kappa * gc, F.kappa * gd, g_ts, g_tp);
+    cf m2 = cmul(m, m);
+    cf st2 = cdiv(cf{1.0f - ci * ci, 0.0f}, m2);
+    cf u = cmul(m, F.ct), v = cscale(m, ci);
+    cf cu = cadd(cf{ci, 0.0f}, u), cv = cadd(v, F.ct);
+    cf dts = cdiv(cf{-2.0f * ci, 0.0f}, cmul(cmul(cu, cu), F.ct));
+    cf dct = cdiv(st2, cmul(m, F.ct));
+    cf dtp = cdiv(cscale(cadd(cf{ci, 0.0f}, dct), -2.0f * ci), cmul(cv, cv));
+    cf du = cdiv(cf{1.0f, 0.0f}, F.ct);
+    cf g = cadd(cmul(g_ts, cconj(dts)), cmul(g_tp, cconj(dtp)));
+    return cadd(g, cscale(cconj(du), gk / ci));
+}
+
+// ============================================================================ GGX
+DEV float ggx_D(float ch, float a) {
+    if (ch <= 0.0f) return 0.0f;
+    float a2 = a * a, d = (a2 - 1.0f) * ch * ch + 1.0f;
+    return a2 / (PI_F * d * d);
+}
+DEV float ggx_dlnD(float ch, float a) {
+    float a2 = a * a, d = (a2 - 1.0f) * ch * ch + 1.0f;
+    return 2.0f / a - 4.0f * a * ch * ch / d;
+}
+DEV float smith_G1(float cw, float a) {
+    if (cw <= 0.0f) return 0.0f;
+    float t2 = (1.0f - cw * cw) / (cw * cw);
+    float s = sqrtf(1.0f + a * a * t2);
+    return 1.0f / (1.0f + 0.5f * (s - 1.0f));
+}
+DEV float smith_dlnG1(float cw, float a) {
+    float t2 = (1.0f - cw * cw) / (cw * cw);
+    float s = sqrtf(1.0f + a * a * t2);
+    float lam = 0.5f * (s - 1.0f);
+    return -(a * t2 / (2.0f * s)) / (1.0f + lam);
+}
+
+// ============================================================================ scene access
+// Parameter reads and gradient writes of one call.  Gradients go to a workgroup-local LDS
+// accumulator when the slot has one (FP64 for small slots, FP32 for textures), else to the
+// global FP64 accumulator.
+struct Call {
+    const CallTable* tab;
+    double* gacc;
+    double* lds_d = nullptr;
+    float* lds_f = nullptr;
+    DEV float p(int slot, int idx) const { return tab->p[slot][idx]; }
+    DEV void g(int slot, int idx, float v) const {
+        if (v == 0.0f) return;
+        if (lds_d) {
+            int o = tab->lds_d[slot];
+            if (o >= 0) { atomicAdd(lds_d + o + idx, (double)v); return; }
+            o = tab->lds_f[slot];
+            if (o >= 0) { atomicAdd(lds_f + o + idx, v); return; }
+        }
+        int64_t o = tab->goff[slot];
+        if (o >= 0) unsafeAtomicAdd(gacc + o + idx, (double)v);
+    }
+};
+
+// Per-vertex gradient of the parameters a vertex reads, combined over its next-event and
+// continuation terms before it is scattered (one bilinear scatter per texture).
+struct GradVtx {
+    float rho[3], alpha, eta, kap, le[3], emit[3];
+    DEV void zero() {
+        rho[0] = rho[1] = rho[2] = 0.0f; alpha = eta = kap = 0.0f;
+        le[0] = le[1] = le[2] = 0.0f; emit[0] = emit[1] = emit[2] = 0.0f;
+    }
+};
+
+// bilinear, clamp to edge, texel centres at (i + 1/2)/N, layout [th][tw][ch]
+struct Bilin { int i[4]; float w[4]; };
+DEV void bilin(float u, float v, int tw, int th, int ch, Bilin& B) {
+    float x = u * (float)tw - 0.5f, y = v * (float)th - 0.5f;
+    float x0f = floorf(x), y0f = floorf(y);
+    float fx = x - x0f, fy = y - y0f;
+    int x0 = (int)x0f, y0 = (int)y0f;
+    int xa = min(max(x0, 0), tw - 1), xb = min(max(x0 + 1, 0), tw - 1);
+    int ya = min(max(y0, 0), th - 1), yb = min(max(y0 + 1, 0), th - 1);
+    B.i[0] = (ya * tw + xa) * ch; B.w[0] = (1.0f - fx) * (1.0f - fy);
+    B.i[1] = (ya * tw + xb) * ch; B.w[1] = fx * (1.0f - fy);
+    B.i[2] = (yb * tw + xa) * ch; B.w[2] = (1.0f - fx) * fy;
+    B.i[3] = (yb * tw + xb) * ch; B.w[3] = fx * fy;
+}
+DEV float albedo(const Call& K, const DevMaterial& m, int c, float u, float v) {
+    if (m.alb_tw == 0) return K.p(m.alb_slot, m.alb_off + c);
+    Bilin B;
+    bilin(u, v, m.alb_tw, m.alb_th, 3, B);
+    float r = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r += K.p(m.alb_slot, m.alb_off + B.i[k] + c) * B.w[k];
+    return r;
+}
+DEV void albedo_scatter(const Call& K, const DevMaterial& m, float u, float v, const float* g) {
+    if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) return;
+    if (m.alb_tw == 0) {
+        for (int c = 0; c < 3; ++c) K.g(m.alb_slot, m.alb_off + c, g[c]);
+        return;
+    }
+    Bilin B;
+    bilin(u, v, m.alb_tw, m.alb_th, 3, B);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) K.g(m.alb_slot, m.alb_off + B.i[k] + c, g[c] * B.w[k]);
+}
+// roughness, clamped to [1e-3, 1]; *inside tells whether the clamp is inactive
+DEV float rough(const Call& K, const DevMaterial& m, float u, float v, bool* inside) {
+    float a;
+    if (m.alpha_tw == 0) {
+        a = K.p(m.alpha_slot, m.alpha_off);
+    } else {
+        Bilin B;
+        bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
+        a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a += K.p(m.alpha_slot, m.alpha_off + B.i[k]) * B.w[k];
+    }
+    bool in = a >= 1e-3f && a <= 1.0f;
+    if (inside) *inside = in;
+    return fminf(fmaxf(a, 1e-3f), 1.0f);
+}
+DEV void rough_scatter(const Call& K, const DevMaterial& m, float u, float v, float g) {
+    if (g == 0.0f) return;
+    if (m.alpha_tw == 0) { K.g(m.alpha_slot, m.alpha_off, g); return; }
+    Bilin B;
+    bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) K.g(m.alpha_slot, m.alpha_off + B.i[k], g * B.w[k]);
+}
+DEV cf ior(const Call& K, const DevMaterial& m) {
+    return cf{K.p(m.eta_slot, m.eta_off), m.kap_slot >= 0 ? K.p(m.kap_slot, m.kap_off) : 0.0f};
+}
+
+// ============================================================================ traversal
+struct Hit { int prim; float t, u, v; };
+
+DEV v3 safe_inv(v3 d) {
+    const float e = 1e-20f;
+    return mk(1.0f / (fabsf(d.x) > e ? d.x : copysignf(e, d.x)), 1.0f / (fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
+              1.0f / (fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
+}
+
+// Closest hit (ANY = false) or any hit (ANY = true) with 0 < t < tmax.
+// stack: this thread's slot in a workgroup-shared array, entry k at stack[k * BLOCK]
+template <bool ANY>
+DEV bool trace(const DevWorld& W, v3 o, v3 d, float tmax, Hit& h, uint32_t& n_nodes, uint32_t& n_prims,
+                int* stack) {
+    h.prim = -1;
+    if (W.n_prims == 0) return false;
+    v3 id = safe_inv(d);
+    v3 ood = mk(o.x * id.x, o.y * id.y, o.z * id.z);
+    int sp = 0;
+    int ref = W.root;
+    float tb = tmax;
+    while (true) {
+        if (ref >= 0) {
+            ++n_nodes;
+            const float4* nd = W.nodes + 4 * ref;
+            float4 q0 = nd[0], q1 = nd[1], q2 = nd[2], q3 = nd[3];
+            float a0 = fmaf(q0.x, id.x, -ood.x), a1 = fmaf(q0.y, id.x, -ood.x);
+            float b0 = fmaf(q0.z, id.y, -ood.y), b1 = fmaf(q0.w, id.y, -ood.y);
+            float c0 = fmaf(q2.x, id.z, -ood.z), c1 = fmaf(q2.y, id.z, -ood.z);
+            float tnL = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
+            float txL = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tb));
+            float e0 = fmaf(q1.x, id.x, -ood.x), e1 = fmaf(q1.y, id.x, -ood.x);
+            float f0 = fmaf(q1.z, id.y, -ood.y), f1 = fmaf(q1.w, id.y, -ood.y);
+            float g0 = fmaf(q2.z, id.z, -ood.z), g1 = fmaf(q2.w, id.z, -ood.z);
+            float tnR = fmaxf(fmaxf(fminf(e0, e1), fminf(f0, f1)), fmaxf(fminf(g0, g1), 0.0f));
+            float txR = fminf(fminf(fmaxf(e0, e1), fmaxf(f0, f1)), fminf(fmaxf(g0, g1), tb));
+            bool hL = tnL <= txL, hR = tnR <= txR;
+            int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
+            if (hL && hR) {
+                if (tnR < tnL) { int t = rL; rL = rR; rR = t; }
+                stack[(sp++) * BLOCK] = rR;
+                ref = rL;
+            } else if (hL) {
+                ref = rL;
+            } else if (hR) {
+                ref = rR;
+            } else {
+                if (sp == 0) break;
+                ref = stack[(--sp) * BLOCK];
+            }
+        } else {
+            int enc = ~ref;
+            int first = enc >> 3, cnt = (enc & 7) + 1;
+            for (int k = 0; k < cnt; ++k) {
+                int i = first + k;
+                ++n_prims;
+                const float4* pr = W.prims + 3 * i;
+                float4 A = pr[0], B = pr[1];
+                if (__float_as_int(B.w) == 0) {
+                    float4 C = pr[2];
+                    v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
+                    v3 p = cross(d, e2);
+                    float det = dot(e1, p);
+                    if (det == 0.0f) continue;
+                    float inv = 1.0f / det;
+                    v3 s = o - v0;
+                    float uu = dot(s, p) * inv;
+                    if (uu < 0.0f || uu > 1.0f) continue;
+                    v3 q = cross(s, e1);
+                    float vv = dot(d, q) * inv;
+                    if (vv < 0.0f || uu + vv > 1.0f) continue;
+                    float t = dot(e2, q) * inv;
+                    if (!(t > 0.0f && t < tb)) continue;
+                    tb = t; h.prim = i; h.t = t; h.u = uu; h.v = vv;
+                } else {
+                    v3 oc = o - mk(A.x, A.y, A.z);
+                    float r = B.x;
+                    float bb = dot(d, oc), cc = dot(oc, oc) - r * r;
+                    float disc = bb * bb - cc;
+                    if (disc < 0.0f) continue;
+                    float sq = sqrtf(disc);
+                    float t = -bb - sq;
+                    if (!(t > 0.0f)) t = -bb + sq;
+                    if (!(t > 0.0f && t < tb)) continue;
+                    tb = t; h.prim = i; h.t = t; h.u = 0.0f; h.v = 0.0f;
+                }
+                if (ANY) return true;
+            }
+            if (sp == 0) break;
+            ref = stack[(--sp) * BLOCK];
+        }
+    }
+    return h.prim >= 0;
+}
+
+DEV float offset_eps(v3 p) { return 1e-4f * (1.0f + fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z))); }
+DEV v3 spawn(v3 p, v3 ng, v3 dir) {
+    float e = offset_eps(p);
+    return p + ng * (dot(dir, ng) > 0.0f ? e : -e);
+}
+
+// ============================================================================ path vertices
+struct Vtx {
+    v3 p, ng, ns, wo, wi, wl;
+    float u, v;
+    int mat, orig;
+    bool front, emit;
+    int lobe, nee, light;
+    float prob, pdf, nee_geom;
+};
+
+struct Sig {
+    uint64_t h;
+    DEV void add(uint32_t x) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { h ^= (x >> (8 * i)) & 0xffu; h *= 1099511628211ull; }
+    }
+};
+
+struct Counters { uint32_t nodes, prims, shadow, verts; };
+
+DEV bool is_delta(int t) { return t == MAT_DIELECTRIC || t == MAT_SHEET; }
+
+// Surface data of a hit (identical whether the hit comes from traversal or from a record).
+DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
+    const float4* pr = W.prims + 3 * h.prim;
+    float4 A = pr[0], B = pr[1];
+    x.orig = __float_as_int(A.w);
+    if (__float_as_int(B.w) == 0) {
+        float4 C = pr[2];
+        v3 e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
+        x.p = mk(A.x, A.y, A.z) + e1 * h.u + e2 * h.v;
+        x.ng = normalize(cross(e1, e2));
+        const float* t = W.tri_uv + 6 * (size_t)x.orig;
+        float b0 = 1.0f - h.u - h.v;
+        x.u = b0 * t[0] + h.u * t[2] + h.v * t[4];
+        x.v = b0 * t[1] + h.u * t[3] + h.v * t[5];
+    } else {
+        x.p = o + d * h.t;
+        v3 nout = normalize(x.p - mk(A.x, A.y, A.z));
+        x.ng = B.x < 0.0f ? -nout : nout;
+        x.u = 0.5f + atan2f(nout.z, nout.x) * (0.5f / PI_F);
+        x.v = acosf(fminf(fmaxf(nout.y, -1.0f), 1.0f)) * (1.0f / PI_F);
+    }
+    x.mat = W.prim_mat[x.orig];
+}
+
+DEV int sample_glossy(v3 ns, v3 wo, float alpha, float u1, float u2, v3& wi, float& pdf) {
+    float tan2 = alpha * alpha * u1 / (1.0f - u1);
+    float ch = 1.0f / sqrtf(1.0f + tan2);
+    float sh = sqrtf(fmaxf(0.0f, 1.0f - ch * ch));
+    float ph = 2.0f * PI_F * u2;
+    v3 tx, ty;
+    onb(ns, tx, ty);
+    v3 h = tx * (sh * cosf(ph)) + ty * (sh * sinf(ph)) + ns * ch;
+    float woh = dot(wo, h);
+    if (!(woh > 0.0f)) return LOBE_INVALID;
+    wi = h * (2.0f * woh) - wo;
+    if (!(dot(ns, wi) > 0.0f)) return LOBE_INVALID;
+    pdf = ggx_D(ch, alpha) * ch / (4.0f * woh);
+    return LOBE_GLOSSY;
+}
+DEV int sample_diffuse(v3 ns, float u1, float u2, v3& wi, float& pdf) {
+    v3 tx, ty;
+    onb(ns, tx, ty);
+    float r = sqrtf(u1), ph = 2.0f * PI_F * u2;
+    wi = tx * (r * cosf(ph)) + ty * (r * sinf(ph)) + ns * sqrtf(fmaxf(0.0f, 1.0f - u1));
+    pdf = dot(ns, wi) * (1.0f / PI_F);
+    return LOBE_DIFFUSE;
+}
+
+// Camera ray of (pixel, sample): jitter from bounce 0, call 0.
+DEV void camera_ray(const DevView& V, int px, int py, uint32_t smp, uint64_t seed, v3& o, v3& d) {
+    float u[4];
+    uniforms(seed, (uint32_t)(py * V.width + px), smp, V.view_id, 0, 0, u);
+    float sx = (2.0f * ((float)px + u[0]) / (float)V.width - 1.0f) * V.tan_h * V.aspect;
+    float sy = (1.0f - 2.0f * ((float)py + u[1]) / (float)V.height) * V.tan_h;
+    o = ld3(V.o);
+    d = normalize(ld3(V.f) + ld3(V.r) * sx + ld3(V.u) * sy);
+}
+
+constexpr int NEE_NONE = 0, NEE_VISIBLE = 1, NEE_OCCLUDED = 2, NEE_ZERO = 3, NEE_PENDING = 4;
+
+// Everything detached about vertex b (1-based) given the ray direction d that reached it:
+// emission rule, the next-event light sample, the lobe choice and continuation direction.
+// When the light sample needs a visibility test, x.nee = NEE_PENDING and (so, sd, stmax)
+// describe the shadow ray; the caller resolves it (a shadow-ray kernel, or a recorded flag).
+DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64_t seed, uint32_t pix, uint32_t smp,
+                      int b, int max_depth, uint32_t flags, bool prev_delta, v3 d, Vtx& x, v3& so, v3& sd,
+                      float& stmax) {
+    const DevMaterial& m = W.mats[x.mat];
+    x.wo = -d;
+    x.front = dot(x.ng, x.wo) > 0.0f;
+    x.ns = x.front ? x.ng : -x.ng;
+    x.emit = m.emit_slot >= 0 && x.front && (b == 1 || prev_delta || (flags & FLAG_NO_NEE));
+    x.lobe = LOBE_NONE;
+    x.nee = NEE_NONE;
+    x.prob = 1.0f; x.pdf = 1.0f; x.nee_geom = 0.0f; x.light = 0;
+    if (m.type == MAT_EMITTER || b == max_depth) return;
+    float ua[4], ub[4];
+    uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 0, ua);
+    uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 1, ub);
+    if (!is_delta(m.type) && !(flags & FLAG_NO_NEE) && W.n_lights > 0) {
+        int nl = W.n_lights;
+        int li = min((int)(ua[3] * (float)nl), nl - 1);
+        const DevLight& L = W.lights[li];
+        v3 y = ld3(L.p0) + ld3(L.eu) * ub[0] + ld3(L.ev) * ub[1];
+        v3 dv = y - x.p;
+        float dist2 = dot(dv, dv), dist = sqrtf(dist2);
+        x.wl = dv * (1.0f / dist);
+        x.light = li;
+        float cos_y = -dot(ld3(L.n), x.wl), cos_x = dot(x.ns, x.wl);
+        if (!(cos_y > 0.0f) || !(cos_x > 0.0f)) {
+            x.nee = NEE_ZERO;
+        } else {
+            so = spawn(x.p, x.ng, x.wl);
+            v3 sv = y - so;
+            float sl = sqrtf(dot(sv, sv));
+            sd = sv * (1.0f / sl);
+            stmax = sl - offset_eps(y);
+            x.nee = NEE_PENDING;
+            x.nee_geom = cos_y * L.area * (float)nl / dist2;
+        }
+    }
+    switch (m.type) {
+        case MAT_LAMBERT:
+            x.lobe = sample_diffuse(x.ns, ua[1], ua[2], x.wi, x.pdf);
+            break;
+        case MAT_GGX_DIELECTRIC:
+        case MAT_GGX_CONDUCTOR:
+            x.lobe = sample_glossy(x.ns, x.wo, rough(K, m, x.u, x.v, nullptr), ua[1], ua[2], x.wi, x.pdf);
+            break;
+        case MAT_BLEND:
+            if (ua[0] < m.blend) {
+                x.lobe = sample_diffuse(x.ns, ua[1], ua[2], x.wi, x.pdf);
+                x.prob = m.blend;
+            } else {
+                x.lobe = sample_glossy(x.ns, x.wo, rough(K, m, x.u, x.v, nullptr), ua[1], ua[2], x.wi, x.pdf);
+                x.prob = 1.0f - m.blend;
+            }
+            break;
+        case MAT_DIELECTRIC: {
+            float eta = K.p(m.eta_slot, m.eta_off);
+            float ecam = x.front ? 1.0f : eta, efar = x.front ? eta : 1.0f;
+            float mr = efar / ecam;
+            float co = dot(x.ns, x.wo);
+            float st2 = (1.0f - co * co) / (mr * mr);
+            float PR = 1.0f;
+            if (st2 < 1.0f) {
+                float a, bb, c, dd;
+                fresnel_R(co, cf{mr, 0.0f}, a, bb, c, dd);
+                PR = a;
+            }
+            if (ua[0] < PR) {
+                x.wi = x.ns * (2.0f * co) - x.wo;
+                x.prob = PR;
+                x.lobe = LOBE_REFLECT;
+            } else {
+                float ct = sqrtf(1.0f - st2);
+                x.wi = normalize((-x.wo) * (1.0f / mr) + x.ns * (co / mr - ct));
+                x.prob = 1.0f - PR;
+                x.lobe = LOBE_TRANSMIT;
+            }
+            break;
+        }
+        case MAT_SHEET:
+            x.wi = -x.wo;
+            x.lobe = LOBE_SHEET;
+            break;
+        default:
+            x.lobe = LOBE_INVALID;
+    }
+}
+
+// ============================================================================ Mueller weights
+// Compact sample weight: W_c = rgb_c * (kind 1: E00 | kind 2: Rout * F(A,B,C,D) * Rin),
+// F = [[A,B,0,0],[B,A,0,0],[0,0,C,D],[0,0,-D,C]], R = rotator (cos 2phi, sin 2phi).
+struct WC {
+    float rgb[3];
+    float A, B, C, D;
+    float ci, si, co, so;
+    int kind;  // 0 zero, 1 diffuse, 2 Fresnel form
+};
+DEV void w_apply(const WC& w, int c, const float* in, float* out) {
+    if (w.kind == 0) { out[0] = out[1] = out[2] = out[3] = 0.0f; return; }
+    if (w.kind == 1) { out[0] = w.rgb[c] * in[0]; out[1] = out[2] = out[3] = 0.0f; return; }
+    float v1 = w.ci * in[1] + w.si * in[2], v2 = -w.si * in[1] + w.ci * in[2];
+    float f0 = w.A * in[0] + w.B * v1, f1 = w.B * in[0] + w.A * v1;
+    float f2 = w.C * v2 + w.D * in[3], f3 = -w.D * v2 + w.C * in[3];
+    float s = w.rgb[c];
+    out[0] = s * f0;
+    out[1] = s * (w.co * f1 + w.so * f2);
+    out[2] = s * (-w.so * f1 + w.co * f2);
+    out[3] = s * f3;
+}
+DEV void w_row(const WC& w, int c, const float* a, float* out) {
+    if (w.kind == 0) { out[0] = out[1] = out[2] = out[3] = 0.0f; return; }
+    if (w.kind == 1) { out[0] = w.rgb[c] * a[0]; out[1] = out[2] = out[3] = 0.0f; return; }
+    float r1 = w.co * a[1] - w.so * a[2], r2 = w.so * a[1] + w.co * a[2];
+    float g0 = w.A * a[0] + w.B * r1, g1 = w.B * a[0] + w.A * r1;
+    float g2 = w.C * r2 - w.D * a[3], g3 = w.D * r2 + w.C * a[3];
+    float s = w.rgb[c];
+    out[0] = s * g0;
+    out[1] = s * (w.ci * g1 - w.si * g2);
+    out[2] = s * (w.si * g1 + w.ci * g2);
+    out[3] = s * g3;
+}
+// Local-frame adjoint of the Fresnel-form entries: gA..gD = sum_c of a_c^T (dW) L_c terms.
+DEV void w_local_grad(const WC& w, const float* a, const float* L, float& gA, float& gB, float& gC, float& gD) {
+    gA = gB = gC = gD = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float* ac = a + 4 * c;
+        const float* Lc = L + 4 * c;
+        float r1 = w.co * ac[1] - w.so * ac[2], r2 = w.so * ac[1] + w.co * ac[2];  // a R_out
+        float l1 = w.ci * Lc[1] + w.si * Lc[2], l2 = -w.si * Lc[1] + w.ci * Lc[2];  // R_in L
+        float s = w.rgb[c];
+        gA += s * (ac[0] * Lc[0] + r1 * l1);
+        gB += s * (ac[0] * l1 + r1 * Lc[0]);
+        gC += s * (r2 * l2 + ac[3] * Lc[3]);
+        gD += s * (r2 * Lc[3] - ac[3] * l2);
+    }
+}
+
+// frames of a specular event with incident propagation k_in, incident-side normal n_inc, output k_out
+DEV void spec_frames(v3 k_in, v3 n_inc, v3 k_out, WC& w) {
+    v3 s = s_axis(k_in, n_inc);
+    rot_cs(k_in, canon_x(k_in), s, w.ci, w.si);
+    rot_cs(k_out, s, canon_x(k_out), w.co, w.so);
+}
+
+// GGX microfacet pBRDF for light arriving along -wi and leaving along wo: frames, local
+// Fresnel entries (unscaled) and kappa = D G / (4 cos_i cos_o).
+struct GGXv { WC w; float a, b, c, d, kappa, ih, ci, co, ch, alpha; bool in; };
+DEV void ggx_eval(const Call& K, const DevMaterial& m, const Vtx& x, v3 wi, cf eta, GGXv& g) {
+    v3 h = normalize(wi + x.wo);
+    g.ci = dot(x.ns, wi); g.co = dot(x.ns, x.wo); g.ch = dot(x.ns, h);
+    g.ih = fabsf(dot(wi, h));
+    g.alpha = rough(K, m, x.u, x.v, &g.in);
+    float D = ggx_D(g.ch, g.alpha);
+    float G = smith_G1(g.ci, g.alpha) * smith_G1(g.co, g.alpha);
+    g.kappa = D * G / (4.0f * g.ci * g.co);
+    fresnel_R(g.ih, eta, g.a, g.b, g.c, g.d);
+    spec_frames(-wi, h, x.wo, g.w);
+    g.w.rgb[0] = g.w.rgb[1] = g.w.rgb[2] = 1.0f;
+    g.w.kind = 2;
+}
+// gradient of a GGX lobe scaled by s: entries of s*kappa*F0 have local adjoint (gA..gD)
+DEV void ggx_backprop(const Vtx& x, cf eta, const GGXv& g, float s, float gA, float gB, float gC, float gD,
+                      GradVtx& gv) {
+    float sk = s * g.kappa;
+    float gk = s * (g.a * gA + g.b * gB + g.c * gC + g.d * gD);  // d/d kappa
+    if (g.in && g.kappa != 0.0f) {
+        float dln = ggx_dlnD(g.ch, g.alpha) + smith_dlnG1(g.ci, g.alpha) + smith_dlnG1(g.co, g.alpha);
+        gv.alpha += gk * g.kappa * dln;
+    }
+    cf gm = fresnel_R_vjp(g.ih, eta, sk * gA, sk * gB, sk * gC, sk * gD);
+    gv.eta += gm.re;
+    gv.kap += gm.im;
+}
+
+// W_b and E_b of a vertex (values), and with GRAD their vector-Jacobian products against the
+// adjoint rows a (3 x 4, canonical frame of wo) and the cached suffix Ln (3 x 4, frame of -wi):
+// d(sum_c a_c . (E_c + W_c Ln_c)) / d params, accumulated through Call.
+// Eemit receives the emission of the vertex and Enee the next-event part (computed when the
+// light sample is visible or still pending).
+template <bool GRAD>
+DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, float* Eemit, float* Enee, const float* a,
+                     const float* Ln) {
+    const DevMaterial& m = W.mats[x.mat];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) { Eemit[i] = 0.0f; Enee[i] = 0.0f; }
+    GradVtx gv;
+    if (GRAD) gv.zero();
+    w.kind = 0;
+    if (x.emit) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Eemit[4 * c] = K.p(m.emit_slot, m.emit_off + c);
+            if (GRAD) gv.emit[c] += a[4 * c];
+        }
+    }
+    // next-event estimation: E_c += f_c e0 * cos_x * geom * Le_c
+    if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
+        const DevLight& L = W.lights[x.light];
+        float cx = dot(x.ns, x.wl);
+        float gs = cx * x.nee_geom;
+        float le[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) le[c] = K.p(L.le_slot, L.le_off + c);
+        float wd = 0.0f, wg = 0.0f;
+        if (m.type == MAT_LAMBERT) wd = 1.0f;
+        else if (m.type == MAT_BLEND) { wd = m.blend; wg = 1.0f - m.blend; }
+        else if (m.type == MAT_GGX_DIELECTRIC || m.type == MAT_GGX_CONDUCTOR) wg = 1.0f;
+        if (wd != 0.0f) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float rho = albedo(K, m, c, x.u, x.v);
+                Enee[4 * c] += wd * rho * (1.0f / PI_F) * gs * le[c];
+                if (GRAD) {
+                    gv.rho[c] += a[4 * c] * wd * gs * le[c] * (1.0f / PI_F);
+                    gv.le[c] += a[4 * c] * wd * rho * gs * (1.0f / PI_F);
+                }
+            }
+        }
+        if (wg != 0.0f) {
+            bool real_ior = m.type != MAT_GGX_CONDUCTOR;
+            cf eta = real_ior ? cf{K.p(m.eta_slot, m.eta_off), 0.0f} : ior(K, m);
+            GGXv g;
+            ggx_eval(K, m, x, x.wl, eta, g);
+            // f e0 = Rout kappa (a, b, 0, 0) = kappa (a, Cout b, -Sout b, 0)
+            float e0 = g.kappa * g.a, e1 = g.kappa * g.w.co * g.b, e2 = -g.kappa * g.w.so * g.b;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float s = wg * gs * le[c];
+                Enee[4 * c] += s * e0; Enee[4 * c + 1] += s * e1; Enee[4 * c + 2] += s * e2;
+            }
+            if (GRAD) {
+                float qa = 0.0f, qb = 0.0f;  // sum_c s_c (a_c0) and sum_c s_c (a_c1 Cout - a_c2 Sout)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float q = a[4 * c], r = a[4 * c + 1] * g.w.co - a[4 * c + 2] * g.w.so;
+                    float s = wg * gs * le[c];
+                    qa += s * q; qb += s * r;
+                    gv.le[c] += wg * gs * g.kappa * (q * g.a + r * g.b);
+                }
+                // local adjoint of kappa*F0 entries: e0 = kappa a, e1/e2 = kappa b rotated
+                ggx_backprop(x, eta, g, 1.0f, qa, qb, 0.0f, 0.0f, gv);
+            }
+        }
+    }
+    // continuation weight W = f cos / (pdf * lobe probability), both detached
+    switch (x.lobe) {
+        case LOBE_DIFFUSE: {
+            w.kind = 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                w.rgb[c] = albedo(K, m, c, x.u, x.v);
+                if (GRAD) gv.rho[c] += a[4 * c] * Ln[4 * c];
+            }
+            w.A = w.B = w.C = w.D = 0.0f; w.ci = w.co = 1.0f; w.si = w.so = 0.0f;
+            break;
+        }
+        case LOBE_GLOSSY: {
+            bool real_ior = m.type != MAT_GGX_CONDUCTOR;
+            cf eta = real_ior ? cf{K.p(m.eta_slot, m.eta_off), 0.0f} : ior(K, m);
+            GGXv g;
+            ggx_eval(K, m, x, x.wi, eta, g);
+            float s = g.ci / x.pdf;  // f cos / pdf; the selected lobe's weight equals its probability
+            float k = g.kappa * s;
+            w = g.w;
+            w.A = k * g.a; w.B = k * g.b; w.C = k * g.c; w.D = k * g.d;
+            if (GRAD) {
+                float gA, gB, gC, gD;
+                w_local_grad(w, a, Ln, gA, gB, gC, gD);
+                ggx_backprop(x, eta, g, s, gA, gB, gC, gD, gv);
+            }
+            break;
+        }
+        case LOBE_REFLECT:
+        case LOBE_TRANSMIT: {
+            float eta = K.p(m.eta_slot, m.eta_off);
+            float ecam = x.front ? 1.0f : eta, efar = x.front ? eta : 1.0f;
+            float a0, b0, c0, d0, ci;
+            cf mm;
+            if (x.lobe == LOBE_REFLECT) {
+                ci = dot(x.ns, x.wo);
+                mm = cf{efar / ecam, 0.0f};
+                fresnel_R(ci, mm, a0, b0, c0, d0);
+                spec_frames(-x.wi, x.ns, x.wo, w);
+            } else {
+                ci = fabsf(dot(x.wi, x.ns));
+                mm = cf{ecam / efar, 0.0f};
+                fresnel_T(ci, mm, a0, b0, c0, d0);
+                spec_frames(-x.wi, -x.ns, x.wo, w);
+            }
+            float ip = 1.0f / x.prob;
+            w.kind = 2;
+            w.rgb[0] = w.rgb[1] = w.rgb[2] = 1.0f;
+            w.A = a0 * ip; w.B = b0 * ip; w.C = c0 * ip; w.D = d0 * ip;
+            if (GRAD) {
+                float gA, gB, gC, gD;
+                w_local_grad(w, a, Ln, gA, gB, gC, gD);
+                cf gm = (x.lobe == LOBE_REFLECT) ? fresnel_R_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip)
+                                                 : fresnel_T_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip);
+                // m = eta (camera outside, reflection) or 1/eta, and the reverse for transmission
+                bool m_is_eta = (x.lobe == LOBE_REFLECT) == x.front;
+                gv.eta += m_is_eta ? gm.re : -gm.re / (eta * eta);
+            }
+            break;
+        }
+        case LOBE_SHEET: {
+            v3 k = x.wo;
+            v3 t = mk(m.axis[0], m.axis[1], m.axis[2]);
+            v3 xt = normalize(t - k * dot(t, k));
+            rot_cs(k, canon_x(k), xt, w.ci, w.si);
+            rot_cs(k, xt, canon_x(k), w.co, w.so);
+            w.kind = 2;
+            w.rgb[0] = w.rgb[1] = w.rgb[2] = 1.0f;
+            w.A = w.B = 0.5f; w.C = w.D = 0.0f;
+            break;
+        }
+        default:
+            break;
+    }
+    if (GRAD) {
+        // one scatter per parameter the vertex read
+        albedo_scatter(K, m, x.u, x.v, gv.rho);
+        if (m.alpha_slot >= 0) rough_scatter(K, m, x.u, x.v, gv.alpha);
+        if (m.eta_slot >= 0) K.g(m.eta_slot, m.eta_off, gv.eta);
+        if (m.kap_slot >= 0) K.g(m.kap_slot, m.kap_off, gv.kap);
+        if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
+            const DevLight& L = W.lights[x.light];
+            for (int c = 0; c < 3; ++c) K.g(L.le_slot, L.le_off + c, gv.le[c]);
+        }
+        if (m.emit_slot >= 0)
+            for (int c = 0; c < 3; ++c) K.g(m.emit_slot, m.emit_off + c, gv.emit[c]);
+    }
+}
+
+// ============================================================================ sensor
+// analyzer a applied to a sensor-frame Stokes vector
+DEV void analyzer_apply(int sensor, float theta, int a, const float* v, float* o) {
+    if (sensor == SENSOR_NONE) { o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; return; }
+    float C, S, q;
+    if (sensor == SENSOR_POLARIZER) {
+        C = cosf(2.0f * theta); S = sinf(2.0f * theta);
+        q = 0.5f * (v[0] + C * v[1] + S * v[2]);
+    } else if (a == 0) { C = 1.0f; S = 0.0f; q = 0.5f * (v[0] + v[1]); }
+    else if (a == 1) { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[2]); }
+    else if (a == 2) { C = -1.0f; S = 0.0f; q = 0.5f * (v[0] - v[1]); }
+    else { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[3]); }  // QWP(0) then polarizer at 45 deg
+    o[0] = q; o[1] = C * q; o[2] = S * q; o[3] = 0.0f;
+}
+// row delta^T A_a
+DEV void analyzer_row(int sensor, float theta, int a, const float* dl, float* r) {
+    if (sensor == SENSOR_NONE) { r[0] = dl[0]; r[1] = dl[1]; r[2] = dl[2]; r[3] = dl[3]; return; }
+    float C, S;
+    int kind = 0;
+    if (sensor == SENSOR_POLARIZER) { C = cosf(2.0f * theta); S = sinf(2.0f * theta); }
+    else if (a == 0) { C = 1.0f; S = 0.0f; }
+    else if (a == 1) { C = 0.0f; S = 1.0f; }
+    else if (a == 2) { C = -1.0f; S = 0.0f; }
+    else { C = 0.0f; S = 1.0f; kind = 1; }
+    float q = 0.5f * (dl[0] + C * dl[1] + S * dl[2]);  // output = w q(v), w = (1, C, S, 0)
+    if (kind == 0) { r[0] = q; r[1] = C * q; r[2] = S * q; r[3] = 0.0f; }
+    else { r[0] = q; r[1] = 0.0f; r[2] = 0.0f; r[3] = q; }
+}
+// delta^T (dP(theta)/dtheta) v
+DEV float polarizer_dtheta(float theta, const float* dl, const float* v) {
+    float C = cosf(2.0f * theta), S = sinf(2.0f * theta);
+    float r0 = -S * dl[1] + C * dl[2];
+    float r1 = -S * dl[0] - 2.0f * C * S * dl[1] + (C * C - S * S) * dl[2];
+    float r2 = C * dl[0] + (C * C - S * S) * dl[1] + 2.0f * C * S * dl[2];
+    return r0 * v[0] + r1 * v[1] + r2 * v[2];
+}
+
+
+}  // namespace ppt

@@ -1,6 +1,6 @@
 // ppt_host.cpp -- host side of the C ABI: scene blob parsing and validation, binned-SAH BVH
 // construction (flattened to the two-box node layout the traversal kernel reads), plan
-// creation (views and work queue), workspace layout and kernel launches.
+// creation (views and chunking of the path index space), workspace layout and the launch sequence.
 #include "ppt_internal.h"
 #include "../../include/ppt.h"
 
@@ -14,14 +14,13 @@
 #include <vector>
 
 namespace ppt {
-hipError_t launch_setup(const CallTable& tab, CallTable* dst, int* queue, Stats* stats, bool reset_stats, hipStream_t s);
+hipError_t launch_setup(const CallTable& tab, CallTable* dst, Stats* stats, bool reset_stats, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
-hipError_t launch_render(const KArgs& a, int grid_blocks, hipStream_t s);
-hipError_t launch_backward(const KArgs& a, int grid_blocks, hipStream_t s);
 hipError_t launch_finalize(const CallTable* tab, const double* gacc, int n_slots, int64_t max_numel, hipStream_t s);
 hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t s);
-hipError_t occupancy(int* render_blocks_per_cu, int* backward_blocks_per_cu);
+hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s);
+hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G);
 }  // namespace ppt
 
 using namespace ppt;
@@ -166,6 +165,7 @@ struct Builder {
 struct WorldHost {
     DevBuf nodes, prims, prim_mat, tri_uv, mats, lights;
     DevWorld dev;
+    int bvh_depth = 0;
 };
 
 struct ppt_scene {
@@ -174,6 +174,7 @@ struct ppt_scene {
     std::vector<WorldHost*> worlds;
     DevBuf dev_worlds;
     int cu_count = 256;
+    int stack_cap = 2;     // traversal stack entries: deepest BVH + 2
     ~ppt_scene() { for (auto* w : worlds) delete w; }
 };
 
@@ -181,12 +182,15 @@ struct ppt_plan {
     const ppt_scene* scene = nullptr;
     std::vector<ppt_view> views;
     std::vector<DevView> dviews;
-    DevBuf dev_views, dev_items;
-    int32_t n_items = 0, max_depth = 1;
+    DevBuf dev_views;
+    int32_t max_depth = 1;
     uint32_t flags = 0;
     int64_t image_numel = 0, num_paths = 0;
-    int grid_render_blocks = 1, grid_backward_blocks = 1;
+    int32_t Q = 64;             // paths per chunk (slots of the path state)
+    int32_t n_chunks = 1;
+    LaunchGrid grid{1, 1, 1, 1};
     const uint8_t* mask = nullptr;
+    bool stats = true;
 };
 
 static bool slot_ok(const ppt_scene* s, int32_t slot, int64_t off, int64_t n) {
@@ -309,6 +313,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
     if (np > 0) {
         B.build(0, (int)np, 0);
         if (B.max_depth >= STACK - 1) return fail(PPT_EUNSUPPORTED, "BVH deeper than the traversal stack");
+        wh.bvh_depth = B.max_depth;
         // leaf references / inner node renumbering (inner nodes only, preorder)
         std::vector<int> inner_id(B.nodes.size(), -1);
         int n_inner = 0;
@@ -389,26 +394,49 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
 }
 
 // ============================================================================ workspace layout
+// [call table][stats][queue counts][path state of one chunk (SoA)][FP64 gradient accumulators]
 struct WsLayout {
-    size_t table, queue, stats, gacc, cache, total;
+    size_t table, stats, counts, gacc, total;
+    int lds_nd = 0, lds_nf = 0;
+    size_t ro, rd, info, pix, smp, hprim, ht, hu, hv, beta, Lo, pend, so, sd, stmax, cache, q0, q1, sq;
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(const ppt_plan* p, int op) {
     WsLayout L{};
+    const size_t Q = (size_t)p->Q;
     size_t at = 0;
-    L.table = at; at = align256(at + sizeof(CallTable));
-    L.queue = at; at = align256(at + 16);
-    L.stats = at; at = align256(at + sizeof(Stats));
+    auto take = [&](size_t bytes) { size_t r = at; at = align256(at + bytes); return r; };
+    L.table = take(sizeof(CallTable));
+    L.stats = take(sizeof(Stats));
+    L.counts = take(16);
+    L.ro = take(12 * Q); L.rd = take(12 * Q); L.info = take(4 * Q); L.pix = take(4 * Q); L.smp = take(4 * Q);
+    L.hprim = take(4 * Q); L.ht = take(4 * Q); L.hu = take(4 * Q); L.hv = take(4 * Q);
+    L.beta = take(op == 0 ? 19 * 4 * Q : 0);
+    L.Lo = take(op == 0 ? 12 * 4 * Q : 0);
+    L.pend = take(12 * 4 * Q);
+    L.so = take(12 * Q); L.sd = take(12 * Q); L.stmax = take(4 * Q);
+    L.cache = take(op == 1 ? (size_t)p->max_depth * CACHE_WORDS * 4 * Q : 0);
+    L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q);
     L.gacc_n = 0;
     if (op == 1)
         for (int64_t n : p->scene->slot_numel) L.gacc_n += n;
-    L.gacc = at; at = align256(at + (size_t)L.gacc_n * 8);
-    L.cache = at;
-    if (op == 1)
-        at = align256(at + (size_t)p->grid_backward_blocks * (BLOCK / WAVE) * p->max_depth * CACHE_WORDS * WAVE * 4);
+    L.gacc = take((size_t)L.gacc_n * 8);
     L.total = at;
     return L;
+}
+static PathState path_state(void* ws, const WsLayout& L) {
+    char* w = (char*)ws;
+    PathState S;
+    S.ro = (float*)(w + L.ro); S.rd = (float*)(w + L.rd); S.info = (int*)(w + L.info);
+    S.pix = (uint32_t*)(w + L.pix); S.smp = (uint32_t*)(w + L.smp);
+    S.hprim = (int*)(w + L.hprim); S.ht = (float*)(w + L.ht); S.hu = (float*)(w + L.hu); S.hv = (float*)(w + L.hv);
+    S.beta = (float*)(w + L.beta); S.Lo = (float*)(w + L.Lo);
+    S.pend = (float*)(w + L.pend); S.so = (float*)(w + L.so); S.sd = (float*)(w + L.sd); S.stmax = (float*)(w + L.stmax);
+    S.cache = (float*)(w + L.cache);
+    S.queue0 = (int*)(w + L.q0); S.queue1 = (int*)(w + L.q1); S.squeue = (int*)(w + L.sq);
+    S.counts = (int*)(w + L.counts);
+    return S;
 }
 
 // ============================================================================ C ABI
@@ -445,6 +473,7 @@ int ppt_scene_create(const void* blob, size_t nbytes, ppt_scene** out) {
         int rc = convert_world(sc, p, end, *wh, (int)w);
         if (rc) { delete sc; return rc; }
         dw.push_back(wh->dev);
+        sc->stack_cap = std::max(sc->stack_cap, wh->bvh_depth + 2);
     }
     if (p != end) { delete sc; return fail(PPT_EINVAL, "trailing bytes after the last world"); }
     int rc = sc->dev_worlds.upload(dw.data(), dw.size() * sizeof(DevWorld), "world table");
@@ -474,7 +503,8 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
     P->max_depth = max_depth;
     P->flags = flags;
     P->views.assign(views, views + n_views);
-    int64_t out_off = 0, path_off = 0, total_tile_samples = 0;
+    int64_t out_off = 0, path_off = 0;
+    if (n_views >= (1 << 19)) { delete P; return fail(PPT_EUNSUPPORTED, "too many views"); }
     for (int32_t v = 0; v < n_views; ++v) {
         const ppt_view& V = views[v];
         bool ok = V.world >= 0 && V.world < (int32_t)sc->worlds.size() && V.width >= 1 && V.height >= 1 &&
@@ -515,37 +545,24 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
         D.view_id = V.view_id;
         D.out_off = out_off;
         D.path_off = path_off;
-        D.tiles_x = (V.crop_w + TILE - 1) / TILE;
-        D.tiles_y = (V.crop_h + TILE - 1) / TILE;
         out_off += (int64_t)D.n_analyzers * V.crop_w * V.crop_h * 12;
         path_off += (int64_t)V.crop_w * V.crop_h * V.spp;
-        total_tile_samples += (int64_t)D.tiles_x * D.tiles_y * V.spp;
         P->dviews.push_back(D);
     }
     P->image_numel = out_off;
     P->num_paths = path_off;
-    // persistent grid from occupancy
-    int rb = 1, bb = 1;
-    if (occupancy(&rb, &bb) != hipSuccess) { delete P; return fail(PPT_EDEVICE, "occupancy query failed"); }
-    int waves_target = opts && opts->grid_waves > 0 ? opts->grid_waves : 0;
-    P->grid_render_blocks = std::max(1, waves_target > 0 ? (waves_target + 3) / 4 : rb * sc->cu_count);
-    P->grid_backward_blocks = std::max(1, waves_target > 0 ? (waves_target + 3) / 4 : bb * sc->cu_count);
-    // work items: (view, tile, sample chunk); chunk chosen for ~4 items per resident wavefront
-    int64_t resident = (int64_t)std::max(P->grid_render_blocks, P->grid_backward_blocks) * (BLOCK / WAVE);
-    int chunk = opts && opts->samples_per_item > 0 ? opts->samples_per_item
-                                                   : (int)std::max<int64_t>(1, total_tile_samples / (4 * resident));
-    std::vector<WorkItem> items;
-    for (int32_t v = 0; v < n_views; ++v) {
-        const DevView& D = P->dviews[v];
-        int ntile = D.tiles_x * D.tiles_y;
-        int c = std::min(chunk, D.spp);
-        for (int t = 0; t < ntile; ++t)
-            for (int s0 = 0; s0 < D.spp; s0 += c) items.push_back(WorkItem{v, t, s0, std::min(D.spp, s0 + c)});
+    // chunk of paths in flight: all paths up to 16M by default, a multiple of the wavefront size
+    int64_t q = opts && opts->chunk_paths > 0 ? opts->chunk_paths : (int64_t)1 << 24;
+    q = std::min<int64_t>(q, std::max<int64_t>(path_off, 1));
+    q = ((q + WAVE - 1) / WAVE) * WAVE;
+    if (q > ((int64_t)1 << 28)) { delete P; return fail(PPT_EUNSUPPORTED, "chunk too large"); }
+    P->Q = (int32_t)q;
+    P->n_chunks = (int32_t)std::max<int64_t>(1, (path_off + q - 1) / q);
+    if (occupancy_grid(sc->cu_count, sc->stack_cap, &P->grid) != hipSuccess) {
+        delete P;
+        return fail(PPT_EDEVICE, "occupancy query failed");
     }
-    if (items.size() >= (size_t)INT32_MAX) { delete P; return fail(PPT_EUNSUPPORTED, "too many work items"); }
-    P->n_items = (int32_t)items.size();
     int rc = P->dev_views.upload(P->dviews.data(), P->dviews.size() * sizeof(DevView), "views");
-    if (!rc) rc = P->dev_items.upload(items.data(), items.size() * sizeof(WorkItem), "work items");
     if (rc) { delete P; return rc; }
     *out = P;
     return PPT_OK;
@@ -558,26 +575,31 @@ size_t ppt_plan_workspace_bytes(const ppt_plan* p, int32_t op) {
     if (!p || op < 0 || op > 1) return 0;
     return ws_layout(p, op).total;
 }
+int ppt_plan_set_stats(ppt_plan* p, int32_t enabled) {
+    if (!p) return fail(PPT_EINVAL, "null plan");
+    p->stats = enabled != 0;
+    return PPT_OK;
+}
 int ppt_plan_set_path_mask(ppt_plan* p, const uint8_t* mask) {
     if (!p) return fail(PPT_EINVAL, "null plan");
     p->mask = mask;
     return PPT_OK;
 }
-int ppt_plan_launch_info(const ppt_plan* p, int32_t* gr, int32_t* gb, int32_t* ni) {
+int ppt_plan_launch_info(const ppt_plan* p, int64_t* chunk_paths, int32_t* n_chunks, int32_t* stack_entries) {
     if (!p) return fail(PPT_EINVAL, "null plan");
-    if (gr) *gr = p->grid_render_blocks * (BLOCK / WAVE);
-    if (gb) *gb = p->grid_backward_blocks * (BLOCK / WAVE);
-    if (ni) *ni = p->n_items;
+    if (chunk_paths) *chunk_paths = p->Q;
+    if (n_chunks) *n_chunks = p->n_chunks;
+    if (stack_entries) *stack_entries = p->scene->stack_cap;
     return PPT_OK;
 }
 
 static int fill_table(const ppt_plan* p, const float* const* params, int32_t n_params, float* const* grads,
-                      const WsLayout& L, CallTable& t, int64_t* max_numel) {
+                      WsLayout& L, CallTable& t, int64_t* max_numel) {
     const ppt_scene* sc = p->scene;
     if (!params || n_params != (int32_t)sc->slot_numel.size()) return fail(PPT_EINVAL, "parameter count mismatch");
     std::memset(&t, 0, sizeof t);
     int64_t off = 0, mx = 1;
-    for (int i = 0; i < MAX_SLOTS; ++i) { t.goff[i] = -1; }
+    for (int i = 0; i < MAX_SLOTS; ++i) { t.goff[i] = -1; t.lds_d[i] = -1; t.lds_f[i] = -1; }
     for (int32_t i = 0; i < n_params; ++i) {
         if (!params[i] && sc->slot_numel[i] > 0) return fail(PPT_EINVAL, "null parameter pointer");
         t.p[i] = params[i];
@@ -587,23 +609,32 @@ static int fill_table(const ppt_plan* p, const float* const* params, int32_t n_p
         mx = std::max(mx, sc->slot_numel[i]);
     }
     if (max_numel) *max_numel = mx;
-    (void)L;
+    // workgroup gradient accumulators: small slots in FP64, then textures in FP32 while they fit
+    int nd = 0, nf = 0;
+    for (int32_t i = 0; i < n_params; ++i) {
+        if (t.goff[i] < 0) continue;
+        int64_t n = sc->slot_numel[i];
+        if (n <= 64 && nd + n <= LDS_GRAD_D) { t.lds_d[i] = nd; nd += (int)n; }
+        else if (nf + n <= LDS_GRAD_F) { t.lds_f[i] = nf; nf += (int)n; }
+    }
+    L.lds_nd = nd; L.lds_nf = nf;
     return PPT_OK;
 }
 
-static KArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayout& L) {
-    KArgs a{};
+static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayout& L) {
+    WArgs a{};
     char* w = (char*)ws;
     a.worlds = (const DevWorld*)p->scene->dev_worlds.p;
     a.views = (const DevView*)p->dev_views.p;
-    a.items = (const WorkItem*)p->dev_items.p;
-    a.n_items = p->n_items;
+    a.n_views = (int32_t)p->dviews.size();
     a.max_depth = p->max_depth;
     a.flags = p->flags;
+    a.stack_cap = p->scene->stack_cap;
     a.seed = seed;
     a.table = (CallTable*)(w + L.table);
-    a.queue = (int*)(w + L.queue);
-    a.stats = (Stats*)(w + L.stats);
+    a.stats = p->stats ? (Stats*)(w + L.stats) : nullptr;
+    a.S = path_state(ws, L);
+    a.Q = p->Q;
     a.mask = p->mask;
     return a;
 }
@@ -616,6 +647,16 @@ static int check_ws(const ppt_plan* p, void* ws, size_t ws_bytes, int op, WsLayo
     return PPT_OK;
 }
 
+static int run_chunks(const ppt_plan* p, WArgs a, int mode, hipStream_t s) {
+    for (int c = 0; c < p->n_chunks; ++c) {
+        a.g0 = (int64_t)c * p->Q;
+        a.n_chunk = (int32_t)std::min<int64_t>(p->Q, p->num_paths - a.g0);
+        if (a.n_chunk <= 0) break;
+        HIP_TRY(launch_chunk(a, mode, p->grid, s), mode == 0 ? "render launch" : "backward launch");
+    }
+    return PPT_OK;
+}
+
 static int render_impl(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed,
                        float* out, uint64_t* sig, void* ws, size_t ws_bytes, void* stream) {
     WsLayout L;
@@ -625,13 +666,12 @@ static int render_impl(const ppt_plan* p, const float* const* params, int32_t n_
     CallTable t;
     if ((rc = fill_table(p, params, n_params, nullptr, L, t, nullptr))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    KArgs a = make_args(p, seed, ws, L);
+    WArgs a = make_args(p, seed, ws, L);
     a.out = out;
     a.sig = sig;
-    HIP_TRY(launch_setup(t, a.table, a.queue, a.stats, true, s), "setup launch");
+    HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), p->stats, s), "setup launch");
     if (out) HIP_TRY(launch_fill_f32(out, p->image_numel, s), "clear launch");
-    HIP_TRY(launch_render(a, p->grid_render_blocks, s), "render launch");
-    return PPT_OK;
+    return run_chunks(p, a, 0, s);
 }
 
 int ppt_render(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed, float* out, void* ws,
@@ -657,22 +697,22 @@ int ppt_backward(const ppt_plan* p, const float* const* params, int32_t n_params
     int64_t mx = 1;
     if ((rc = fill_table(p, params, n_params, grads, L, t, &mx))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    KArgs a = make_args(p, seed, ws, L);
-    char* w = (char*)ws;
+    WArgs a = make_args(p, seed, ws, L);
     a.dout = d_stokes;
-    a.gacc = (double*)(w + L.gacc);
-    a.cache = (float*)(w + L.cache);
-    HIP_TRY(launch_setup(t, a.table, a.queue, a.stats, true, s), "setup launch");
+    a.gacc = (double*)((char*)ws + L.gacc);
+    a.lds_nd = L.lds_nd;
+    a.lds_nf = L.lds_nf;
+    HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), p->stats, s), "setup launch");
     HIP_TRY(launch_fill_f64(a.gacc, L.gacc_n, s), "clear launch");
-    HIP_TRY(launch_backward(a, p->grid_backward_blocks, s), "backward launch");
+    if ((rc = run_chunks(p, a, 1, s))) return rc;
     HIP_TRY(launch_finalize(a.table, a.gacc, n_params, mx, s), "finalize launch");
     return PPT_OK;
 }
 
 int ppt_read_stats(const void* ws, int64_t* out, void* stream) {
     if (!ws || !out) return fail(PPT_EINVAL, "null argument");
-    // the stats block sits at a fixed offset (after the call table and queue)
-    size_t off = align256(align256(sizeof(CallTable)) + 16);
+    // the stats block sits at a fixed offset, right after the call table
+    size_t off = align256(sizeof(CallTable));
     Stats st;
     HIP_TRY(hipMemcpyAsync(&st, (const char*)ws + off, sizeof st, hipMemcpyDeviceToHost, (hipStream_t)stream), "stats copy");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "stats sync");

@@ -7,13 +7,12 @@
 namespace ppt {
 
 constexpr int MAX_SLOTS = 64;   // parameter tensors per scene
-constexpr int TILE = 8;         // an 8x8 pixel tile is one 64-lane wavefront
 constexpr int WAVE = 64;
-constexpr int BLOCK = 256;      // 4 wavefronts per workgroup; each fetches its own work items
+constexpr int BLOCK = 256;      // 4 wavefronts per workgroup
 constexpr int MAX_DEPTH = 64;
 constexpr int STACK = 64;       // BVH traversal stack entries per lane
 
-// per-vertex cache record of the backward pass (32-bit words, lane-interleaved in memory)
+// per-vertex cache record of the backward pass (32-bit words, one SoA array per word)
 constexpr int CW_W = 0;         // 11 words: compact Mueller weight (rgb[3], a, b, c, d, Cin, Sin, Cout, Sout)
 constexpr int CW_E = 11;        // 12 words: E_b per channel, overwritten by the suffix L[b] in the fold
 constexpr int CW_HIT = 23;      // 3 words: prim | flags, barycentric u (or t), barycentric v
@@ -67,10 +66,7 @@ struct DevView {
     uint32_t view_id, pad;
     int64_t out_off;             // float offset of this view in the output image
     int64_t path_off;            // index of its first path (view, crop row, crop column, sample)
-    int32_t tiles_x, tiles_y;
 };
-
-struct WorkItem { int32_t view, tile, s0, s1; };
 
 // Per-call device table written by the setup kernel (kernel arguments cannot be indexed
 // per lane without spilling): parameter pointers and gradient accumulator offsets.
@@ -79,31 +75,67 @@ struct CallTable {
     int64_t goff[MAX_SLOTS];     // element offset into the FP64 gradient accumulator, -1 = not requested
     float* gout[MAX_SLOTS];      // user gradient tensors (finalize kernel)
     int64_t numel[MAX_SLOTS];
+    int32_t lds_d[MAX_SLOTS];    // offset in the workgroup FP64 gradient accumulator, -1 = none
+    int32_t lds_f[MAX_SLOTS];    // offset in the workgroup FP32 gradient accumulator, -1 = none
 };
+
+constexpr int LDS_GRAD_D = 1024;    // FP64 entries of the workgroup gradient accumulator (small slots)
+constexpr int LDS_GRAD_F = 12800;   // FP32 entries (textures)
 
 struct Stats {                  // accumulated by every launch (64-bit counters)
     unsigned long long vertices, paths, nodes, prims, shadow_rays;
 };
 
-struct KArgs {
+// Structure-of-arrays state of the paths of one chunk (capacity Q slots), in the workspace.
+// Arrays of k components store component j of slot i at [j * Q + i].
+struct PathState {
+    float* ro;      // 3: ray origin
+    float* rd;      // 3: ray direction
+    int* info;      // vertices so far (bits 0-7), previous vertex delta (bit 8), masked (bit 9), view (bits 12+)
+    uint32_t* pix;  // pixel index in the full image (random-stream key)
+    uint32_t* smp;  // sample index
+    int* hprim;     // closest hit: primitive (BVH order) or -1
+    float* ht;
+    float* hu;
+    float* hv;
+    float* beta;    // render: 16 shared prefix-Mueller entries + 3 RGB scales (set at the first vertex)
+    float* Lo;      // render: 12 accumulated Stokes components (canonical frame of the camera ray)
+    float* pend;    // 12: next-event contribution awaiting its visibility test
+    float* so;      // 3: shadow ray origin
+    float* sd;      // 3: shadow ray direction
+    float* stmax;   // shadow ray length
+    float* cache;   // backward: [max_depth][CACHE_WORDS][Q] per-vertex cache
+    int* queue0;    // ray queues (alternating per bounce) and the shadow queue
+    int* queue1;
+    int* squeue;
+    int* counts;    // 4 ints: queue0, queue1, shadow queue sizes
+};
+
+struct WArgs {
     const DevWorld* worlds;
     const DevView* views;
-    const WorkItem* items;
-    int32_t n_items;
+    int32_t n_views;
     int32_t max_depth;
     uint32_t flags;
-    uint32_t pad0;
+    int32_t stack_cap;      // traversal stack entries per thread (LDS)
     uint64_t seed;
-    CallTable* table;            // in the workspace
-    int* queue;                  // work-queue head (workspace)
-    Stats* stats;                // workspace
-    float* out;                  // render: Stokes image
-    const float* dout;           // backward: dL/dStokes
-    double* gacc;                // backward: FP64 gradient accumulator
-    float* cache;                // backward: per-lane vertex cache
-    uint64_t* sig;               // optional per-path signature output
-    const uint8_t* mask;         // optional per-path mask
+    CallTable* table;
+    Stats* stats;           // NULL: no counters
+    PathState S;
+    int32_t Q;              // slots per chunk
+    int32_t n_chunk;        // paths in this chunk
+    int64_t g0;             // global index of the chunk's first path
+    int32_t qin;            // ray queue read in this bounce (0/1)
+    int32_t first;          // first bounce: the queue is the identity over the chunk's slots
+    int32_t lds_nd, lds_nf;  // used entries of the workgroup gradient accumulators
+    float* out;             // render output
+    const float* dout;      // backward: dL/dStokes
+    double* gacc;           // backward: FP64 gradient accumulators
+    uint64_t* sig;          // optional per-path signatures (global path index)
+    const uint8_t* mask;    // optional per-path mask (global path index)
 };
+
+struct LaunchGrid { int extend, shade, adjoint, other; };  // workgroups per kernel family
 
 constexpr uint32_t FLAG_NO_NEE = 1u;
 

@@ -1,1031 +1,447 @@
-// ppt_kernels.hip -- gfx950 kernels of the differentiable polarized path tracer.
+// ppt_kernels.hip -- wavefront kernels of the differentiable polarized path tracer (gfx950).
 //
-// One lane owns one pixel of an 8x8 tile (one 64-lane wavefront per tile) and loops over a
-// chunk of that pixel's samples.  Wavefronts of a persistent grid pull (view, tile, sample
-// chunk) items from an atomic queue.  Everything is FP32 vector ALU work: 4-vector Stokes
-// states and structured 4x4 Mueller operators (no dense contraction, so no MFMA).
-//
-// Paper references: Monte Carlo estimator and rendering equation (Sec. 3.1, Eq. 2); path
-// replay backpropagation (Sec. 3.2); Mueller-Stokes calculus (Sec. 3.3); cached suffix
-// replay (Sec. 4.3, Fig. 2): the backward pass traces each path once, caching per-vertex
-// weights, emission and a hit record, folds the cache backward into suffix radiance
-// L[b] = E_b + W_b L[b+1], then replays the path forward from the hit records (no second
-// traversal) and differentiates each vertex locally against the cached L[b+1].
-#include "ppt_internal.h"
-
-#include <hip/hip_runtime.h>
-#include <cstdint>
+// Paths are processed in chunks of a flat index space that spans every view of a plan (the
+// batch): path g = (view, crop pixel, sample), samples fastest.  Per chunk and bounce:
+//   k_extend   closest-hit traversal of the queued rays (lean kernel, LDS traversal stack),
+//   k_shade    vertex sampling and Mueller weights; appends continuing paths to the next ray
+//              queue and next-event rays to the shadow queue (wave-aggregated atomics),
+//   k_shadow   any-hit traversal of the next-event rays.
+// Render (Sec. 3.1, Eq. 2): the state carries the prefix Mueller product beta and the radiance
+// sum; k_accum reduces the samples of each pixel.  Backward (Sec. 3.2, 4.3, Fig. 2): the primal
+// pass caches, per vertex, the weight W_b, the emission + next-event Stokes E_b and a hit record;
+// k_adjoint folds the cache into suffix radiance L[b] = E_b + W_b L[b+1] and replays the path
+// forward from the hit records (no second traversal), differentiating each vertex against the
+// cached L[b+1].  No Mueller matrix is inverted.
+#include "ppt_device.h"
 
 namespace ppt {
 
-#define DEV __device__ __forceinline__
-
-constexpr float PI_F = 3.14159265358979323846f;
-
-// ============================================================================ vectors
-struct v3 { float x, y, z; };
-DEV v3 mk(float x, float y, float z) { return {x, y, z}; }
-DEV v3 operator+(v3 a, v3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-DEV v3 operator-(v3 a, v3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-DEV v3 operator-(v3 a) { return {-a.x, -a.y, -a.z}; }
-DEV v3 operator*(v3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
-DEV float dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-DEV v3 cross(v3 a, v3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
-DEV v3 normalize(v3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
-DEV v3 ld3(const float* p) { return {p[0], p[1], p[2]}; }
-
-// ============================================================================ complex
-struct cf { float re, im; };
-DEV cf cadd(cf a, cf b) { return {a.re + b.re, a.im + b.im}; }
-DEV cf csub(cf a, cf b) { return {a.re - b.re, a.im - b.im}; }
-DEV cf cmul(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-DEV cf cscale(cf a, float s) { return {a.re * s, a.im * s}; }
-DEV cf cconj(cf a) { return {a.re, -a.im}; }
-DEV float cabs2(cf a) { return a.re * a.re + a.im * a.im; }
-DEV cf cdiv(cf a, cf b) {
-    float d = 1.0f / cabs2(b);
-    return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
-}
-// principal square root; a zero imaginary part counts as +0
-DEV cf csqrt(cf z) {
-    float r = hypotf(z.re, z.im);
-    if (r == 0.0f) return {0.0f, 0.0f};
-    if (z.re >= 0.0f) {
-        float t = sqrtf(0.5f * (r + z.re));
-        return {t, z.im / (2.0f * t)};
-    }
-    float t = sqrtf(0.5f * (r - z.re));
-    return {fabsf(z.im) / (2.0f * t), z.im < 0.0f ? -t : t};
-}
-
-// ============================================================================ RNG
-// Philox4x32-10 (Salmon et al., SC'11).  Counter (pixel, sample, view << 8 | bounce, call).
-DEV void philox(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
-    }
-}
-DEV float u01(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }  // exact: 24 bits / 2^24
-DEV void uniforms(uint64_t seed, uint32_t pix, uint32_t smp, uint32_t view, uint32_t bounce, uint32_t call,
-                  float u[4]) {
-    uint32_t c0 = pix, c1 = smp, c2 = (view << 8) | (bounce & 0xffu), c3 = call;
-    philox(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
-    u[0] = u01(c0); u[1] = u01(c1); u[2] = u01(c2); u[3] = u01(c3);
-}
-
 // ============================================================================ wave helpers
-DEV int lane_id() { return threadIdx.x & (WAVE - 1); }
-DEV float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-DEV uint32_t wave_sum_u(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-// ============================================================================ frames
-// Orthonormal basis (x, y, n) of Duff et al. 2017.
-DEV void onb(v3 n, v3& x, v3& y) {
-    float sg = copysignf(1.0f, n.z);
-    float a = -1.0f / (sg + n.z);
-    float b = n.x * n.y * a;
-    x = mk(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
-    y = mk(b, sg + n.y * n.y * a, -n.y);
-}
-// canonical transverse basis vector of the Stokes frame of light travelling along k
-DEV v3 canon_x(v3 k) {
-    v3 x, y;
-    onb(k, x, y);
-    return x;
-}
-// Stokes rotator between transverse bases x_from -> x_to about k: (cos 2phi, sin 2phi)
-DEV void rot_cs(v3 k, v3 x_from, v3 x_to, float& C, float& S) {
-    float c = dot(x_from, x_to), s = dot(cross(k, x_from), x_to);
-    C = c * c - s * s;
-    S = 2.0f * c * s;
-}
-// s-axis of a specular event for incident propagation k_in and normal n_inc on the incident side
-DEV v3 s_axis(v3 k_in, v3 n_inc) {
-    v3 s = cross(k_in, n_inc);
-    float l2 = dot(s, s);
-    if (l2 < 1e-16f) return canon_x(k_in);
-    return s * (1.0f / sqrtf(l2));
-}
-
-// ============================================================================ Fresnel
-struct Fres { cf rs, rp, ts, tp, ct; float kappa, st2r; };
-// Born & Wolf amplitudes for incidence cosine ci and relative index m = n2 / n1.
-DEV void fresnel_amp(float ci, cf m, Fres& F, bool trans) {
-    cf m2 = cmul(m, m);
-    cf st2 = cdiv(cf{1.0f - ci * ci, 0.0f}, m2);
-    F.ct = csqrt(csub(cf{1.0f, 0.0f}, st2));
-    cf mct = cmul(m, F.ct), mci = cscale(m, ci);
-    cf c{ci, 0.0f};
-    F.rs = cdiv(csub(c, mct), cadd(c, mct));
-    F.rp = cdiv(csub(mci, F.ct), cadd(mci, F.ct));
-    if (trans) {
-        F.ts = cdiv(cf{2.0f * ci, 0.0f}, cadd(c, mct));
-        F.tp = cdiv(cf{2.0f * ci, 0.0f}, cadd(mci, F.ct));
-        F.kappa = mct.re / ci;
+// Workgroup-aggregated counters: one global atomic per workgroup and counter.  Every thread of
+// the workgroup must call it (it synchronizes the workgroup).
+DEV void flush_stats(Stats* st, uint32_t nodes, uint32_t prims, uint32_t shadow, uint32_t verts, uint32_t paths) {
+    if (!st) return;
+    __shared__ uint32_t part[5];
+    if (threadIdx.x < 5) part[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t v[5] = {wave_sum_u(nodes), wave_sum_u(prims), wave_sum_u(shadow), wave_sum_u(verts), wave_sum_u(paths)};
+    if (lane_id() == 0)
+        for (int k = 0; k < 5; ++k)
+            if (v[k]) atomicAdd(&part[k], v[k]);
+    __syncthreads();
+    if (threadIdx.x < 5 && part[threadIdx.x]) {
+        unsigned long long* dst[5] = {&st->nodes, &st->prims, &st->shadow_rays, &st->vertices, &st->paths};
+        atomicAdd(dst[threadIdx.x], (unsigned long long)part[threadIdx.x]);
     }
 }
-// Mueller entries (a, b, c, d) of a Jones matrix diag(as, ap)
-DEV void jones_abcd(cf as, cf ap, float& a, float& b, float& c, float& d) {
-    float A = cabs2(as), B = cabs2(ap);
-    cf z = cmul(as, cconj(ap));
-    a = 0.5f * (A + B); b = 0.5f * (A - B); c = z.re; d = z.im;
-}
-DEV void fresnel_R(float ci, cf m, float& a, float& b, float& c, float& d) {
-    Fres F;
-    fresnel_amp(ci, m, F, false);
-    jones_abcd(F.rs, F.rp, a, b, c, d);
-}
-DEV void fresnel_T(float ci, cf m, float& a, float& b, float& c, float& d) {
-    Fres F;
-    fresnel_amp(ci, m, F, true);
-    jones_abcd(F.ts, F.tp, a, b, c, d);
-    a *= F.kappa; b *= F.kappa; c *= F.kappa; d *= F.kappa;
-}
-// Adjoint of jones_abcd: gradients (conjugate convention d/dRe + i d/dIm) of the amplitudes.
-DEV void jones_abcd_vjp(cf as, cf ap, float ga, float gb, float gc, float gd, cf& g_as, cf& g_ap) {
-    float gA = 0.5f * (ga + gb), gB = 0.5f * (ga - gb);
-    cf gz{gc, gd}, gzc{gc, -gd};
-    g_as = cadd(cscale(as, 2.0f * gA), cmul(gz, ap));
-    g_ap = cadd(cscale(ap, 2.0f * gB), cmul(gzc, as));
-}
-// d(loss)/dm (conjugate convention) of the reflection entries; the amplitudes are holomorphic
-// in m with d(m ct)/dm = 1/ct and d ct/dm = st2 / (m ct).
-DEV cf fresnel_R_vjp(float ci, cf m, float ga, float gb, float gc, float gd) {
-    Fres F;
-    fresnel_amp(ci, m, F, false);
-    cf g_rs, g_rp;
-    jones_abcd_vjp(F.rs, F.rp, ga, gb, gc, gd, g_rs, g_rp);
-    cf m2 = cmul(m, m);
-    cf st2 = cdiv(cf{1.0f - ci * ci, 0.0f}, m2);
-    cf u = cmul(m, F.ct), v = cscale(m, ci);
-    cf cu = cadd(cf{ci, 0.0f}, u), cv = cadd(v, F.ct);
-    cf drs = cdiv(cf{-2.0f * ci, 0.0f}, cmul(cmul(cu, cu), F.ct));
-    cf drp = cdiv(cscale(csub(cmul(F.ct, F.ct), st2), 2.0f * ci), cmul(F.ct, cmul(cv, cv)));
-    return cadd(cmul(g_rs, cconj(drs)), cmul(g_rp, cconj(drp)));
-}
-DEV cf fresnel_T_vjp(float ci, cf m, float ga, float gb, float gc, float gd) {
-    Fres F;
-    fresnel_amp(ci, m, F, true);
-    float a, b, c, d;
-    jones_abcd(F.ts, F.tp, a, b, c, d);
-    float gk = ga * a + gb * b + gc * c + gd * d;
-    cf g_ts, g_tp;
-    jones_abcd_vjp(F.ts, F.tp, F.kappa * ga, F.kappa * gb, F.kappa * gc, F.kappa * gd, g_ts, g_tp);
-    cf m2 = cmul(m, m);
-    cf st2 = cdiv(cf{1.0f - ci * ci, 0.0f}, m2);
-    cf u = cmul(m, F.ct), v = cscale(m, ci);
-    cf cu = cadd(cf{ci, 0.0f}, u), cv = cadd(v, F.ct);
-    cf dts = cdiv(cf{-2.0f * ci, 0.0f}, cmul(cmul(cu, cu), F.ct));
-    cf dct = cdiv(st2, cmul(m, F.ct));
-    cf dtp = cdiv(cscale(cadd(cf{ci, 0.0f}, dct), -2.0f * ci), cmul(cv, cv));
-    cf du = cdiv(cf{1.0f, 0.0f}, F.ct);
-    cf g = cadd(cmul(g_ts, cconj(dts)), cmul(g_tp, cconj(dtp)));
-    return cadd(g, cscale(cconj(du), gk / ci));
-}
 
-// ============================================================================ GGX
-DEV float ggx_D(float ch, float a) {
-    if (ch <= 0.0f) return 0.0f;
-    float a2 = a * a, d = (a2 - 1.0f) * ch * ch + 1.0f;
-    return a2 / (PI_F * d * d);
-}
-DEV float ggx_dlnD(float ch, float a) {
-    float a2 = a * a, d = (a2 - 1.0f) * ch * ch + 1.0f;
-    return 2.0f / a - 4.0f * a * ch * ch / d;
-}
-DEV float smith_G1(float cw, float a) {
-    if (cw <= 0.0f) return 0.0f;
-    float t2 = (1.0f - cw * cw) / (cw * cw);
-    float s = sqrtf(1.0f + a * a * t2);
-    return 1.0f / (1.0f + 0.5f * (s - 1.0f));
-}
-DEV float smith_dlnG1(float cw, float a) {
-    float t2 = (1.0f - cw * cw) / (cw * cw);
-    float s = sqrtf(1.0f + a * a * t2);
-    float lam = 0.5f * (s - 1.0f);
-    return -(a * t2 / (2.0f * s)) / (1.0f + lam);
-}
-
-// ============================================================================ scene access
-struct Call {
-    const CallTable* tab;
-    double* gacc;
-    DEV float p(int slot, int idx) const { return tab->p[slot][idx]; }
-    DEV void g(int slot, int idx, float v) const {
-        if (v == 0.0f) return;
-        int64_t o = tab->goff[slot];
-        if (o >= 0) unsafeAtomicAdd(gacc + o + idx, (double)v);
-    }
+// Workgroup queue in LDS: lanes append with one LDS atomic per wavefront; the buffer is copied
+// to the global queue (one global atomic per flush) when another workgroup iteration might not
+// fit, and at the end.
+constexpr int QBUF = 2048;
+struct BlockQueue {
+    int n, base;
+    int buf[QBUF];
 };
-
-// bilinear, clamp to edge, texel centres at (i + 1/2)/N, layout [th][tw][ch]
-struct Bilin { int i[4]; float w[4]; };
-DEV void bilin(float u, float v, int tw, int th, int ch, Bilin& B) {
-    float x = u * (float)tw - 0.5f, y = v * (float)th - 0.5f;
-    float x0f = floorf(x), y0f = floorf(y);
-    float fx = x - x0f, fy = y - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    int xa = min(max(x0, 0), tw - 1), xb = min(max(x0 + 1, 0), tw - 1);
-    int ya = min(max(y0, 0), th - 1), yb = min(max(y0 + 1, 0), th - 1);
-    B.i[0] = (ya * tw + xa) * ch; B.w[0] = (1.0f - fx) * (1.0f - fy);
-    B.i[1] = (ya * tw + xb) * ch; B.w[1] = fx * (1.0f - fy);
-    B.i[2] = (yb * tw + xa) * ch; B.w[2] = (1.0f - fx) * fy;
-    B.i[3] = (yb * tw + xb) * ch; B.w[3] = fx * fy;
+DEV void bq_push(BlockQueue& q, bool pred, int slot) {
+    unsigned long long m = __ballot(pred);
+    int wb = 0;
+    if (lane_id() == 0 && m) wb = atomicAdd(&q.n, (int)__popcll(m));
+    wb = __shfl(wb, 0, WAVE);
+    if (pred) q.buf[wb + (int)__popcll(m & ((1ull << lane_id()) - 1ull))] = slot;
 }
-DEV float albedo(const Call& K, const DevMaterial& m, int c, float u, float v) {
-    if (m.alb_tw == 0) return K.p(m.alb_slot, m.alb_off + c);
-    Bilin B;
-    bilin(u, v, m.alb_tw, m.alb_th, 3, B);
-    float r = 0.0f;
+// all threads of the workgroup call it after the pushes of an iteration
+DEV void bq_flush(BlockQueue& q, int* gcount, int* gqueue, bool force) {
+    __syncthreads();
+    int n = q.n;
+    if (n > 0 && (force || n > QBUF - BLOCK)) {
+        if (threadIdx.x == 0) q.base = atomicAdd(gcount, n);
+        __syncthreads();
+        int b = q.base;
+        for (int k = threadIdx.x; k < n; k += BLOCK) gqueue[b + k] = q.buf[k];
+        __syncthreads();
+        if (threadIdx.x == 0) q.n = 0;
+        __syncthreads();
+    }
+}
+DEV void sig_add(uint64_t& h, uint32_t x) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) r += K.p(m.alb_slot, m.alb_off + B.i[k] + c) * B.w[k];
+    for (int i = 0; i < 4; ++i) { h ^= (x >> (8 * i)) & 0xffu; h *= 1099511628211ull; }
+}
+
+// view of a global path index (views are few; binary search over their path offsets)
+DEV int find_view(const DevView* views, int n_views, int64_t g) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (views[mid].path_off <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+struct PathId { int v, px, py, lx, ly; uint32_t smp, pix; };
+DEV PathId path_id(const DevView* views, int n_views, int64_t g) {
+    PathId r;
+    r.v = find_view(views, n_views, g);
+    const DevView& V = views[r.v];
+    int64_t local = g - V.path_off;
+    int64_t pl = local / V.spp;
+    r.smp = (uint32_t)(local - pl * V.spp);
+    r.lx = (int)(pl % V.crop_w);
+    r.ly = (int)(pl / V.crop_w);
+    r.px = V.crop_x0 + r.lx;
+    r.py = V.crop_y0 + r.ly;
+    r.pix = (uint32_t)(r.py * V.width + r.px);
     return r;
 }
-DEV void albedo_grad(const Call& K, const DevMaterial& m, int c, float u, float v, float g) {
-    if (g == 0.0f) return;
-    if (m.alb_tw == 0) { K.g(m.alb_slot, m.alb_off + c, g); return; }
-    Bilin B;
-    bilin(u, v, m.alb_tw, m.alb_th, 3, B);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) K.g(m.alb_slot, m.alb_off + B.i[k] + c, g * B.w[k]);
-}
-// roughness, clamped to [1e-3, 1]; *inside tells whether the clamp is inactive
-DEV float rough(const Call& K, const DevMaterial& m, float u, float v, bool* inside) {
-    float a;
-    if (m.alpha_tw == 0) {
-        a = K.p(m.alpha_slot, m.alpha_off);
-    } else {
-        Bilin B;
-        bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
-        a = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a += K.p(m.alpha_slot, m.alpha_off + B.i[k]) * B.w[k];
-    }
-    bool in = a >= 1e-3f && a <= 1.0f;
-    if (inside) *inside = in;
-    return fminf(fmaxf(a, 1e-3f), 1.0f);
-}
-DEV void rough_grad(const Call& K, const DevMaterial& m, float u, float v, float g) {
-    if (g == 0.0f) return;
-    if (m.alpha_tw == 0) { K.g(m.alpha_slot, m.alpha_off, g); return; }
-    Bilin B;
-    bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) K.g(m.alpha_slot, m.alpha_off + B.i[k], g * B.w[k]);
-}
-DEV cf ior(const Call& K, const DevMaterial& m) {
-    return cf{K.p(m.eta_slot, m.eta_off), m.kap_slot >= 0 ? K.p(m.kap_slot, m.kap_off) : 0.0f};
+
+// SoA accessors
+DEV v3 ld_v3(const float* a, int Q, int i) { return mk(a[i], a[Q + i], a[2 * Q + i]); }
+DEV void st_v3(float* a, int Q, int i, v3 v) { a[i] = v.x; a[Q + i] = v.y; a[2 * Q + i] = v.z; }
+
+constexpr int INFO_DEAD = 1 << 9;
+DEV int info_make(int nverts, bool prev_delta, int view) { return nverts | (prev_delta ? 256 : 0) | (view << 12); }
+
+// ============================================================================ chunk start
+__global__ void k_reset_counts(int* counts) {
+    if (threadIdx.x < 4) counts[threadIdx.x] = 0;
 }
 
-// ============================================================================ traversal
-struct Hit { int prim; float t, u, v; };
-
-DEV v3 safe_inv(v3 d) {
-    const float e = 1e-20f;
-    return mk(1.0f / (fabsf(d.x) > e ? d.x : copysignf(e, d.x)), 1.0f / (fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
-              1.0f / (fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
-}
-
-// Closest hit (ANY = false) or any hit (ANY = true) with 0 < t < tmax.
-template <bool ANY>
-DEV bool trace(const DevWorld& W, v3 o, v3 d, float tmax, Hit& h, uint32_t& n_nodes, uint32_t& n_prims) {
-    h.prim = -1;
-    if (W.n_prims == 0) return false;
-    v3 id = safe_inv(d);
-    v3 ood = mk(o.x * id.x, o.y * id.y, o.z * id.z);
-    int stack[STACK];
-    int sp = 0;
-    int ref = W.root;
-    float tb = tmax;
-    while (true) {
-        if (ref >= 0) {
-            ++n_nodes;
-            const float4* nd = W.nodes + 4 * ref;
-            float4 q0 = nd[0], q1 = nd[1], q2 = nd[2], q3 = nd[3];
-            float a0 = fmaf(q0.x, id.x, -ood.x), a1 = fmaf(q0.y, id.x, -ood.x);
-            float b0 = fmaf(q0.z, id.y, -ood.y), b1 = fmaf(q0.w, id.y, -ood.y);
-            float c0 = fmaf(q2.x, id.z, -ood.z), c1 = fmaf(q2.y, id.z, -ood.z);
-            float tnL = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
-            float txL = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tb));
-            float e0 = fmaf(q1.x, id.x, -ood.x), e1 = fmaf(q1.y, id.x, -ood.x);
-            float f0 = fmaf(q1.z, id.y, -ood.y), f1 = fmaf(q1.w, id.y, -ood.y);
-            float g0 = fmaf(q2.z, id.z, -ood.z), g1 = fmaf(q2.w, id.z, -ood.z);
-            float tnR = fmaxf(fmaxf(fminf(e0, e1), fminf(f0, f1)), fmaxf(fminf(g0, g1), 0.0f));
-            float txR = fminf(fminf(fmaxf(e0, e1), fmaxf(f0, f1)), fminf(fmaxf(g0, g1), tb));
-            bool hL = tnL <= txL, hR = tnR <= txR;
-            int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
-            if (hL && hR) {
-                if (tnR < tnL) { int t = rL; rL = rR; rR = t; }
-                stack[sp++] = rR;
-                ref = rL;
-            } else if (hL) {
-                ref = rL;
-            } else if (hR) {
-                ref = rR;
-            } else {
-                if (sp == 0) break;
-                ref = stack[--sp];
-            }
-        } else {
-            int enc = ~ref;
-            int first = enc >> 3, cnt = (enc & 7) + 1;
-            for (int k = 0; k < cnt; ++k) {
-                int i = first + k;
-                ++n_prims;
-                const float4* pr = W.prims + 3 * i;
-                float4 A = pr[0], B = pr[1];
-                if (__float_as_int(B.w) == 0) {
-                    float4 C = pr[2];
-                    v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
-                    v3 p = cross(d, e2);
-                    float det = dot(e1, p);
-                    if (det == 0.0f) continue;
-                    float inv = 1.0f / det;
-                    v3 s = o - v0;
-                    float uu = dot(s, p) * inv;
-                    if (uu < 0.0f || uu > 1.0f) continue;
-                    v3 q = cross(s, e1);
-                    float vv = dot(d, q) * inv;
-                    if (vv < 0.0f || uu + vv > 1.0f) continue;
-                    float t = dot(e2, q) * inv;
-                    if (!(t > 0.0f && t < tb)) continue;
-                    tb = t; h.prim = i; h.t = t; h.u = uu; h.v = vv;
-                } else {
-                    v3 oc = o - mk(A.x, A.y, A.z);
-                    float r = B.x;
-                    float bb = dot(d, oc), cc = dot(oc, oc) - r * r;
-                    float disc = bb * bb - cc;
-                    if (disc < 0.0f) continue;
-                    float sq = sqrtf(disc);
-                    float t = -bb - sq;
-                    if (!(t > 0.0f)) t = -bb + sq;
-                    if (!(t > 0.0f && t < tb)) continue;
-                    tb = t; h.prim = i; h.t = t; h.u = 0.0f; h.v = 0.0f;
-                }
-                if (ANY) return true;
-            }
-            if (sp == 0) break;
-            ref = stack[--sp];
-        }
-    }
-    return h.prim >= 0;
-}
-
-DEV float offset_eps(v3 p) { return 1e-4f * (1.0f + fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z))); }
-DEV v3 spawn(v3 p, v3 ng, v3 dir) {
-    float e = offset_eps(p);
-    return p + ng * (dot(dir, ng) > 0.0f ? e : -e);
-}
-
-// ============================================================================ path vertices
-struct Vtx {
-    v3 p, ng, ns, wo, wi, wl;
-    float u, v;
-    int mat, orig;
-    bool front, emit;
-    int lobe, nee, light;
-    float prob, pdf, nee_geom;
-};
-
-struct Sig {
-    uint64_t h;
-    DEV void add(uint32_t x) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { h ^= (x >> (8 * i)) & 0xffu; h *= 1099511628211ull; }
-    }
-};
-
-struct Counters { uint32_t nodes, prims, shadow, verts; };
-
-DEV bool is_delta(int t) { return t == MAT_DIELECTRIC || t == MAT_SHEET; }
-
-// Surface data of a hit (identical whether the hit comes from traversal or from a record).
-DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
-    const float4* pr = W.prims + 3 * h.prim;
-    float4 A = pr[0], B = pr[1];
-    x.orig = __float_as_int(A.w);
-    if (__float_as_int(B.w) == 0) {
-        float4 C = pr[2];
-        v3 e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
-        x.p = mk(A.x, A.y, A.z) + e1 * h.u + e2 * h.v;
-        x.ng = normalize(cross(e1, e2));
-        const float* t = W.tri_uv + 6 * (size_t)x.orig;
-        float b0 = 1.0f - h.u - h.v;
-        x.u = b0 * t[0] + h.u * t[2] + h.v * t[4];
-        x.v = b0 * t[1] + h.u * t[3] + h.v * t[5];
-    } else {
-        x.p = o + d * h.t;
-        v3 nout = normalize(x.p - mk(A.x, A.y, A.z));
-        x.ng = B.x < 0.0f ? -nout : nout;
-        x.u = 0.5f + atan2f(nout.z, nout.x) * (0.5f / PI_F);
-        x.v = acosf(fminf(fmaxf(nout.y, -1.0f), 1.0f)) * (1.0f / PI_F);
-    }
-    x.mat = W.prim_mat[x.orig];
-}
-
-DEV int sample_glossy(v3 ns, v3 wo, float alpha, float u1, float u2, v3& wi, float& pdf) {
-    float tan2 = alpha * alpha * u1 / (1.0f - u1);
-    float ch = 1.0f / sqrtf(1.0f + tan2);
-    float sh = sqrtf(fmaxf(0.0f, 1.0f - ch * ch));
-    float ph = 2.0f * PI_F * u2;
-    v3 tx, ty;
-    onb(ns, tx, ty);
-    v3 h = tx * (sh * cosf(ph)) + ty * (sh * sinf(ph)) + ns * ch;
-    float woh = dot(wo, h);
-    if (!(woh > 0.0f)) return LOBE_INVALID;
-    wi = h * (2.0f * woh) - wo;
-    if (!(dot(ns, wi) > 0.0f)) return LOBE_INVALID;
-    pdf = ggx_D(ch, alpha) * ch / (4.0f * woh);
-    return LOBE_GLOSSY;
-}
-DEV int sample_diffuse(v3 ns, float u1, float u2, v3& wi, float& pdf) {
-    v3 tx, ty;
-    onb(ns, tx, ty);
-    float r = sqrtf(u1), ph = 2.0f * PI_F * u2;
-    wi = tx * (r * cosf(ph)) + ty * (r * sinf(ph)) + ns * sqrtf(fmaxf(0.0f, 1.0f - u1));
-    pdf = dot(ns, wi) * (1.0f / PI_F);
-    return LOBE_DIFFUSE;
-}
-
-// Camera ray of (pixel, sample): jitter from bounce 0, call 0.
-DEV void camera_ray(const DevView& V, int px, int py, uint32_t smp, uint64_t seed, v3& o, v3& d) {
-    float u[4];
-    uniforms(seed, (uint32_t)(py * V.width + px), smp, V.view_id, 0, 0, u);
-    float sx = (2.0f * ((float)px + u[0]) / (float)V.width - 1.0f) * V.tan_h * V.aspect;
-    float sy = (1.0f - 2.0f * ((float)py + u[1]) / (float)V.height) * V.tan_h;
-    o = ld3(V.o);
-    d = normalize(ld3(V.f) + ld3(V.r) * sx + ld3(V.u) * sy);
-}
-
-// Everything detached about vertex b (1-based) given the ray that reached it: emission rule,
-// next-event light sample and visibility, lobe choice and continuation direction.
-// REPLAY: the visibility comes from the recorded flag instead of a shadow ray.
-template <bool REPLAY>
-DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64_t seed, uint32_t pix, uint32_t smp,
-                      int b, int max_depth, uint32_t flags, bool prev_delta, v3 d, Vtx& x, int rec_nee,
-                      Counters& cnt) {
-    const DevMaterial& m = W.mats[x.mat];
-    x.wo = -d;
-    x.front = dot(x.ng, x.wo) > 0.0f;
-    x.ns = x.front ? x.ng : -x.ng;
-    x.emit = m.emit_slot >= 0 && x.front && (b == 1 || prev_delta || (flags & FLAG_NO_NEE));
-    x.lobe = LOBE_NONE;
-    x.nee = 0;
-    x.prob = 1.0f; x.pdf = 1.0f; x.nee_geom = 0.0f; x.light = 0;
-    if (m.type == MAT_EMITTER || b == max_depth) return;
-    float ua[4], ub[4];
-    uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 0, ua);
-    uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 1, ub);
-    if (!is_delta(m.type) && !(flags & FLAG_NO_NEE) && W.n_lights > 0) {
-        int nl = W.n_lights;
-        int li = min((int)(ua[3] * (float)nl), nl - 1);
-        const DevLight& L = W.lights[li];
-        v3 y = ld3(L.p0) + ld3(L.eu) * ub[0] + ld3(L.ev) * ub[1];
-        v3 dv = y - x.p;
-        float dist2 = dot(dv, dv), dist = sqrtf(dist2);
-        x.wl = dv * (1.0f / dist);
-        x.light = li;
-        float cos_y = -dot(ld3(L.n), x.wl), cos_x = dot(x.ns, x.wl);
-        if (!(cos_y > 0.0f) || !(cos_x > 0.0f)) {
-            x.nee = 3;
-        } else {
-            if (REPLAY) {
-                x.nee = rec_nee;
-            } else {
-                v3 so = spawn(x.p, x.ng, x.wl);
-                v3 sd = y - so;
-                float sl = sqrtf(dot(sd, sd));
-                sd = sd * (1.0f / sl);
-                Hit hh;
-                ++cnt.shadow;
-                bool occ = trace<true>(W, so, sd, sl - offset_eps(y), hh, cnt.nodes, cnt.prims);
-                x.nee = occ ? 2 : 1;
-            }
-            x.nee_geom = cos_y * L.area * (float)nl / dist2;
-        }
-    }
-    switch (m.type) {
-        case MAT_LAMBERT:
-            x.lobe = sample_diffuse(x.ns, ua[1], ua[2], x.wi, x.pdf);
-            break;
-        case MAT_GGX_DIELECTRIC:
-        case MAT_GGX_CONDUCTOR:
-            x.lobe = sample_glossy(x.ns, x.wo, rough(K, m, x.u, x.v, nullptr), ua[1], ua[2], x.wi, x.pdf);
-            break;
-        case MAT_BLEND:
-            if (ua[0] < m.blend) {
-                x.lobe = sample_diffuse(x.ns, ua[1], ua[2], x.wi, x.pdf);
-                x.prob = m.blend;
-            } else {
-                x.lobe = sample_glossy(x.ns, x.wo, rough(K, m, x.u, x.v, nullptr), ua[1], ua[2], x.wi, x.pdf);
-                x.prob = 1.0f - m.blend;
-            }
-            break;
-        case MAT_DIELECTRIC: {
-            float eta = K.p(m.eta_slot, m.eta_off);
-            float ecam = x.front ? 1.0f : eta, efar = x.front ? eta : 1.0f;
-            float mr = efar / ecam;
-            float co = dot(x.ns, x.wo);
-            float st2 = (1.0f - co * co) / (mr * mr);
-            float PR = 1.0f;
-            if (st2 < 1.0f) {
-                float a, bb, c, dd;
-                fresnel_R(co, cf{mr, 0.0f}, a, bb, c, dd);
-                PR = a;
-            }
-            if (ua[0] < PR) {
-                x.wi = x.ns * (2.0f * co) - x.wo;
-                x.prob = PR;
-                x.lobe = LOBE_REFLECT;
-            } else {
-                float ct = sqrtf(1.0f - st2);
-                x.wi = normalize((-x.wo) * (1.0f / mr) + x.ns * (co / mr - ct));
-                x.prob = 1.0f - PR;
-                x.lobe = LOBE_TRANSMIT;
-            }
-            break;
-        }
-        case MAT_SHEET:
-            x.wi = -x.wo;
-            x.lobe = LOBE_SHEET;
-            break;
-        default:
-            x.lobe = LOBE_INVALID;
-    }
-}
-
-// ============================================================================ Mueller weights
-// Compact sample weight: W_c = rgb_c * (kind 1: E00 | kind 2: Rout * F(A,B,C,D) * Rin),
-// F = [[A,B,0,0],[B,A,0,0],[0,0,C,D],[0,0,-D,C]], R = rotator (cos 2phi, sin 2phi).
-struct WC {
-    float rgb[3];
-    float A, B, C, D;
-    float ci, si, co, so;
-    int kind;  // 0 zero, 1 diffuse, 2 Fresnel form
-};
-DEV void w_apply(const WC& w, int c, const float* in, float* out) {
-    if (w.kind == 0) { out[0] = out[1] = out[2] = out[3] = 0.0f; return; }
-    if (w.kind == 1) { out[0] = w.rgb[c] * in[0]; out[1] = out[2] = out[3] = 0.0f; return; }
-    float v1 = w.ci * in[1] + w.si * in[2], v2 = -w.si * in[1] + w.ci * in[2];
-    float f0 = w.A * in[0] + w.B * v1, f1 = w.B * in[0] + w.A * v1;
-    float f2 = w.C * v2 + w.D * in[3], f3 = -w.D * v2 + w.C * in[3];
-    float s = w.rgb[c];
-    out[0] = s * f0;
-    out[1] = s * (w.co * f1 + w.so * f2);
-    out[2] = s * (-w.so * f1 + w.co * f2);
-    out[3] = s * f3;
-}
-DEV void w_row(const WC& w, int c, const float* a, float* out) {
-    if (w.kind == 0) { out[0] = out[1] = out[2] = out[3] = 0.0f; return; }
-    if (w.kind == 1) { out[0] = w.rgb[c] * a[0]; out[1] = out[2] = out[3] = 0.0f; return; }
-    float r1 = w.co * a[1] - w.so * a[2], r2 = w.so * a[1] + w.co * a[2];
-    float g0 = w.A * a[0] + w.B * r1, g1 = w.B * a[0] + w.A * r1;
-    float g2 = w.C * r2 - w.D * a[3], g3 = w.D * r2 + w.C * a[3];
-    float s = w.rgb[c];
-    out[0] = s * g0;
-    out[1] = s * (w.ci * g1 - w.si * g2);
-    out[2] = s * (w.si * g1 + w.ci * g2);
-    out[3] = s * g3;
-}
-// Local-frame adjoint of the Fresnel-form entries: gA..gD = sum_c of a_c^T (dW) L_c terms.
-DEV void w_local_grad(const WC& w, const float* a, const float* L, float& gA, float& gB, float& gC, float& gD) {
-    gA = gB = gC = gD = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float* ac = a + 4 * c;
-        const float* Lc = L + 4 * c;
-        float r1 = w.co * ac[1] - w.so * ac[2], r2 = w.so * ac[1] + w.co * ac[2];  // a R_out
-        float l1 = w.ci * Lc[1] + w.si * Lc[2], l2 = -w.si * Lc[1] + w.ci * Lc[2];  // R_in L
-        float s = w.rgb[c];
-        gA += s * (ac[0] * Lc[0] + r1 * l1);
-        gB += s * (ac[0] * l1 + r1 * Lc[0]);
-        gC += s * (r2 * l2 + ac[3] * Lc[3]);
-        gD += s * (r2 * Lc[3] - ac[3] * l2);
-    }
-}
-
-// frames of a specular event with incident propagation k_in, incident-side normal n_inc, output k_out
-DEV void spec_frames(v3 k_in, v3 n_inc, v3 k_out, WC& w) {
-    v3 s = s_axis(k_in, n_inc);
-    rot_cs(k_in, canon_x(k_in), s, w.ci, w.si);
-    rot_cs(k_out, s, canon_x(k_out), w.co, w.so);
-}
-
-// GGX microfacet pBRDF for light arriving along -wi and leaving along wo: frames, local
-// Fresnel entries (unscaled) and kappa = D G / (4 cos_i cos_o).
-struct GGXv { WC w; float a, b, c, d, kappa, ih, ci, co, ch, alpha; bool in; };
-DEV void ggx_eval(const Call& K, const DevMaterial& m, const Vtx& x, v3 wi, cf eta, GGXv& g) {
-    v3 h = normalize(wi + x.wo);
-    g.ci = dot(x.ns, wi); g.co = dot(x.ns, x.wo); g.ch = dot(x.ns, h);
-    g.ih = fabsf(dot(wi, h));
-    g.alpha = rough(K, m, x.u, x.v, &g.in);
-    float D = ggx_D(g.ch, g.alpha);
-    float G = smith_G1(g.ci, g.alpha) * smith_G1(g.co, g.alpha);
-    g.kappa = D * G / (4.0f * g.ci * g.co);
-    fresnel_R(g.ih, eta, g.a, g.b, g.c, g.d);
-    spec_frames(-wi, h, x.wo, g.w);
-    g.w.rgb[0] = g.w.rgb[1] = g.w.rgb[2] = 1.0f;
-    g.w.kind = 2;
-}
-// gradient of a GGX lobe scaled by s: entries of s*kappa*F0 have local adjoint (gA..gD)
-DEV void ggx_backprop(const Call& K, const DevMaterial& m, const Vtx& x, cf eta, bool real_ior, const GGXv& g,
-                      float s, float gA, float gB, float gC, float gD) {
-    float sk = s * g.kappa;
-    float gk = s * (g.a * gA + g.b * gB + g.c * gC + g.d * gD);  // d/d kappa
-    if (g.in && g.kappa != 0.0f) {
-        float dln = ggx_dlnD(g.ch, g.alpha) + smith_dlnG1(g.ci, g.alpha) + smith_dlnG1(g.co, g.alpha);
-        rough_grad(K, m, x.u, x.v, gk * g.kappa * dln);
-    }
-    cf gm = fresnel_R_vjp(g.ih, eta, sk * gA, sk * gB, sk * gC, sk * gD);
-    K.g(m.eta_slot, m.eta_off, gm.re);
-    if (!real_ior && m.kap_slot >= 0) K.g(m.kap_slot, m.kap_off, gm.im);
-}
-
-// W_b and E_b of a vertex (values), and with GRAD their vector-Jacobian products against the
-// adjoint rows a (3 x 4, canonical frame of wo) and the cached suffix Ln (3 x 4, frame of -wi):
-// d(sum_c a_c . (E_c + W_c Ln_c)) / d params, accumulated through Call.
-template <bool GRAD>
-DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, float* E, const float* a, const float* Ln) {
-    const DevMaterial& m = W.mats[x.mat];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) E[i] = 0.0f;
-    w.kind = 0;
-    if (x.emit) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            E[4 * c] = K.p(m.emit_slot, m.emit_off + c);
-            if (GRAD) K.g(m.emit_slot, m.emit_off + c, a[4 * c]);
-        }
-    }
-    // next-event estimation: E_c += f_c e0 * cos_x * geom * Le_c
-    if (x.nee == 1) {
-        const DevLight& L = W.lights[x.light];
-        float cx = dot(x.ns, x.wl);
-        float gs = cx * x.nee_geom;
-        float le[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) le[c] = K.p(L.le_slot, L.le_off + c);
-        float wd = 0.0f, wg = 0.0f;
-        if (m.type == MAT_LAMBERT) wd = 1.0f;
-        else if (m.type == MAT_BLEND) { wd = m.blend; wg = 1.0f - m.blend; }
-        else if (m.type == MAT_GGX_DIELECTRIC || m.type == MAT_GGX_CONDUCTOR) wg = 1.0f;
-        if (wd != 0.0f) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float rho = albedo(K, m, c, x.u, x.v);
-                E[4 * c] += wd * rho * (1.0f / PI_F) * gs * le[c];
-                if (GRAD) {
-                    albedo_grad(K, m, c, x.u, x.v, a[4 * c] * wd * gs * le[c] * (1.0f / PI_F));
-                    K.g(L.le_slot, L.le_off + c, a[4 * c] * wd * rho * gs * (1.0f / PI_F));
-                }
-            }
-        }
-        if (wg != 0.0f) {
-            bool real_ior = m.type != MAT_GGX_CONDUCTOR;
-            cf eta = real_ior ? cf{K.p(m.eta_slot, m.eta_off), 0.0f} : ior(K, m);
-            GGXv g;
-            ggx_eval(K, m, x, x.wl, eta, g);
-            // f e0 = Rout kappa (a, b, 0, 0) = kappa (a, Cout b, -Sout b, 0)
-            float e0 = g.kappa * g.a, e1 = g.kappa * g.w.co * g.b, e2 = -g.kappa * g.w.so * g.b;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float s = wg * gs * le[c];
-                E[4 * c] += s * e0; E[4 * c + 1] += s * e1; E[4 * c + 2] += s * e2;
-            }
-            if (GRAD) {
-                float qa = 0.0f, qb = 0.0f;  // sum_c s_c (a_c0) and sum_c s_c (a_c1 Cout - a_c2 Sout)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float q = a[4 * c], r = a[4 * c + 1] * g.w.co - a[4 * c + 2] * g.w.so;
-                    float s = wg * gs * le[c];
-                    qa += s * q; qb += s * r;
-                    K.g(L.le_slot, L.le_off + c, wg * gs * g.kappa * (q * g.a + r * g.b));
-                }
-                // local adjoint of kappa*F0 entries: e0 = kappa a, e1/e2 = kappa b rotated
-                ggx_backprop(K, m, x, eta, real_ior, g, 1.0f, qa, qb, 0.0f, 0.0f);
-            }
-        }
-    }
-    // continuation weight W = f cos / (pdf * lobe probability), both detached
-    switch (x.lobe) {
-        case LOBE_DIFFUSE: {
-            w.kind = 1;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                w.rgb[c] = albedo(K, m, c, x.u, x.v);
-                if (GRAD) albedo_grad(K, m, c, x.u, x.v, a[4 * c] * Ln[4 * c]);
-            }
-            w.A = w.B = w.C = w.D = 0.0f; w.ci = w.co = 1.0f; w.si = w.so = 0.0f;
-            break;
-        }
-        case LOBE_GLOSSY: {
-            bool real_ior = m.type != MAT_GGX_CONDUCTOR;
-            cf eta = real_ior ? cf{K.p(m.eta_slot, m.eta_off), 0.0f} : ior(K, m);
-            GGXv g;
-            ggx_eval(K, m, x, x.wi, eta, g);
-            float s = g.ci / x.pdf;  // f cos / pdf; the selected lobe's weight equals its probability
-            float k = g.kappa * s;
-            w = g.w;
-            w.A = k * g.a; w.B = k * g.b; w.C = k * g.c; w.D = k * g.d;
-            if (GRAD) {
-                float gA, gB, gC, gD;
-                w_local_grad(w, a, Ln, gA, gB, gC, gD);
-                ggx_backprop(K, m, x, eta, real_ior, g, s, gA, gB, gC, gD);
-            }
-            break;
-        }
-        case LOBE_REFLECT:
-        case LOBE_TRANSMIT: {
-            float eta = K.p(m.eta_slot, m.eta_off);
-            float ecam = x.front ? 1.0f : eta, efar = x.front ? eta : 1.0f;
-            float a0, b0, c0, d0, ci;
-            cf mm;
-            if (x.lobe == LOBE_REFLECT) {
-                ci = dot(x.ns, x.wo);
-                mm = cf{efar / ecam, 0.0f};
-                fresnel_R(ci, mm, a0, b0, c0, d0);
-                spec_frames(-x.wi, x.ns, x.wo, w);
-            } else {
-                ci = fabsf(dot(x.wi, x.ns));
-                mm = cf{ecam / efar, 0.0f};
-                fresnel_T(ci, mm, a0, b0, c0, d0);
-                spec_frames(-x.wi, -x.ns, x.wo, w);
-            }
-            float ip = 1.0f / x.prob;
-            w.kind = 2;
-            w.rgb[0] = w.rgb[1] = w.rgb[2] = 1.0f;
-            w.A = a0 * ip; w.B = b0 * ip; w.C = c0 * ip; w.D = d0 * ip;
-            if (GRAD) {
-                float gA, gB, gC, gD;
-                w_local_grad(w, a, Ln, gA, gB, gC, gD);
-                cf gm = (x.lobe == LOBE_REFLECT) ? fresnel_R_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip)
-                                                 : fresnel_T_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip);
-                // m = eta (camera outside, reflection) or 1/eta, and the reverse for transmission
-                bool m_is_eta = (x.lobe == LOBE_REFLECT) == x.front;
-                K.g(m.eta_slot, m.eta_off, m_is_eta ? gm.re : -gm.re / (eta * eta));
-            }
-            break;
-        }
-        case LOBE_SHEET: {
-            v3 k = x.wo;
-            v3 t = mk(m.axis[0], m.axis[1], m.axis[2]);
-            v3 xt = normalize(t - k * dot(t, k));
-            rot_cs(k, canon_x(k), xt, w.ci, w.si);
-            rot_cs(k, xt, canon_x(k), w.co, w.so);
-            w.kind = 2;
-            w.rgb[0] = w.rgb[1] = w.rgb[2] = 1.0f;
-            w.A = w.B = 0.5f; w.C = w.D = 0.0f;
-            break;
-        }
-        default:
-            break;
-    }
-}
-
-// ============================================================================ sensor
-// analyzer a applied to a sensor-frame Stokes vector
-DEV void analyzer_apply(int sensor, float theta, int a, const float* v, float* o) {
-    if (sensor == SENSOR_NONE) { o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; return; }
-    float C, S, q;
-    if (sensor == SENSOR_POLARIZER) {
-        C = cosf(2.0f * theta); S = sinf(2.0f * theta);
-        q = 0.5f * (v[0] + C * v[1] + S * v[2]);
-    } else if (a == 0) { C = 1.0f; S = 0.0f; q = 0.5f * (v[0] + v[1]); }
-    else if (a == 1) { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[2]); }
-    else if (a == 2) { C = -1.0f; S = 0.0f; q = 0.5f * (v[0] - v[1]); }
-    else { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[3]); }  // QWP(0) then polarizer at 45 deg
-    o[0] = q; o[1] = C * q; o[2] = S * q; o[3] = 0.0f;
-}
-// row delta^T A_a
-DEV void analyzer_row(int sensor, float theta, int a, const float* dl, float* r) {
-    if (sensor == SENSOR_NONE) { r[0] = dl[0]; r[1] = dl[1]; r[2] = dl[2]; r[3] = dl[3]; return; }
-    float C, S;
-    int kind = 0;
-    if (sensor == SENSOR_POLARIZER) { C = cosf(2.0f * theta); S = sinf(2.0f * theta); }
-    else if (a == 0) { C = 1.0f; S = 0.0f; }
-    else if (a == 1) { C = 0.0f; S = 1.0f; }
-    else if (a == 2) { C = -1.0f; S = 0.0f; }
-    else { C = 0.0f; S = 1.0f; kind = 1; }
-    float q = 0.5f * (dl[0] + C * dl[1] + S * dl[2]);  // output = w q(v), w = (1, C, S, 0)
-    if (kind == 0) { r[0] = q; r[1] = C * q; r[2] = S * q; r[3] = 0.0f; }
-    else { r[0] = q; r[1] = 0.0f; r[2] = 0.0f; r[3] = q; }
-}
-// delta^T (dP(theta)/dtheta) v
-DEV float polarizer_dtheta(float theta, const float* dl, const float* v) {
-    float C = cosf(2.0f * theta), S = sinf(2.0f * theta);
-    float r0 = -S * dl[1] + C * dl[2];
-    float r1 = -S * dl[0] - 2.0f * C * S * dl[1] + (C * C - S * S) * dl[2];
-    float r2 = C * dl[0] + (C * C - S * S) * dl[1] + 2.0f * C * S * dl[2];
-    return r0 * v[0] + r1 * v[1] + r2 * v[2];
-}
-
-// ============================================================================ kernels
-DEV int next_item(int* q) {
-    int v = 0;
-    if (lane_id() == 0) v = atomicAdd(q, 1);
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-DEV void flush_counters(Stats* st, const Counters& c, uint32_t paths) {
-    uint32_t n = wave_sum_u(c.nodes), p = wave_sum_u(c.prims), s = wave_sum_u(c.shadow);
-    uint32_t v = wave_sum_u(c.verts), q = wave_sum_u(paths);
-    if (lane_id() == 0) {
-        atomicAdd(&st->nodes, (unsigned long long)n);
-        atomicAdd(&st->prims, (unsigned long long)p);
-        atomicAdd(&st->shadow_rays, (unsigned long long)s);
-        atomicAdd(&st->vertices, (unsigned long long)v);
-        atomicAdd(&st->paths, (unsigned long long)q);
-    }
-}
-
-// Forward path: returns the sensor-frame Stokes (3 x 4) of one sample.  beta (prefix product)
-// is kept as a shared 4x4 plus an RGB scale, which is exact for every material here.
-DEV void render_path(const KArgs& A, const Call& K, const DevWorld& W, const DevView& V, int px, int py,
-                     uint32_t smp, float* Ls, Counters& cnt, uint64_t* sig_out) {
-    v3 o, d;
-    camera_ray(V, px, py, smp, A.seed, o, d);
-    v3 kc = -d;
-    float Cs, Ss;
-    rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
-    float beta[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
-    float brgb[3] = {1.0f, 1.0f, 1.0f};
-    float Lo[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) Lo[i] = 0.0f;
-    Sig sig{1469598103934665603ull};
-    uint32_t pix = (uint32_t)(py * V.width + px);
-    bool prev_delta = false;
-    for (int b = 1; b <= A.max_depth; ++b) {
-        Hit h;
-        if (!trace<false>(W, o, d, 3.0e38f, h, cnt.nodes, cnt.prims)) { sig.add(0xffffffffu); break; }
-        ++cnt.verts;
-        Vtx x;
-        surface(W, h, o, d, x);
-        vertex_setup<false>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, 0, cnt);
-        sig.add((uint32_t)x.orig); sig.add((uint32_t)x.nee); sig.add((uint32_t)x.lobe);
-        WC w;
-        float E[12];
-        eval_vertex<false>(W, K, x, w, E, nullptr, nullptr);
-        // Lo_c += brgb_c * beta * E_c
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float s = beta[4 * i] * E[4 * c] + beta[4 * i + 1] * E[4 * c + 1] + beta[4 * i + 2] * E[4 * c + 2] +
-                          beta[4 * i + 3] * E[4 * c + 3];
-                Lo[4 * c + i] += brgb[c] * s;
-            }
-        }
-        if (x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) break;
-        // beta <- beta * W (rows of beta times the shared part; RGB scale separately)
-        if (w.kind == 1) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { beta[4 * i + 1] = beta[4 * i + 2] = beta[4 * i + 3] = 0.0f; }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) brgb[c] *= w.rgb[c];
-        } else {
-            WC ws = w;
-            ws.rgb[0] = 1.0f;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float r[4] = {beta[4 * i], beta[4 * i + 1], beta[4 * i + 2], beta[4 * i + 3]}, o4[4];
-                w_row(ws, 0, r, o4);
-                beta[4 * i] = o4[0]; beta[4 * i + 1] = o4[1]; beta[4 * i + 2] = o4[2]; beta[4 * i + 3] = o4[3];
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) brgb[c] *= w.rgb[c];
-        }
-        prev_delta = is_delta(W.mats[x.mat].type);
-        o = spawn(x.p, x.ng, x.wi);
-        d = x.wi;
-    }
-    if (sig_out) *sig_out = sig.h;
-    // rotate into the sensor frame
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float l1 = Lo[4 * c + 1], l2 = Lo[4 * c + 2];
-        Ls[4 * c] = Lo[4 * c];
-        Ls[4 * c + 1] = Cs * l1 + Ss * l2;
-        Ls[4 * c + 2] = -Ss * l1 + Cs * l2;
-        Ls[4 * c + 3] = Lo[4 * c + 3];
-    }
-}
-
-__global__ void __launch_bounds__(BLOCK) k_render(KArgs A) {
-    const int lane = lane_id();
-    Call K{A.table, nullptr};
-    Counters cnt{0, 0, 0, 0};
+// Camera rays of the chunk's paths (masked paths are marked and skipped by the first bounce).
+__global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
+    PathState& S = A.S;
+    const int Q = A.Q;
     uint32_t npaths = 0;
-    while (true) {
-        int item = next_item(A.queue);
-        if (item >= A.n_items) break;
-        const WorkItem it = A.items[item];
-        const DevView& V = A.views[it.view];
-        const DevWorld& W = A.worlds[V.world];
-        int tx = it.tile % V.tiles_x, ty = it.tile / V.tiles_x;
-        int lx = tx * TILE + (lane & 7), ly = ty * TILE + (lane >> 3);
-        bool active = lx < V.crop_w && ly < V.crop_h;
-        float acc[12];
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
+        int64_t g = A.g0 + i;
+        PathId id = path_id(A.views, A.n_views, g);
+        const DevView& V = A.views[id.v];
+        bool live = !(A.mask && !A.mask[g]);
+        v3 o, d;
+        camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
+        st_v3(S.ro, Q, i, o);
+        st_v3(S.rd, Q, i, d);
+        S.info[i] = info_make(0, false, id.v) | (live ? 0 : INFO_DEAD);
+        S.pix[i] = id.pix;
+        S.smp[i] = id.smp;
+        if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
+        if (live) ++npaths;
+    }
+    flush_stats(A.stats, 0, 0, 0, 0, npaths);
+}
+
+// ============================================================================ traversal kernels
+__global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
+    extern __shared__ int lds_stack[];
+    int* stack = lds_stack + threadIdx.x;
+    PathState& S = A.S;
+    const int Q = A.Q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the queues the following shade kernel appends to
+        S.counts[1 - A.qin] = 0;
+        S.counts[2] = 0;
+    }
+    const int* q = A.qin ? S.queue1 : S.queue0;
+    const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    uint32_t nodes = 0, prims = 0;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+        int slot = A.first ? i : q[i];
+        int info = S.info[slot];
+        if (info & INFO_DEAD) continue;
+        int v = info >> 12;
+        const DevWorld& W = A.worlds[A.views[v].world];
+        Hit h;
+        trace<false>(W, ld_v3(S.ro, Q, slot), ld_v3(S.rd, Q, slot), 3.0e38f, h, nodes, prims, stack);
+        S.hprim[slot] = h.prim;
+        S.ht[slot] = h.t; S.hu[slot] = h.u; S.hv[slot] = h.v;
+    }
+    flush_stats(A.stats, nodes, prims, 0, 0, 0);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
+    extern __shared__ int lds_stack[];
+    int* stack = lds_stack + threadIdx.x;
+    PathState& S = A.S;
+    const int Q = A.Q;
+    const int n = S.counts[2];
+    uint32_t nodes = 0, prims = 0, rays = 0;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+        int slot = S.squeue[i];
+        int info = S.info[slot];
+        const DevWorld& W = A.worlds[A.views[info >> 12].world];
+        Hit h;
+        ++rays;
+        bool occ = trace<true>(W, ld_v3(S.so, Q, slot), ld_v3(S.sd, Q, slot), S.stmax[slot], h, nodes, prims, stack);
+        if (MODE == 0) {
+            if (!occ)
 #pragma unroll
-        for (int i = 0; i < 12; ++i) acc[i] = 0.0f;
-        if (active) {
-            int px = V.crop_x0 + lx, py = V.crop_y0 + ly;
-            int64_t pbase = V.path_off + ((int64_t)ly * V.crop_w + lx) * V.spp;
-            for (int s = it.s0; s < it.s1; ++s) {
-                if (A.mask && !A.mask[pbase + s]) { if (A.sig) A.sig[pbase + s] = 0; continue; }
-                float Ls[12];
-                render_path(A, K, W, V, px, py, (uint32_t)s, Ls, cnt, A.sig ? A.sig + pbase + s : nullptr);
-                ++npaths;
+                for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] += S.pend[k * Q + slot];
+        } else {
+            int b = (info & 255) - 1;  // the vertex whose light sample this is
+            float* C = S.cache + (size_t)b * CACHE_WORDS * Q;
+            if (!occ)
 #pragma unroll
-                for (int i = 0; i < 12; ++i) acc[i] += Ls[i];
-            }
-            if (A.out) {
-                float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
-                float inv = 1.0f / (float)V.spp;
-                int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
-                int64_t base = V.out_off + ((int64_t)ly * V.crop_w + lx) * 12;
-                for (int a = 0; a < V.n_analyzers; ++a)
+                for (int k = 0; k < 12; ++k) C[(CW_E + k) * Q + slot] += S.pend[k * Q + slot];
+            uint32_t hw = (uint32_t)__float_as_int(C[CW_HIT * Q + slot]);
+            hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
+            C[CW_HIT * Q + slot] = __int_as_float((int)hw);
+        }
+        if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
+    }
+    flush_stats(A.stats, nodes, prims, rays, 0, 0);
+}
+
+// ============================================================================ shading
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
+    PathState& S = A.S;
+    const int Q = A.Q;
+    Call K{A.table, nullptr};
+    const int* qin = A.qin ? S.queue1 : S.queue0;
+    int* qout = A.qin ? S.queue0 : S.queue1;
+    const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    __shared__ BlockQueue qn, qs;
+    if (threadIdx.x == 0) { qn.n = 0; qs.n = 0; }
+    __syncthreads();
+    uint32_t nverts = 0;
+    for (int bb = blockIdx.x * BLOCK; bb < n; bb += gridDim.x * BLOCK) {
+        int i = bb + threadIdx.x;
+        bool cont = false, shadow = false;
+        int slot = 0;
+        if (i < n) slot = A.first ? i : qin[i];
+        if (i < n && !(S.info[slot] & INFO_DEAD)) {
+            int info = S.info[slot];
+            int nb = info & 255, v = info >> 12;
+            bool prev_delta = (info >> 8) & 1;
+            int64_t g = A.g0 + slot;
+            const uint32_t pix = S.pix[slot], smp = S.smp[slot];
+            const DevView& V = A.views[v];
+            const DevWorld& W = A.worlds[V.world];
+            Hit h;
+            h.prim = S.hprim[slot];
+            h.t = S.ht[slot]; h.u = S.hu[slot]; h.v = S.hv[slot];
+            v3 o = ld_v3(S.ro, Q, slot), d = ld_v3(S.rd, Q, slot);
+            if (h.prim < 0) {
+                if (A.sig) sig_add(A.sig[g], 0xffffffffu);
+                if (MODE == 0 && nb == 0)
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] = 0.0f;
+            } else {
+                int b = nb + 1;
+                ++nverts;
+                Vtx x;
+                surface(W, h, o, d, x);
+                v3 so, sd;
+                float stmax = 0.0f;
+                vertex_setup(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+                if (A.sig) {
+                    uint64_t sg = A.sig[g];
+                    sig_add(sg, (uint32_t)x.orig);
+                    sig_add(sg, (uint32_t)x.lobe);
+                    if (x.nee != NEE_PENDING) sig_add(sg, (uint32_t)x.nee);
+                    A.sig[g] = sg;
+                }
+                WC w;
+                float Ee[12], En[12];
+                eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
+                cont = x.lobe != LOBE_NONE && x.lobe != LOBE_INVALID;
+                shadow = x.nee == NEE_PENDING;
+                if (MODE == 0) {
+                    float beta[16], brgb[3], Lo[12];
+                    if (nb == 0) {  // first vertex: beta = I, no radiance yet
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) beta[k] = (k % 5 == 0) ? 1.0f : 0.0f;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) brgb[c] = 1.0f;
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) Lo[k] = 0.0f;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) beta[k] = S.beta[k * Q + slot];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) brgb[c] = S.beta[(16 + c) * Q + slot];
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) Lo[k] = S.Lo[k * Q + slot];
+                    }
+                    // Lo_c += brgb_c beta Ee_c; the pending next-event part likewise
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        float o4[4];
-                        analyzer_apply(V.sensor, theta, a, acc + 4 * c, o4);
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            if (o4[k] != 0.0f) atomicAdd(A.out + base + a * astride + 4 * c + k, o4[k] * inv);
+                        for (int r = 0; r < 4; ++r) {
+                            float se = beta[4 * r] * Ee[4 * c] + beta[4 * r + 1] * Ee[4 * c + 1] +
+                                       beta[4 * r + 2] * Ee[4 * c + 2] + beta[4 * r + 3] * Ee[4 * c + 3];
+                            Lo[4 * c + r] += brgb[c] * se;
+                            if (shadow) {
+                                float sn = beta[4 * r] * En[4 * c] + beta[4 * r + 1] * En[4 * c + 1] +
+                                           beta[4 * r + 2] * En[4 * c + 2] + beta[4 * r + 3] * En[4 * c + 3];
+                                S.pend[(4 * c + r) * Q + slot] = brgb[c] * sn;
+                            }
+                        }
                     }
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] = Lo[k];
+                    if (cont) {
+                        if (w.kind == 1) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) { beta[4 * r + 1] = beta[4 * r + 2] = beta[4 * r + 3] = 0.0f; }
+                        } else {
+                            WC ws = w;
+                            ws.rgb[0] = 1.0f;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                float row[4] = {beta[4 * r], beta[4 * r + 1], beta[4 * r + 2], beta[4 * r + 3]}, o4[4];
+                                w_row(ws, 0, row, o4);
+                                beta[4 * r] = o4[0]; beta[4 * r + 1] = o4[1]; beta[4 * r + 2] = o4[2]; beta[4 * r + 3] = o4[3];
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) S.beta[k * Q + slot] = beta[k];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) S.beta[(16 + c) * Q + slot] = brgb[c] * w.rgb[c];
+                    }
+                } else {
+                    float* C = S.cache + (size_t)(b - 1) * CACHE_WORDS * Q;
+                    C[0 * Q + slot] = w.rgb[0]; C[1 * Q + slot] = w.rgb[1]; C[2 * Q + slot] = w.rgb[2];
+                    C[3 * Q + slot] = w.A; C[4 * Q + slot] = w.B; C[5 * Q + slot] = w.C; C[6 * Q + slot] = w.D;
+                    C[7 * Q + slot] = w.ci; C[8 * Q + slot] = w.si; C[9 * Q + slot] = w.co; C[10 * Q + slot] = w.so;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) C[(CW_E + k) * Q + slot] = Ee[k];
+                    if (shadow)
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) S.pend[k * Q + slot] = En[k];
+                    bool sphere = __float_as_int(W.prims[3 * h.prim + 1].w) != 0;
+                    C[CW_HIT * Q + slot] = __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29));
+                    C[(CW_HIT + 1) * Q + slot] = sphere ? h.t : h.u;
+                    C[(CW_HIT + 2) * Q + slot] = h.v;
+                }
+                if (shadow) {
+                    st_v3(S.so, Q, slot, so);
+                    st_v3(S.sd, Q, slot, sd);
+                    S.stmax[slot] = stmax;
+                }
+                if (cont) {
+                    st_v3(S.ro, Q, slot, spawn(x.p, x.ng, x.wi));
+                    st_v3(S.rd, Q, slot, x.wi);
+                }
+                S.info[slot] = info_make(b, is_delta(W.mats[x.mat].type), v);
             }
         }
+        bq_push(qn, cont, slot);
+        bq_push(qs, shadow, slot);
+        bq_flush(qn, &S.counts[1 - A.qin], qout, false);
+        bq_flush(qs, &S.counts[2], S.squeue, false);
     }
-    flush_counters(A.stats, cnt, npaths);
+    bq_flush(qn, &S.counts[1 - A.qin], qout, true);
+    bq_flush(qs, &S.counts[2], S.squeue, true);
+    flush_stats(A.stats, 0, 0, 0, nverts, 0);
 }
 
-// ---------------------------------------------------------------------------- backward
-struct CacheRef {
-    float* base;  // this wavefront's cache, word (b, w) of lane l at base[(b * CACHE_WORDS + w) * 64 + l]
-    int lane;
-    DEV float& at(int b, int w) const { return base[((size_t)b * CACHE_WORDS + w) * WAVE + lane]; }
-};
-
-DEV void store_w(const CacheRef& C, int b, const WC& w) {
-    C.at(b, 0) = w.rgb[0]; C.at(b, 1) = w.rgb[1]; C.at(b, 2) = w.rgb[2];
-    C.at(b, 3) = w.A; C.at(b, 4) = w.B; C.at(b, 5) = w.C; C.at(b, 6) = w.D;
-    C.at(b, 7) = w.ci; C.at(b, 8) = w.si; C.at(b, 9) = w.co; C.at(b, 10) = w.so;
-}
-DEV void load_w(const CacheRef& C, int b, int kind, WC& w) {
-    w.rgb[0] = C.at(b, 0); w.rgb[1] = C.at(b, 1); w.rgb[2] = C.at(b, 2);
-    w.A = C.at(b, 3); w.B = C.at(b, 4); w.C = C.at(b, 5); w.D = C.at(b, 6);
-    w.ci = C.at(b, 7); w.si = C.at(b, 8); w.co = C.at(b, 9); w.so = C.at(b, 10);
-    w.kind = kind;
-}
-
-__global__ void __launch_bounds__(BLOCK) k_backward(KArgs A) {
+// ============================================================================ render: pixel reduction
+// Every lane rotates its path's radiance into the sensor frame; the lanes of one pixel (adjacent,
+// samples fastest) are summed by a segmented wavefront scan, and the last lane of each segment
+// applies the analyzers and adds the mean to the image.  A pixel whose samples span two
+// wavefronts or chunks receives several additions.
+__global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
+    if (!A.out) return;  // signature-only runs produce no image
+    PathState& S = A.S;
+    const int Q = A.Q;
+    Call K{A.table, nullptr};
     const int lane = lane_id();
-    const int wave = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
-    Call K{A.table, A.gacc};
-    CacheRef C{A.cache + (size_t)wave * A.max_depth * CACHE_WORDS * WAVE, lane};
-    Counters cnt{0, 0, 0, 0};
-    uint32_t npaths = 0;
-    while (true) {
-        int item = next_item(A.queue);
-        if (item >= A.n_items) break;
-        const WorkItem it = A.items[item];
-        const DevView& V = A.views[it.view];
-        const DevWorld& W = A.worlds[V.world];
-        int tx = it.tile % V.tiles_x, ty = it.tile / V.tiles_x;
-        int lx = tx * TILE + (lane & 7), ly = ty * TILE + (lane >> 3);
-        bool active = lx < V.crop_w && ly < V.crop_h;
-        float gtheta = 0.0f;
-        if (active) {
-            int px = V.crop_x0 + lx, py = V.crop_y0 + ly;
-            int64_t pbase = V.path_off + ((int64_t)ly * V.crop_w + lx) * V.spp;
-            uint32_t pix = (uint32_t)(py * V.width + px);
+    for (int base = blockIdx.x * BLOCK + (threadIdx.x & ~(WAVE - 1)); base < A.n_chunk; base += gridDim.x * BLOCK) {
+        int i = base + lane;
+        bool valid = i < A.n_chunk;
+        int64_t key = -1 - lane;  // distinct per invalid lane
+        float acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
+        PathId id{};
+        if (valid) {
+            int64_t g = A.g0 + i;
+            id = path_id(A.views, A.n_views, g);
+            key = g - id.smp;
+            if (!(S.info[i] & INFO_DEAD)) {
+                const DevView& V = A.views[id.v];
+                v3 o, d;
+                camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
+                v3 kc = -d;
+                float Cs, Ss;
+                rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float l1 = S.Lo[(4 * c + 1) * Q + i], l2 = S.Lo[(4 * c + 2) * Q + i];
+                    acc[4 * c] = S.Lo[(4 * c) * Q + i];
+                    acc[4 * c + 1] = Cs * l1 + Ss * l2;
+                    acc[4 * c + 2] = -Ss * l1 + Cs * l2;
+                    acc[4 * c + 3] = S.Lo[(4 * c + 3) * Q + i];
+                }
+            }
+        }
+        // inclusive segmented scan toward higher lanes
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            int64_t kup = __shfl_up(key, off, WAVE);
+            bool take = lane >= off && kup == key;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                float v = __shfl_up(acc[k], off, WAVE);
+                if (take) acc[k] += v;
+            }
+        }
+        int64_t knext = __shfl_down(key, 1, WAVE);
+        bool tail = valid && (lane == WAVE - 1 || knext != key);
+        if (tail) {
+            const DevView& V = A.views[id.v];
             float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
-            // adjoint of the pixel mean in the sensor frame: a_sens_c = sum_a delta_a,c^T A_a / spp
-            float asens[12], dl[48];
             float inv = 1.0f / (float)V.spp;
             int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
-            int64_t base = V.out_off + ((int64_t)ly * V.crop_w + lx) * 12;
+            int64_t ob = V.out_off + ((int64_t)id.ly * V.crop_w + id.lx) * 12;
+            for (int a = 0; a < V.n_analyzers; ++a)
 #pragma unroll
-            for (int i = 0; i < 12; ++i) asens[i] = 0.0f;
+                for (int c = 0; c < 3; ++c) {
+                    float o4[4];
+                    analyzer_apply(V.sensor, theta, a, acc + 4 * c, o4);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (o4[k] != 0.0f) atomicAdd(A.out + ob + a * astride + 4 * c + k, o4[k] * inv);
+                }
+        }
+    }
+}
+
+// ============================================================================ backward: fold + replay
+__global__ void __launch_bounds__(BLOCK) k_adjoint(WArgs A) {
+    extern __shared__ double lds_grad[];
+    PathState& S = A.S;
+    const int Q = A.Q;
+    Call K{A.table, A.gacc};
+    K.lds_d = lds_grad;
+    K.lds_f = (float*)(lds_grad + A.lds_nd);
+    for (int k = threadIdx.x; k < A.lds_nd; k += BLOCK) K.lds_d[k] = 0.0;
+    for (int k = threadIdx.x; k < A.lds_nf; k += BLOCK) K.lds_f[k] = 0.0f;
+    __syncthreads();
+    for (int base = blockIdx.x * BLOCK + (threadIdx.x & ~(WAVE - 1)); base < A.n_chunk; base += gridDim.x * BLOCK) {
+        int i = base + lane_id();
+        float gtheta = 0.0f;
+        int tkey = -1;
+        if (i < A.n_chunk && !(S.info[i] & INFO_DEAD)) {
+            int64_t g = A.g0 + i;
+            PathId id = path_id(A.views, A.n_views, g);
+            const DevView& V = A.views[id.v];
+            const DevWorld& W = A.worlds[V.world];
+            const int B = S.info[i] & 255;
+            float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
+            // adjoint of the pixel mean in the sensor frame: a_sens_c = sum_a delta_a,c^T A_a / spp
+            float asens[12], dl[12];
+            float inv = 1.0f / (float)V.spp;
+            int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
+            int64_t ob = V.out_off + ((int64_t)id.ly * V.crop_w + id.lx) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) asens[k] = 0.0f;
             for (int a = 0; a < V.n_analyzers; ++a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     float d4[4], r4[4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) d4[k] = A.dout[base + a * astride + 4 * c + k] * inv;
+                    for (int k = 0; k < 4; ++k) d4[k] = A.dout[ob + a * astride + 4 * c + k] * inv;
                     if (a == 0) {
 #pragma unroll
                         for (int k = 0; k < 4; ++k) dl[4 * c + k] = d4[k];
@@ -1034,154 +450,131 @@ __global__ void __launch_bounds__(BLOCK) k_backward(KArgs A) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) asens[4 * c + k] += r4[k];
                 }
-            float Lsum[12];
+            v3 o, d;
+            camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
+            v3 kc = -d;
+            float Cs, Ss;
+            rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
+            // ---- backward fold over the cache: L[b] = E_b + W_b L[b+1], written over E_b
+            float L[12];
 #pragma unroll
-            for (int i = 0; i < 12; ++i) Lsum[i] = 0.0f;
-            for (int s = it.s0; s < it.s1; ++s) {
-                if (A.mask && !A.mask[pbase + s]) continue;
-                ++npaths;
-                uint32_t smp = (uint32_t)s;
-                v3 o0, d0;
-                camera_ray(V, px, py, smp, A.seed, o0, d0);
-                v3 kc = -d0;
-                float Cs, Ss;
-                rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
-                // ---- primal with per-vertex cache (weights, emission + NEE, hit record)
-                int B = 0;
-                {
-                    v3 o = o0, d = d0;
-                    bool prev_delta = false;
-                    for (int b = 1; b <= A.max_depth; ++b) {
-                        Hit h;
-                        if (!trace<false>(W, o, d, 3.0e38f, h, cnt.nodes, cnt.prims)) break;
-                        ++cnt.verts;
-                        Vtx x;
-                        surface(W, h, o, d, x);
-                        vertex_setup<false>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, 0,
-                                            cnt);
-                        WC w;
-                        float E[12];
-                        eval_vertex<false>(W, K, x, w, E, nullptr, nullptr);
-                        store_w(C, b - 1, w);
+            for (int k = 0; k < 12; ++k) L[k] = 0.0f;
+            for (int b = B - 1; b >= 0; --b) {
+                float* C = S.cache + (size_t)b * CACHE_WORDS * Q;
+                WC w;
+                w.rgb[0] = C[0 * Q + i]; w.rgb[1] = C[1 * Q + i]; w.rgb[2] = C[2 * Q + i];
+                w.A = C[3 * Q + i]; w.B = C[4 * Q + i]; w.C = C[5 * Q + i]; w.D = C[6 * Q + i];
+                w.ci = C[7 * Q + i]; w.si = C[8 * Q + i]; w.co = C[9 * Q + i]; w.so = C[10 * Q + i];
+                w.kind = (__float_as_int(C[CW_HIT * Q + i]) >> 29) & 3;
 #pragma unroll
-                        for (int i = 0; i < 12; ++i) C.at(b - 1, CW_E + i) = E[i];
-                        C.at(b - 1, CW_HIT) = __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29));
-                        C.at(b - 1, CW_HIT + 1) = __float_as_int(W.prims[3 * h.prim + 1].w) == 0 ? h.u : h.t;
-                        C.at(b - 1, CW_HIT + 2) = h.v;
-                        B = b;
-                        if (x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) break;
-                        prev_delta = is_delta(W.mats[x.mat].type);
-                        o = spawn(x.p, x.ng, x.wi);
-                        d = x.wi;
+                for (int c = 0; c < 3; ++c) {
+                    float o4[4];
+                    w_apply(w, c, L + 4 * c, o4);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        L[4 * c + k] = C[(CW_E + 4 * c + k) * Q + i] + o4[k];
+                        C[(CW_E + 4 * c + k) * Q + i] = L[4 * c + k];
                     }
                 }
-                // ---- backward fold: L[b] = E_b + W_b L[b+1], stored over E_b
-                float L[12];
-#pragma unroll
-                for (int i = 0; i < 12; ++i) L[i] = 0.0f;
-                for (int b = B - 1; b >= 0; --b) {
-                    int kind = (__float_as_int(C.at(b, CW_HIT)) >> 29) & 3;
-                    WC w;
-                    load_w(C, b, kind, w);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float o4[4];
-                        w_apply(w, c, L + 4 * c, o4);
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            L[4 * c + k] = C.at(b, CW_E + 4 * c + k) + o4[k];
-                            C.at(b, CW_E + 4 * c + k) = L[4 * c + k];
-                        }
-                    }
-                }
-                // sensor-frame suffix radiance of the whole path (for the polarizer angle)
+            }
+            // polarizer-angle term: delta^T (dP/dtheta) R_s L[1]
+            if (V.sensor == SENSOR_POLARIZER) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     float l1 = L[4 * c + 1], l2 = L[4 * c + 2];
-                    Lsum[4 * c] += L[4 * c];
-                    Lsum[4 * c + 1] += Cs * l1 + Ss * l2;
-                    Lsum[4 * c + 2] += -Ss * l1 + Cs * l2;
-                    Lsum[4 * c + 3] += L[4 * c + 3];
+                    float ls[4] = {L[4 * c], Cs * l1 + Ss * l2, -Ss * l1 + Cs * l2, L[4 * c + 3]};
+                    gtheta += polarizer_dtheta(theta, dl + 4 * c, ls);
                 }
-                // ---- adjoint replay from the hit records: a_c = a_sens_c R_s, then per vertex
-                float av[12];
+                tkey = id.v;
+            }
+            // ---- replay from the hit records: a_c = a_sens_c R_s, then vertex by vertex
+            float av[12];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float a1 = asens[4 * c + 1], a2 = asens[4 * c + 2];
+                av[4 * c] = asens[4 * c];
+                av[4 * c + 1] = Cs * a1 - Ss * a2;
+                av[4 * c + 2] = Ss * a1 + Cs * a2;
+                av[4 * c + 3] = asens[4 * c + 3];
+            }
+            bool prev_delta = false;
+            for (int b = 1; b <= B; ++b) {
+                const float* C = S.cache + (size_t)(b - 1) * CACHE_WORDS * Q;
+                uint32_t hw = (uint32_t)__float_as_int(C[CW_HIT * Q + i]);
+                Hit h;
+                h.prim = (int)(hw & ((1u << 26) - 1));
+                int rec_nee = (int)((hw >> 26) & 7);
+                float hu = C[(CW_HIT + 1) * Q + i];
+                h.u = hu; h.t = hu; h.v = C[(CW_HIT + 2) * Q + i];
+                Vtx x;
+                surface(W, h, o, d, x);
+                v3 so, sd;
+                float stmax;
+                vertex_setup(W, K, V, A.seed, id.pix, id.smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+                if (x.nee == NEE_PENDING) x.nee = rec_nee;
+                float Ln[12];
+                if (b < B) {
+                    const float* Cn = S.cache + (size_t)b * CACHE_WORDS * Q;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) Ln[k] = Cn[(CW_E + k) * Q + i];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) Ln[k] = 0.0f;
+                }
+                WC w;
+                float Ee[12], En[12];
+                eval_vertex<true>(W, K, x, w, Ee, En, av, Ln);
+                if (x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) break;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    float a1 = asens[4 * c + 1], a2 = asens[4 * c + 2];
-                    av[4 * c] = asens[4 * c];
-                    av[4 * c + 1] = Cs * a1 - Ss * a2;
-                    av[4 * c + 2] = Ss * a1 + Cs * a2;
-                    av[4 * c + 3] = asens[4 * c + 3];
+                    float o4[4];
+                    w_row(w, c, av + 4 * c, o4);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) av[4 * c + k] = o4[k];
                 }
-                {
-                    v3 o = o0, d = d0;
-                    bool prev_delta = false;
-                    for (int b = 1; b <= B; ++b) {
-                        uint32_t hw = (uint32_t)__float_as_int(C.at(b - 1, CW_HIT));
-                        Hit h;
-                        h.prim = (int)(hw & ((1u << 26) - 1));
-                        int rec_nee = (int)((hw >> 26) & 7);
-                        float hu = C.at(b - 1, CW_HIT + 1);
-                        h.u = hu; h.t = hu; h.v = C.at(b - 1, CW_HIT + 2);
-                        Vtx x;
-                        surface(W, h, o, d, x);
-                        vertex_setup<true>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x,
-                                           rec_nee, cnt);
-                        float Ln[12];
-                        if (b < B) {
-#pragma unroll
-                            for (int i = 0; i < 12; ++i) Ln[i] = C.at(b, CW_E + i);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < 12; ++i) Ln[i] = 0.0f;
-                        }
-                        WC w;
-                        float E[12];
-                        eval_vertex<true>(W, K, x, w, E, av, Ln);
-                        if (x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) break;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            float o4[4];
-                            w_row(w, c, av + 4 * c, o4);
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) av[4 * c + k] = o4[k];
-                        }
-                        prev_delta = is_delta(W.mats[x.mat].type);
-                        o = spawn(x.p, x.ng, x.wi);
-                        d = x.wi;
-                    }
-                }
-            }
-            if (V.sensor == SENSOR_POLARIZER) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) gtheta += polarizer_dtheta(theta, dl + 4 * c, Lsum + 4 * c);
+                prev_delta = is_delta(W.mats[x.mat].type);
+                o = spawn(x.p, x.ng, x.wi);
+                d = x.wi;
             }
         }
-        // one atomic per wavefront for the polarizer angle of this view
-        if (V.sensor == SENSOR_POLARIZER) {
-            float g = wave_sum(gtheta);
-            if (lane == 0) K.g(V.theta_slot, V.theta_off, g);
+        // polarizer angles: one atomic per distinct view in the wavefront
+        bool pending = tkey >= 0;
+        while (__ballot(pending)) {
+            unsigned long long m = __ballot(pending);
+            int leader = __ffsll((long long)m) - 1;
+            int key = __shfl(tkey, leader, WAVE);
+            bool mine = pending && tkey == key;
+            float s = wave_sum(mine ? gtheta : 0.0f);
+            if (lane_id() == leader) K.g(A.views[key].theta_slot, A.views[key].theta_off, s);
+            pending = pending && !mine;
         }
     }
-    flush_counters(A.stats, cnt, npaths);
+    // flush the workgroup accumulators into the global FP64 accumulator
+    __syncthreads();
+    const CallTable* T = A.table;
+    for (int s = 0; s < MAX_SLOTS; ++s) {
+        int od = T->lds_d[s], of = T->lds_f[s];
+        if (od < 0 && of < 0) continue;
+        int64_t go = T->goff[s], n = T->numel[s];
+        for (int64_t k = threadIdx.x; k < n; k += BLOCK) {
+            double v = od >= 0 ? K.lds_d[od + k] : (double)K.lds_f[of + k];
+            if (v != 0.0) unsafeAtomicAdd(A.gacc + go + k, v);
+        }
+    }
 }
 
-// ---------------------------------------------------------------------------- small kernels
-__global__ void k_setup(CallTable tab, CallTable* dst, int* queue, Stats* stats, int reset_stats) {
+// ============================================================================ small kernels
+__global__ void k_setup(CallTable tab, CallTable* dst, Stats* stats, int reset_stats) {
     int i = threadIdx.x;
     if (i < MAX_SLOTS) {
         dst->p[i] = tab.p[i];
         dst->goff[i] = tab.goff[i];
         dst->gout[i] = tab.gout[i];
         dst->numel[i] = tab.numel[i];
+        dst->lds_d[i] = tab.lds_d[i];
+        dst->lds_f[i] = tab.lds_f[i];
     }
-    if (i == 0) {
-        queue[0] = 0;
-        queue[1] = 0;
-        if (reset_stats) {
-            stats->vertices = stats->paths = stats->nodes = stats->prims = stats->shadow_rays = 0ull;
-        }
-    }
+    if (i == 0 && reset_stats) stats->vertices = stats->paths = stats->nodes = stats->prims = stats->shadow_rays = 0ull;
 }
 __global__ void k_fill_f32(float* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1191,7 +584,6 @@ __global__ void k_fill_f64(double* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
 }
-// FP64 accumulators -> user float32 gradient tensors
 __global__ void k_finalize(const CallTable* tab, const double* gacc, int n_slots) {
     for (int s = 0; s < n_slots; ++s) {
         float* out = tab->gout[s];
@@ -1210,38 +602,29 @@ __global__ void k_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t
 }
 
 // ============================================================================ launchers
-hipError_t launch_setup(const CallTable& tab, CallTable* dst, int* queue, Stats* stats, bool reset_stats,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(MAX_SLOTS), 0, s, tab, dst, queue, stats, reset_stats ? 1 : 0);
+static int blocks_for(int64_t n, int cap) {
+    int64_t b = (n + BLOCK - 1) / BLOCK;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+hipError_t launch_setup(const CallTable& tab, CallTable* dst, Stats* stats, bool reset_stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(MAX_SLOTS), 0, s, tab, dst, stats, reset_stats ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n, 4096)), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
-    return hipGetLastError();
-}
-hipError_t launch_render(const KArgs& a, int grid_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_render, dim3(grid_blocks), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
-}
-hipError_t launch_backward(const KArgs& a, int grid_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_backward, dim3(grid_blocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 4096)), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
 hipError_t launch_finalize(const CallTable* tab, const double* gacc, int n_slots, int64_t max_numel, hipStream_t s) {
-    int64_t blocks = (max_numel + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, s, tab, gacc, n_slots);
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(max_numel, 2048)), dim3(BLOCK), 0, s, tab, gacc, n_slots);
     return hipGetLastError();
 }
 hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t s) {
@@ -1249,10 +632,48 @@ hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t
     hipLaunchKernelGGL(k_rng, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, ctr, out, n);
     return hipGetLastError();
 }
-hipError_t occupancy(int* render_blocks_per_cu, int* backward_blocks_per_cu) {
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(render_blocks_per_cu, k_render, BLOCK, 0);
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(backward_blocks_per_cu, k_backward, BLOCK, 0);
+
+// One chunk of paths through every bounce.  mode 0: render, 1: backward.
+hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s) {
+    size_t lds = (size_t)a.stack_cap * BLOCK * sizeof(int);
+    hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, s, a.S.counts);
+    int gb = blocks_for(a.n_chunk, G.other);
+    hipLaunchKernelGGL(k_gen, dim3(gb), dim3(BLOCK), 0, s, a);
+    for (int b = 1; b <= a.max_depth; ++b) {
+        a.qin = (b - 1) & 1;
+        a.first = b == 1;
+        hipLaunchKernelGGL(k_extend, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
+        if (mode == 0) {
+            hipLaunchKernelGGL(k_shade<0>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL(k_shadow<0>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
+        } else {
+            hipLaunchKernelGGL(k_shade<1>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL(k_shadow<1>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
+        }
+    }
+    if (mode == 0) {
+        if (a.out) hipLaunchKernelGGL(k_accum, dim3(gb), dim3(BLOCK), 0, s, a);
+    } else {
+        size_t glds = (size_t)a.lds_nd * sizeof(double) + (size_t)a.lds_nf * sizeof(float);
+        hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
+    int e = 0, sh = 0, ad = 0, ot = 0;
+    size_t lds = (size_t)stack_cap * BLOCK * sizeof(int);
+    hipError_t r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend, BLOCK, lds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1>, BLOCK, 0)) != hipSuccess) return r;
+    size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_adjoint, BLOCK, glds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_gen, BLOCK, 0)) != hipSuccess) return r;
+    G->extend = (e > 0 ? e : 1) * cu;
+    G->shade = (sh > 0 ? sh : 1) * cu;
+    G->adjoint = (ad > 0 ? ad : 1) * cu;
+    G->other = (ot > 0 ? ot : 1) * cu;
+    return hipSuccess;
 }
 
 }  // namespace ppt
