@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--cpu-paths", type=int, default=40000, help="paths in the oracle sample")
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--spp", type=int, default=32)
-    ap.add_argument("--chunk-paths", type=int, default=0)
+    ap.add_argument("--chunk-paths", type=int, default=0, help="0: autotuned (cached per workload)")
+    ap.add_argument("--retune", action="store_true")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -68,12 +71,30 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration} MiB three times")
+        return
     wl = sg.config3(res=args.res, spp=args.spp)
     log(f"[bench] workload {wl.name}: {len(wl.views)} views {args.res}^2 x {args.spp} spp, depth {wl.max_depth}")
-    scene = ppt.Scene(wl.scene.to_blob())
-    plan = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, chunk_paths=args.chunk_paths)
-    info = plan.launch_info()
+    blob = wl.scene.to_blob()
+    scene = ppt.Scene(blob)
     params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
+    chunk = args.chunk_paths
+    tuned = None
+    if chunk == 0:
+        from paper_2607_13265_amd import autotune
+        want0 = [n in wl.grad_slots for n in wl.scene.slot_names]
+        chunk, tuned = autotune.tune(scene, blob, wl.views, wl.max_depth, params, want=want0, flags=wl.flags,
+                                     force=args.retune, log=log)
+        log(f"[bench] autotuned chunk {chunk}: {tuned}")
+    plan = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, chunk_paths=chunk)
+    info = plan.launch_info()
     rng = np.random.default_rng(wl.meta["delta_seed"])
     d = torch.from_numpy(rng.standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
     want = [n in wl.grad_slots for n in wl.scene.slot_names]
@@ -141,14 +162,15 @@ def main():
                                "icosphere scene, render + PRB backward, HIP-graph replay",
                    "views": len(wl.views), "resolution": args.res, "spp": args.spp, "max_depth": wl.max_depth,
                    "vertices_per_step": verts, "paths_per_step": st_r["paths"],
-                   "chunk_paths": info["chunk_paths"], "chunks": info["n_chunks"]},
+                   "chunk_paths": info["chunk_paths"], "chunks": info["n_chunks"],
+                   "autotune_ms": tuned},
     }
 
     # per-view launches on the same paths (view_id keeps the random streams identical)
     if not args.no_per_view:
         plans = []
         for v in range(len(wl.views)):
-            pv = ppt.Plan(scene, wl.views[v:v + 1], wl.max_depth, wl.flags, chunk_paths=args.chunk_paths)
+            pv = ppt.Plan(scene, wl.views[v:v + 1], wl.max_depth, wl.flags, chunk_paths=chunk)
             plans.append(pv)
         outs = [torch.empty(p.image_numel, dtype=torch.float32, device=dev) for p in plans]
         offs = sg.view_offsets(wl.views)

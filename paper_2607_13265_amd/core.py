@@ -93,9 +93,11 @@ class Plan:
         return ws
 
     @staticmethod
-    def _ws_ptr(ws):
+    def _ws_args(ws):
+        """(256-byte aligned device pointer, usable bytes) of a uint8 workspace tensor."""
         p = ws.data_ptr()
-        return p + ((-p) % 256)
+        pad = (-p) % 256
+        return ctypes.c_void_p(p + pad), max(0, ws.numel() * ws.element_size() - pad)
 
     def set_stats(self, enabled: bool):
         """Enable/disable the in-kernel work counters (on by default)."""
@@ -123,10 +125,13 @@ class Plan:
         params = self._params(params)
         if out is None:
             out = torch.empty(self.image_numel, dtype=torch.float32, device=params[0].device)
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != self.image_numel or not out.is_contiguous():
+            raise PPTError("out must be a contiguous float32 device tensor of image_numel entries")
         ws = self.workspace(0, params[0].device) if ws is None else ws
         pt = ptr_table(params)
+        wp, wn = self._ws_args(ws)
         check(lib().ppt_render(self._h, pt, len(params), int(seed) & (2**64 - 1), ctypes.c_void_p(out.data_ptr()),
-                               ctypes.c_void_p(self._ws_ptr(ws)), ws.numel() - 256, _stream(stream)))
+                               wp, wn, _stream(stream)))
         return out
 
     def backward(self, params, seed: int, d_stokes, want=None, grads=None, ws=None, stream=None):
@@ -137,26 +142,30 @@ class Plan:
         if grads is None:
             want = [True] * len(params) if want is None else list(want)
             grads = [torch.empty_like(p) if w else None for p, w in zip(params, want)]
+        if len(grads) != len(params) or any(g is not None and (g.dtype != torch.float32 or not g.is_cuda or
+                                                                g.numel() != p.numel() or not g.is_contiguous())
+                                            for g, p in zip(grads, params)):
+            raise PPTError("grads must match the parameter tensors (float32, contiguous, same sizes)")
         ws = self.workspace(1, params[0].device) if ws is None else ws
         pt, gt = ptr_table(params), ptr_table(grads)
+        wp, wn = self._ws_args(ws)
         check(lib().ppt_backward(self._h, pt, len(params), int(seed) & (2**64 - 1),
-                                 ctypes.c_void_p(d_stokes.data_ptr()), gt, ctypes.c_void_p(self._ws_ptr(ws)),
-                                 ws.numel() - 256, _stream(stream)))
+                                 ctypes.c_void_p(d_stokes.data_ptr()), gt, wp, wn, _stream(stream)))
         return grads
 
     def signatures(self, params, seed: int, ws=None, stream=None):
         params = self._params(params)
         sig = torch.empty(self.num_paths, dtype=torch.int64, device=params[0].device)
         ws = self.workspace(0, params[0].device) if ws is None else ws
+        wp, wn = self._ws_args(ws)
         check(lib().ppt_signatures(self._h, ptr_table(params), len(params), int(seed) & (2**64 - 1),
-                                   ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(self._ws_ptr(ws)),
-                                   ws.numel() - 256, _stream(stream)))
+                                   ctypes.c_void_p(sig.data_ptr()), wp, wn, _stream(stream)))
         return sig
 
     def stats(self, op: int, stream=None):
         ws = self._ws[(op, str(torch.device("cuda", torch.cuda.current_device())))]
         out = (ctypes.c_int64 * 5)()
-        check(lib().ppt_read_stats(ctypes.c_void_p(self._ws_ptr(ws)), out, _stream(stream)))
+        check(lib().ppt_read_stats(self._ws_args(ws)[0], out, _stream(stream)))
         keys = ("vertices", "paths", "nodes", "prim_tests", "shadow_rays")
         return {k: int(out[i]) for i, k in enumerate(keys)}
 

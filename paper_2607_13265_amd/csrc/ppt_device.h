@@ -318,19 +318,60 @@ DEV v3 safe_inv(v3 d) {
 }
 
 // Closest hit (ANY = false) or any hit (ANY = true) with 0 < t < tmax.
-// stack: this thread's slot in a workgroup-shared array, entry k at stack[k * BLOCK]
+// Closest hit (ANY = false) or any hit (ANY = true) with 0 < t < tmax.
+// While-while traversal with speculative leaf postponement (Aila & Laine 2009): a lane that
+// reaches a leaf parks it and keeps descending until every lane of the wavefront still in the
+// node loop holds a leaf; then the wavefront tests primitives together.
+// stack: this thread's slot in a workgroup-shared array, entry k at stack[k * BLOCK].
+DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
+    const float4* pr = prims + 3 * i;
+    float4 A = pr[0], B = pr[1];
+    if (__float_as_int(B.w) == 0) {
+        float4 C = pr[2];
+        v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
+        v3 p = cross(d, e2);
+        float det = dot(e1, p);
+        if (det == 0.0f) return false;
+        float inv = 1.0f / det;
+        v3 s = o - v0;
+        float uu = dot(s, p) * inv;
+        if (uu < 0.0f || uu > 1.0f) return false;
+        v3 q = cross(s, e1);
+        float vv = dot(d, q) * inv;
+        if (vv < 0.0f || uu + vv > 1.0f) return false;
+        float t = dot(e2, q) * inv;
+        if (!(t > 0.0f && t < tb)) return false;
+        tb = t; h.prim = i; h.t = t; h.u = uu; h.v = vv;
+        return true;
+    }
+    v3 oc = o - mk(A.x, A.y, A.z);
+    float r = B.x;
+    float bb = dot(d, oc), cc = dot(oc, oc) - r * r;
+    float disc = bb * bb - cc;
+    if (disc < 0.0f) return false;
+    float sq = sqrtf(disc);
+    float t = -bb - sq;
+    if (!(t > 0.0f)) t = -bb + sq;
+    if (!(t > 0.0f && t < tb)) return false;
+    tb = t; h.prim = i; h.t = t; h.u = 0.0f; h.v = 0.0f;
+    return true;
+}
+
 template <bool ANY>
 DEV bool trace(const DevWorld& W, v3 o, v3 d, float tmax, Hit& h, uint32_t& n_nodes, uint32_t& n_prims,
                 int* stack) {
     h.prim = -1;
     if (W.n_prims == 0) return false;
+    constexpr int DONE = 0x7fffffff;
     v3 id = safe_inv(d);
     v3 ood = mk(o.x * id.x, o.y * id.y, o.z * id.z);
     int sp = 0;
-    int ref = W.root;
+    int ref = W.root;  // >= 0 inner node, < 0 leaf, DONE when the stack is exhausted
+    int leaf = 0;      // parked leaf (< 0) or none
     float tb = tmax;
+    if (ref < 0) { leaf = ref; ref = DONE; }
     while (true) {
-        if (ref >= 0) {
+        while (ref != DONE && ref >= 0) {
             ++n_nodes;
             const float4* nd = W.nodes + 4 * ref;
             float4 q0 = nd[0], q1 = nd[1], q2 = nd[2], q3 = nd[3];
@@ -355,50 +396,28 @@ DEV bool trace(const DevWorld& W, v3 o, v3 d, float tmax, Hit& h, uint32_t& n_no
             } else if (hR) {
                 ref = rR;
             } else {
-                if (sp == 0) break;
-                ref = stack[(--sp) * BLOCK];
+                ref = sp ? stack[(--sp) * BLOCK] : DONE;
             }
-        } else {
-            int enc = ~ref;
+            if (ref < 0 && leaf == 0) {  // park the leaf, keep descending
+                leaf = ref;
+                ref = sp ? stack[(--sp) * BLOCK] : DONE;
+            }
+            if (!__any(leaf == 0)) break;  // every lane in this loop holds a leaf
+        }
+        while (leaf < 0) {
+            int enc = ~leaf;
             int first = enc >> 3, cnt = (enc & 7) + 1;
             for (int k = 0; k < cnt; ++k) {
-                int i = first + k;
                 ++n_prims;
-                const float4* pr = W.prims + 3 * i;
-                float4 A = pr[0], B = pr[1];
-                if (__float_as_int(B.w) == 0) {
-                    float4 C = pr[2];
-                    v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
-                    v3 p = cross(d, e2);
-                    float det = dot(e1, p);
-                    if (det == 0.0f) continue;
-                    float inv = 1.0f / det;
-                    v3 s = o - v0;
-                    float uu = dot(s, p) * inv;
-                    if (uu < 0.0f || uu > 1.0f) continue;
-                    v3 q = cross(s, e1);
-                    float vv = dot(d, q) * inv;
-                    if (vv < 0.0f || uu + vv > 1.0f) continue;
-                    float t = dot(e2, q) * inv;
-                    if (!(t > 0.0f && t < tb)) continue;
-                    tb = t; h.prim = i; h.t = t; h.u = uu; h.v = vv;
-                } else {
-                    v3 oc = o - mk(A.x, A.y, A.z);
-                    float r = B.x;
-                    float bb = dot(d, oc), cc = dot(oc, oc) - r * r;
-                    float disc = bb * bb - cc;
-                    if (disc < 0.0f) continue;
-                    float sq = sqrtf(disc);
-                    float t = -bb - sq;
-                    if (!(t > 0.0f)) t = -bb + sq;
-                    if (!(t > 0.0f && t < tb)) continue;
-                    tb = t; h.prim = i; h.t = t; h.u = 0.0f; h.v = 0.0f;
-                }
-                if (ANY) return true;
+                if (hit_prim(W.prims, first + k, o, d, tb, h) && ANY) return true;
             }
-            if (sp == 0) break;
-            ref = stack[(--sp) * BLOCK];
+            leaf = 0;
+            if (ref < 0) {  // the node loop stopped on a second leaf
+                leaf = ref;
+                ref = sp ? stack[(--sp) * BLOCK] : DONE;
+            }
         }
+        if (ref == DONE) break;
     }
     return h.prim >= 0;
 }

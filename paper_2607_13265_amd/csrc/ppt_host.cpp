@@ -197,7 +197,8 @@ static bool slot_ok(const ppt_scene* s, int32_t slot, int64_t off, int64_t n) {
     return slot >= 0 && slot < (int32_t)s->slot_numel.size() && off >= 0 && n >= 0 && off + n <= s->slot_numel[slot];
 }
 
-static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, WorldHost& wh, int wi) {
+// Parse and validate one world; unless dry, build its BVH and upload it.
+static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, WorldHost& wh, int wi, bool dry) {
     auto need = [&](size_t k) { return (size_t)(end - p) >= k; };
     if (!need(16)) return fail(PPT_EINVAL, "blob truncated (world header)");
     uint32_t cnt[4];
@@ -294,12 +295,16 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
         B.idx[i] = (int)i;
         if (i < nt) {
             const float* v = tv + 9 * i;
+            for (int k = 0; k < 9; ++k)
+                if (!std::isfinite(v[k])) return fail(PPT_EINVAL, "non-finite geometry");
             for (int a = 0; a < 3; ++a) {
                 q.lo[a] = std::min({v[a], v[3 + a], v[6 + a]});
                 q.hi[a] = std::max({v[a], v[3 + a], v[6 + a]});
             }
         } else {
             const float* s = sp + 4 * (i - nt);
+            for (int k = 0; k < 4; ++k)
+                if (!std::isfinite(s[k])) return fail(PPT_EINVAL, "non-finite geometry");
             float r = std::fabs(s[3]);
             for (int a = 0; a < 3; ++a) { q.lo[a] = s[a] - r; q.hi[a] = s[a] + r; }
         }
@@ -308,6 +313,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
             q.c[a] = 0.5f * (q.lo[a] + q.hi[a]);
         }
     }
+    if (dry) return PPT_OK;
     int root_ref = 0;
     std::vector<float4> nodes, prims;
     if (np > 0) {
@@ -457,25 +463,33 @@ int ppt_scene_create(const void* blob, size_t nbytes, ppt_scene** out) {
     if (hdr[3] == 0 || hdr[3] > 4096) return fail(PPT_EINVAL, "bad world count");
     if ((size_t)(end - p) < 4ull * hdr[2]) return fail(PPT_EINVAL, "blob truncated (slots)");
     ppt_scene* sc = new ppt_scene();
-    if (hipGetDevice(&sc->device) != hipSuccess) { delete sc; return fail(PPT_EDEVICE, "no HIP device"); }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, sc->device) != hipSuccess) { delete sc; return fail(PPT_EDEVICE, "device properties"); }
-    sc->cu_count = prop.multiProcessorCount;
     for (uint32_t i = 0; i < hdr[2]; ++i) {
         uint32_t n;
         std::memcpy(&n, p, 4); p += 4;
         sc->slot_numel.push_back(n);
     }
+    // validate every world on the host before any device work
+    const uint8_t* body = p;
+    for (uint32_t w = 0; w < hdr[3]; ++w) {
+        WorldHost tmp;
+        int rc = convert_world(sc, p, end, tmp, (int)w, true);
+        if (rc) { delete sc; return rc; }
+    }
+    if (p != end) { delete sc; return fail(PPT_EINVAL, "trailing bytes after the last world"); }
+    p = body;
+    if (hipGetDevice(&sc->device) != hipSuccess) { delete sc; return fail(PPT_EDEVICE, "no HIP device"); }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, sc->device) != hipSuccess) { delete sc; return fail(PPT_EDEVICE, "device properties"); }
+    sc->cu_count = prop.multiProcessorCount;
     std::vector<DevWorld> dw;
     for (uint32_t w = 0; w < hdr[3]; ++w) {
         WorldHost* wh = new WorldHost();
         sc->worlds.push_back(wh);
-        int rc = convert_world(sc, p, end, *wh, (int)w);
+        int rc = convert_world(sc, p, end, *wh, (int)w, false);
         if (rc) { delete sc; return rc; }
         dw.push_back(wh->dev);
         sc->stack_cap = std::max(sc->stack_cap, wh->bvh_depth + 2);
     }
-    if (p != end) { delete sc; return fail(PPT_EINVAL, "trailing bytes after the last world"); }
     int rc = sc->dev_worlds.upload(dw.data(), dw.size() * sizeof(DevWorld), "world table");
     if (rc) { delete sc; return rc; }
     *out = sc;

@@ -1,0 +1,277 @@
+"""GPU system tests through the C ABI: closed forms on the device, batching, chunking, graph
+replay, edge cases, plan-level errors, the autograd wrapper and full-size sampled parity."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from parity import GRAD_TOL, IMG_TOL, describe, pixel_slices, rel, run
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _ppt():
+    import paper_2607_13265_amd as ppt
+    return ppt
+
+
+def _params(scene):
+    return [torch.from_numpy(p).cuda() for p in scene.params()]
+
+
+# ----------------------------------------------------------------------------- closed forms on the GPU
+def test_gpu_halving_malus_chain():
+    ppt = _ppt()
+    for sheets, theta, expect in [((), 0.7, 5.0), ((1.1,), 0.3, 5.0 * np.cos(0.3 - 1.1) ** 2)]:
+        sc, s_th = sg.emitter_wall_scene(le=10.0, sheets=sheets)
+        p = sc.params(); p[s_th][0] = theta
+        v = np.asarray([sg.make_view(0, 8, 8, 2, (0, 0, 0), (0, 0, -1), (0, 1, 0), 0.01, sg.SENSOR_POLARIZER, s_th)],
+                       sg.VIEW_DTYPE)
+        plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, 4)
+        img = plan.render([torch.from_numpy(x).cuda() for x in p], 3).cpu().numpy().reshape(-1, 3, 4)
+        assert np.allclose(img[..., 0], expect, rtol=2e-5)
+    n = 8
+    angles = [0.0] + [k * np.pi / (2 * n) for k in range(1, n + 1)]
+    sc, _ = sg.emitter_wall_scene(le=10.0, sheets=tuple(reversed(angles)), z_light=-(n + 6.0))
+    v = np.asarray([sg.make_view(0, 4, 4, 1, (0, 0, 0), (0, 0, -1), (0, 1, 0), 0.01, sg.SENSOR_NONE)], sg.VIEW_DTYPE)
+    plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, n + 3)
+    img = plan.render(_params(sc), 3).cpu().numpy().reshape(-1, 3, 4)
+    e = 5.0 * np.cos(np.pi / (2 * n)) ** (2 * n)
+    assert np.allclose(img[..., 0], e, rtol=2e-5) and np.allclose(img[..., 1], -e, rtol=2e-5)
+
+
+@pytest.mark.parametrize("depth", [1, 4])
+def test_gpu_furnace_value_and_gradient(depth):
+    ppt = _ppt()
+    sc, _ = sg.furnace_scene(rho=0.6, le=1.5)
+    rho = float(sc.slot_values[sc.slot("albedo")][0]); le = float(sc.slot_values[sc.slot("emission")][0])
+    v = np.asarray([sg.make_view(0, 16, 8, 4, (0.1, 0.2, 0.3), (1, 0, 0), (0, 1, 0), 60.0, sg.SENSOR_NONE)], sg.VIEW_DTYPE)
+    plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, depth, ppt.FLAG_NO_NEE)
+    params = _params(sc)
+    img = plan.render(params, 9).cpu().numpy().reshape(-1, 3, 4)
+    expect = le * sum(rho ** k for k in range(depth))
+    assert np.allclose(img[..., 0], expect, rtol=1e-5) and np.allclose(img[..., 1:], 0, atol=1e-5)
+    d = np.zeros((img.shape[0], 3, 4), np.float32); d[..., 0] = 1
+    g = plan.backward(params, 9, torch.from_numpy(d.ravel()).cuda())
+    g_expect = le * sum(k * rho ** (k - 1) for k in range(1, depth)) * img.shape[0]
+    assert np.allclose(g[sc.slot("albedo")].cpu().numpy(), g_expect, rtol=1e-5, atol=1e-6)
+
+
+# ----------------------------------------------------------------------------- batching / chunking / graphs
+def _small_batch(n_views=6, res=24, spp=4):
+    wl = sg.config3(res=res, spp=spp, n_angles=3, n_poses=2)
+    wl.views = wl.views[:n_views]
+    return wl
+
+
+def test_batched_equals_per_view_and_chunk_invariance():
+    ppt = _ppt()
+    wl = _small_batch()
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = _params(wl.scene)
+    plan = ppt.Plan(scene, wl.views, wl.max_depth)
+    img = plan.render(params, 11)
+    d = torch.randn(plan.image_numel, device="cuda")
+    g = plan.backward(params, 11, d)
+    offs = sg.view_offsets(wl.views)
+    gsum = [torch.zeros_like(p) for p in params]
+    for v in range(len(wl.views)):
+        pv = ppt.Plan(scene, wl.views[v:v + 1], wl.max_depth)
+        o = int(offs[v])
+        iv = pv.render(params, 11)
+        assert torch.equal(iv, img[o:o + pv.image_numel])
+        gv = pv.backward(params, 11, d[o:o + pv.image_numel].contiguous())
+        for a, b in zip(gsum, gv):
+            a += b
+    for a, b in zip(gsum, g):
+        assert rel(a.cpu().numpy(), b.cpu().numpy(), floor=1e-12) < 1e-5
+    # a chunk size that splits pixels between chunks gives the same image and gradients
+    pc = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=1000)
+    assert pc.launch_info()["n_chunks"] > 1
+    assert rel(pc.render(params, 11).cpu().numpy(), img.cpu().numpy()) < 1e-6
+    for a, b in zip(pc.backward(params, 11, d), g):
+        assert rel(a.cpu().numpy(), b.cpu().numpy(), floor=1e-12) < 1e-5
+
+
+def test_graph_replay_matches_eager():
+    ppt = _ppt()
+    wl = _small_batch()
+    plan = ppt.Plan(ppt.Scene(wl.scene.to_blob()), wl.views, wl.max_depth)
+    params = _params(wl.scene)
+    d = torch.randn(plan.image_numel, device="cuda")
+    out = torch.empty(plan.image_numel, device="cuda")
+    grads = [torch.empty_like(p) for p in params]
+    ws0, ws1 = plan.workspace(0), plan.workspace(1)
+
+    def step():
+        plan.render(params, 5, out=out, ws=ws0)
+        plan.backward(params, 5, d, grads=grads, ws=ws1)
+
+    step()
+    torch.cuda.synchronize()
+    ref_img = out.clone()
+    ref_g = [x.clone() for x in grads]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for r in range(3):
+        out.zero_()
+        for x in grads:
+            x.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_img), r
+        for a, b in zip(grads, ref_g):
+            assert rel(a.cpu().numpy(), b.cpu().numpy(), floor=1e-12) < 1e-6
+        _ = plan.render(params, 6)  # eager work between replays
+        torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------------------------- edge cases (parity)
+def _check(res, gate=None):
+    print(describe(res))
+    assert res["divergent"] <= 0.01 * res["n_paths"]
+    assert res["img_rel"] <= IMG_TOL
+    for k, v in res.get("grad_rel", {}).items():
+        if gate is None or k in gate:
+            assert v <= GRAD_TOL, (k, v)
+    for k, v in res.get("pixel_grad_rel", {}).items():
+        assert v <= GRAD_TOL, (k, v)
+
+
+def test_edge_ragged_spp1_depth1_empty_view():
+    wl = sg.config2()
+    v0 = sg.crop_views(wl.views, 70, 90, 13, 7)
+    v0["spp"] = 1
+    v1 = sg.crop_views(wl.views, 10, 10, 0, 5)  # empty window
+    v1["view_id"] = 1
+    v2 = sg.crop_views(wl.views, 120, 100, 9, 9)
+    v2["spp"] = 3; v2["view_id"] = 2
+    wl.views = np.concatenate([v0, v1, v2])
+    _check(run(wl, pixel_grad_slots=("theta",)), gate=("albedo_tex", "light_Le"))
+    wl.max_depth = 1
+    _check(run(wl), gate=("albedo_tex", "light_Le", "theta"))
+
+
+def test_edge_no_nee_and_sensor_modes():
+    wl = sg.config1()
+    wl.flags = sg.FLAG_NO_NEE
+    wl.views["spp"] = 16
+    _check(run(wl, pixel_grad_slots=("theta", "ior")), gate=("albedo", "light_Le"))
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 100, 120, 10, 10)
+    wl.views["sensor"] = sg.SENSOR_ANALYZER4
+    wl.views["spp"] = 16
+    _check(run(wl, pixel_grad_slots=("roughness",)), gate=("albedo_tex", "light_Le"))
+    wl.views["sensor"] = sg.SENSOR_NONE
+    _check(run(wl, pixel_grad_slots=("cond_k",)), gate=("albedo_tex", "light_Le"))
+
+
+# ----------------------------------------------------------------------------- errors
+def test_plan_and_call_errors():
+    ppt = _ppt()
+    wl = sg.config1()
+    scene = ppt.Scene(wl.scene.to_blob())
+    bad = wl.views.copy(); bad["crop_w"] = 40  # window outside the image
+    with pytest.raises(ppt.PPTError, match="EINVAL"):
+        ppt.Plan(scene, bad, 3)
+    bad = wl.views.copy(); bad["theta_slot"] = 9
+    with pytest.raises(ppt.PPTError, match="EINVAL"):
+        ppt.Plan(scene, bad, 3)
+    for depth in (0, 65):
+        with pytest.raises(ppt.PPTError, match="EUNSUPPORTED"):
+            ppt.Plan(scene, wl.views, depth)
+    plan = ppt.Plan(scene, wl.views, 3)
+    params = _params(wl.scene)
+    with pytest.raises(ppt.PPTError):
+        plan.render(params[:-1], 1)
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ppt.PPTError, match="workspace"):
+        plan.render(params, 1, ws=small)
+
+
+# ----------------------------------------------------------------------------- autograd
+def test_autograd_function_matches_backward():
+    ppt = _ppt()
+    wl = sg.config1()
+    plan = ppt.Plan(ppt.Scene(wl.scene.to_blob()), wl.views, wl.max_depth)
+    params = [p.clone().requires_grad_(True) for p in _params(wl.scene)]
+    target = plan.render([p.detach() for p in params], 1234)
+    img = ppt.render(plan, params, wl.seed)
+    loss = ((img - target) ** 2).sum()
+    loss.backward()
+    d = (2 * (img.detach() - target)).contiguous()
+    ref = plan.backward([p.detach() for p in params], wl.seed, d)
+    for p, r in zip(params, ref):
+        assert torch.allclose(p.grad, r, rtol=1e-5, atol=1e-7)
+
+
+# ----------------------------------------------------------------------------- full size, sampled
+def test_full_size_batched_sampled_parity():
+    """The 128-view configuration at full size in the launch configuration the benchmark times,
+    checked on sampled pixel windows (the oracle computes them one by one; dL/dI is zero outside
+    the windows, so the gradient is exactly theirs)."""
+    ppt = _ppt()
+    wl = sg.config3()
+    scene = ppt.Scene(wl.scene.to_blob())
+    plan = ppt.Plan(scene, wl.views, wl.max_depth)
+    params = _params(wl.scene)
+    picks = [(0, 56, 60), (45, 64, 40), (97, 30, 80), (127, 90, 64)]  # (view, x0, y0) of 4x4 windows
+    osc = oracle.OracleScene.from_scene(wl.scene)
+    p64 = [p.astype(np.float64) for p in wl.scene.params()]
+    sub = np.concatenate([sg.crop_views(wl.views[v:v + 1], x0, y0, 4, 4) for v, x0, y0 in picks])
+    sig_o = osc.run(p64, sub, wl.max_depth, wl.seed, want_sig=True, want_image=False)["sig"]
+    # signatures of the same paths from the full launch
+    sig_full = plan.signatures(params, wl.seed).cpu().numpy().view(np.uint64)
+    spp = int(wl.views["spp"][0]); W = int(wl.views["width"][0])
+    idx = []
+    for v, x0, y0 in picks:
+        base = v * W * W * spp
+        for y in range(y0, y0 + 4):
+            for x in range(x0, x0 + 4):
+                idx.extend(base + (y * W + x) * spp + np.arange(spp))
+    idx = np.asarray(idx)
+    agree = sig_full[idx] == sig_o
+    mask_full = np.ones(plan.num_paths, np.uint8)
+    mask_full[idx[~agree]] = 0
+    plan.set_path_mask(torch.from_numpy(mask_full).cuda())
+    img = plan.render(params, wl.seed).cpu().numpy()
+    ref = osc.run(p64, sub, wl.max_depth, wl.seed, mask=agree.astype(np.uint8))
+    offs = sg.view_offsets(wl.views)
+    got = []
+    for v, x0, y0 in picks:
+        blk = img[int(offs[v]):int(offs[v]) + W * W * 12].reshape(W, W, 12)
+        got.append(blk[y0:y0 + 4, x0:x0 + 4].ravel())
+    got = np.concatenate(got)
+    print("divergent", int((~agree).sum()), "of", agree.size, "image rel", rel(got, ref["image"]))
+    assert (~agree).sum() <= 0.01 * agree.size
+    assert rel(got, ref["image"]) <= IMG_TOL
+    # gradients of the windows only
+    d_sub = np.random.default_rng(3).normal(size=ref["image"].size).astype(np.float32)
+    d_full = np.zeros(plan.image_numel, np.float32)
+    k = 0
+    for v, x0, y0 in picks:
+        blk = d_full[int(offs[v]):int(offs[v]) + W * W * 12].reshape(W, W, 12)
+        blk[y0:y0 + 4, x0:x0 + 4] = d_sub[k:k + 4 * 4 * 12].reshape(4, 4, 12)
+        k += 4 * 4 * 12
+    g = plan.backward(params, wl.seed, torch.from_numpy(d_full).cuda())
+    gr = osc.run(p64, sub, wl.max_depth, wl.seed, mode=oracle.MODE_TAPE_AD, d_image=d_sub.astype(np.float64),
+                 mask=agree.astype(np.uint8))["grads"]
+    s = wl.scene.slot
+    for name in ("albedo_tex", "light_Le"):
+        r = rel(g[s(name)].cpu().numpy(), gr[s(name)], floor=1e-12)
+        print(name, r)
+        assert r <= GRAD_TOL
