@@ -27,12 +27,52 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpath-vertices/s fwd+PRB adjoint; batched vs per-view launch, grad rel.err≤1e-3"
 
 # Algorithmic FP32 operations (an FMA counts 2) per unit of work, read off the kernel source;
-# see the design notes for the itemisation.
-FLOP_NODE = 47      # one two-box BVH node test
-FLOP_PRIM = 52      # one Moller-Trumbore triangle test
-FLOP_VERT_FWD = 450     # shading of one vertex in the render kernel
-FLOP_VERT_BWD = 1400    # primal shading + cache + fold + replay with vector-Jacobian products
-PEAK_FP32_TFLOPS = 157.3  # MI355X fp32 vector peak (256 CU x 2.4 GHz x 64 lanes x FMA x packed)
+# the design notes itemise them.
+FLOP_NODE = 47          # one two-box BVH node test
+FLOP_PRIM = 52          # one Moller-Trumbore triangle test
+FLOP_SHADE = 450        # one vertex in the shading kernel (sampling, Fresnel/GGX weight, next-event setup)
+FLOP_REPLAY = 950       # one vertex of the adjoint replay (re-evaluation + vector-Jacobian products)
+BYTES_FOLD_VERTEX = 144  # fold: 24 cache words read + 12 written back per vertex
+BYTES_FOLD_PATH = 84     # fold: keys read, adjoint rows + camera ray written per folded path
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 64 lanes x FMA x packed)
+PEAK_HBM_GBS = 8000.0
+# files whose content decides whether stored hardware counters still describe the kernels
+KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_device.h",
+                  "paper_2607_13265_amd/csrc/ppt_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batched128.md")
+KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "shadow": "ppt::k_shadow",
+                 "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, chunk: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when there is
+    none for this kernel and chunk size or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("    ") and ":" in line:
+                k, v = line.strip().split(":", 1)
+                kv.setdefault(k.strip(), []).append(v.strip())
+    try:
+        if kv["source_digest"][0] != kernel_source_digest() or int(kv["chunk_paths"][0]) != chunk:
+            return None
+        for name, val in zip(kv["kernel"], kv["traffic_bytes_per_launch"]):
+            if name == kernel:
+                return float(val)
+    except (KeyError, ValueError, IndexError):
+        return None
+    return None
 
 
 def parse():
@@ -43,7 +83,8 @@ def parse():
     ap.add_argument("--per-view-steps", type=int, default=2)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-paths", type=int, default=40000, help="paths in the oracle sample")
+    ap.add_argument("--cpu-views", type=int, default=32, help="full views in the oracle sample")
+    ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--spp", type=int, default=32)
     ap.add_argument("--chunk-paths", type=int, default=0, help="0: autotuned (cached per workload)")
@@ -198,25 +239,58 @@ def main():
         result["speedup_batched_vs_per_view"] = round(ms_pv / ms_step, 3)
         log(f"[bench] per-view: {ms_pv:.2f} ms/step, image rel diff {img_rel:.2e}")
 
-    # roofline of the dominant kernel (backward), algorithmic FLOPs from in-kernel counters
-    flops_b = FLOP_NODE * st_b["nodes"] + FLOP_PRIM * st_b["prim_tests"] + FLOP_VERT_BWD * st_b["vertices"]
-    flops_r = FLOP_NODE * st_r["nodes"] + FLOP_PRIM * st_r["prim_tests"] + FLOP_VERT_FWD * st_r["vertices"]
-    ach_b = flops_b / (ms_b * 1e-3) / 1e12
-    result["roofline"] = {"kernel": "k_backward", "bound": "alu", "achieved": round(ach_b, 3),
-                          "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(ach_b / PEAK_FP32_TFLOPS, 4),
-                          "traffic": None, "kernel_ms": round(ms_b, 3), "algorithmic_tflop_per_launch":
-                          round(flops_b / 1e12, 4),
-                          "render": {"achieved": round(flops_r / (ms_r * 1e-3) / 1e12, 3), "kernel_ms": round(ms_r, 3)},
-                          "counters_backward": st_b}
+    # per-kernel HIP-event timing on the launch stream (eager steps right after the timed region)
+    plan.set_timing(True)
+    fam_ms, fam_n = {}, {}
+    for _ in range(max(1, args.timing_steps)):
+        step()
+        for op in (0, 1):
+            for f, (ms, n) in plan.kernel_times(op).items():
+                fam_ms[f] = fam_ms.get(f, 0.0) + ms
+                fam_n[f] = fam_n.get(f, 0) + n
+    plan.set_timing(False)
+    reps = max(1, args.timing_steps)
+    per_step = {f: fam_ms[f] / reps for f in fam_ms if fam_n[f]}
+    launches = {f: fam_n[f] // reps for f in fam_ms if fam_n[f]}
+    log("[bench] per-kernel ms/step: " + ", ".join(f"{f} {per_step[f]:.2f} ({launches[f]})" for f in per_step))
 
-    # CPU baseline: the FP64 oracle (render + cached-suffix replay) on a bounded sample
+    # algorithmic work per step of every family, from the in-kernel counters
+    st = {k: st_r[k] + st_b[k] for k in st_r}
+    work = {
+        "extend": ("alu", FLOP_NODE * st["nodes"] + FLOP_PRIM * st["prim_tests"]),
+        "shadow": ("alu", FLOP_NODE * st["shadow_nodes"] + FLOP_PRIM * st["shadow_prim_tests"]),
+        "shade": ("alu", FLOP_SHADE * st["vertices"]),
+        "replay": ("alu", FLOP_REPLAY * st_b["vertices"]),
+        "fold": ("hbm", BYTES_FOLD_VERTEX * st_b["vertices"] + BYTES_FOLD_PATH * st_b["paths"]),
+    }
+    fams = {}
+    for f, (bound, amount) in work.items():
+        if f not in per_step:
+            continue
+        avg_ms = per_step[f] / launches[f]
+        per_launch = amount / launches[f]
+        if bound == "alu":
+            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, PEAK_FP32_TFLOPS, "TFLOP/s"
+        else:
+            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
+        fams[f] = {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                   "frac": round(ach / peak, 4), "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches[f],
+                   "ms_per_step": round(per_step[f], 3), "work_per_launch": per_launch}
+    dom = max(fams, key=lambda f: fams[f]["ms_per_step"])
+    D = fams[dom]
+    result["roofline"] = {"bound": D["bound"], "achieved": D["achieved"], "peak": D["peak"], "unit": D["unit"],
+                          "frac": D["frac"], "traffic": stored_traffic(KERNEL_SYMBOL[dom], info["chunk_paths"]),
+                          "kernel": KERNEL_SYMBOL[dom], "avg_launch_ms": D["avg_launch_ms"],
+                          "launches_per_step": D["launches_per_step"],
+                          "algorithmic_per_launch": D["work_per_launch"],
+                          "kernels": {KERNEL_SYMBOL[f]: v for f, v in fams.items()},
+                          "counters": {"render": st_r, "backward": st_b}}
+
+    # CPU baseline: the FP64 oracle (render + cached-suffix replay) on a bounded sample of whole views
     if not args.no_cpu:
         import oracle
-        nthreads = os.cpu_count() or 1
-        sample_views = sg.crop_views(wl.views[:4], 0, 0, args.res, args.res)
-        npix = max(1, args.cpu_paths // (4 * args.spp))
-        side = max(1, int(np.sqrt(npix)))
-        sample_views = sg.crop_views(wl.views[:4], args.res // 2 - side // 2, args.res // 2 - side // 2, side, side)
+        nthreads = min(16, os.cpu_count() or 1)
+        sample_views = wl.views[:max(1, min(args.cpu_views, len(wl.views)))]
         osc = oracle.OracleScene.from_scene(wl.scene)
         p64 = [p.astype(np.float64) for p in wl.scene.params()]
         dd = np.random.default_rng(1).standard_normal(sg.image_numel(sample_views))
@@ -227,9 +301,10 @@ def main():
         tc = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(r["n_vertices"] / tc / 1e6, 4), "unit": "Mpath-vertices/s",
                                   "cores": nthreads, "kind": "oracle",
-                                  "sample": f"4 views x {side}x{side} central pixels x {args.spp} spp, depth "
-                                            f"{wl.max_depth} ({r['n_paths']} paths, {r['n_vertices']} vertices), "
-                                            f"FP64 render + cached-suffix replay, {tc:.1f} s"}
+                                  "sample": f"{len(sample_views)} of the {len(wl.views)} views, whole "
+                                            f"{args.res}x{args.res} images x {args.spp} spp, depth {wl.max_depth} "
+                                            f"({r['n_paths']} paths, {r['n_vertices']} vertices): FP64 render + "
+                                            f"cached-suffix replay, {tc:.1f} s"}
         log(f"[bench] cpu oracle: {result['cpu_baseline']}")
 
     line = json.dumps(result)

@@ -146,11 +146,25 @@ int ppt_signatures(const ppt_plan* plan, const float* const* params, int32_t n_p
                    uint64_t* sig_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Work counters of the last render/backward call made with a workspace: out[0] path vertices,
- * [1] paths, [2] BVH nodes visited, [3] primitive tests, [4] shadow rays.  Collected while the
- * plan's counters are enabled (the default; ppt_plan_set_stats), else left at zero.
- * Synchronizes the stream.  ws: device workspace; out: host, 5 entries. */
+ * [1] paths, [2] BVH nodes visited by closest-hit rays, [3] their primitive tests, [4] shadow
+ * (next-event) rays, [5] closest-hit rays, [6] BVH nodes visited by shadow rays, [7] their
+ * primitive tests.  Collected while the plan's counters are enabled (the default;
+ * ppt_plan_set_stats), else left at zero.  Synchronizes the stream.  ws: device workspace;
+ * out: host, 8 entries. */
 int ppt_plan_set_stats(ppt_plan* plan, int32_t enabled);
 int ppt_read_stats(const void* ws, int64_t* out, void* stream);
+
+/* Per-kernel event timing (diagnostics).  While enabled, every render/backward call on the plan
+ * records a HIP event on its stream before each kernel launch and one after its last launch.
+ * ppt_plan_kernel_times waits for the most recent such call of `op` (0 render, 1 backward) and
+ * writes, for kernel family k < n, the summed time between an event and the next (ms[k], in
+ * milliseconds) and the number of launches (launches[k]).  Families: 0 camera rays,
+ * 1 closest-hit traversal, 2 shading, 3 shadow rays, 4 pixel reduction, 5 suffix fold,
+ * 6 adjoint replay, 7 setup / clearing / finalization.  Enabling or disabling clears the
+ * records.  Not for use under stream capture; calls on one plan must not overlap while
+ * enabled.  Errors: PPT_EINVAL when no timed call of `op` was made, PPT_EDEVICE on HIP errors. */
+int ppt_plan_set_timing(ppt_plan* plan, int32_t enabled);
+int ppt_plan_kernel_times(const ppt_plan* plan, int32_t op, double* ms, int32_t* launches, int32_t n);
 
 /* Philox4x32-10 (Salmon et al. 2011) on n counters: ctr and out are device arrays of n x 4
  * uint32; key = (seed low 32 bits, seed high 32 bits). */

@@ -26,6 +26,8 @@ SIGNATURES = {
     "ppt_plan_workspace_bytes": (_sz, [_vp, _i32]),
     "ppt_plan_set_path_mask": (_i32, [_vp, _vp]),
     "ppt_plan_set_stats": (_i32, [_vp, _i32]),
+    "ppt_plan_set_timing": (_i32, [_vp, _i32]),
+    "ppt_plan_kernel_times": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "ppt_render": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),
     "ppt_backward": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _vp, _sz, _vp]),
     "ppt_signatures": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),

@@ -19,6 +19,12 @@ VIEW_DTYPE = np.dtype([
 ])
 
 
+# counters of ppt_read_stats and kernel families of ppt_plan_kernel_times, in ABI order
+STAT_KEYS = ("vertices", "paths", "nodes", "prim_tests", "shadow_rays", "rays", "shadow_nodes",
+             "shadow_prim_tests")
+KERNEL_FAMILIES = ("camera", "extend", "shade", "shadow", "accum", "fold", "replay", "other")
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
@@ -103,6 +109,18 @@ class Plan:
         """Enable/disable the in-kernel work counters (on by default)."""
         check(lib().ppt_plan_set_stats(self._h, 1 if enabled else 0))
 
+    def set_timing(self, enabled: bool):
+        """Enable/disable per-kernel HIP-event timing of the plan's calls (diagnostics; not under capture)."""
+        check(lib().ppt_plan_set_timing(self._h, 1 if enabled else 0))
+
+    def kernel_times(self, op: int):
+        """Per kernel family of the most recent timed call of op (0 render, 1 backward):
+        {family: (milliseconds, launches)}; waits for that call to finish."""
+        ms = (ctypes.c_double * len(KERNEL_FAMILIES))()
+        n = (ctypes.c_int32 * len(KERNEL_FAMILIES))()
+        check(lib().ppt_plan_kernel_times(self._h, int(op), ms, n, len(KERNEL_FAMILIES)))
+        return {f: (float(ms[i]), int(n[i])) for i, f in enumerate(KERNEL_FAMILIES)}
+
     def set_path_mask(self, mask):
         """Optional per-path mask (uint8 device tensor of num_paths entries) or None."""
         if mask is not None:
@@ -164,10 +182,9 @@ class Plan:
 
     def stats(self, op: int, stream=None):
         ws = self._ws[(op, str(torch.device("cuda", torch.cuda.current_device())))]
-        out = (ctypes.c_int64 * 5)()
+        out = (ctypes.c_int64 * len(STAT_KEYS))()
         check(lib().ppt_read_stats(self._ws_args(ws)[0], out, _stream(stream)))
-        keys = ("vertices", "paths", "nodes", "prim_tests", "shadow_rays")
-        return {k: int(out[i]) for i, k in enumerate(keys)}
+        return {k: int(out[i]) for i, k in enumerate(STAT_KEYS)}
 
 
 def debug_rng(seed: int, ctr):

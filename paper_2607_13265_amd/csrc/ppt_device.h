@@ -82,6 +82,12 @@ DEV uint32_t wave_sum_u(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
 }
+// maximum over the wavefront, returned wave-uniform (every lane must be active)
+DEV int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    return __builtin_amdgcn_readfirstlane(v);
+}
 
 // ============================================================================ frames
 // Orthonormal basis (x, y, n) of Duff et al. 2017.

@@ -19,7 +19,7 @@ hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_finalize(const CallTable* tab, const double* gacc, int n_slots, int64_t max_numel, hipStream_t s);
 hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t s);
-hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s);
+hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M);
 hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G);
 }  // namespace ppt
 
@@ -178,6 +178,29 @@ struct ppt_scene {
     ~ppt_scene() { for (auto* w : worlds) delete w; }
 };
 
+// Optional event timing of the launches of one call (diagnostics): an event before every kernel
+// launch and one after the last, with the family of the kernel each interval belongs to.
+struct KTimer {
+    std::vector<hipEvent_t> ev;  // pool, grown on demand
+    std::vector<int> fam;
+    size_t n = 0;
+    bool failed = false;
+    ~KTimer() { for (hipEvent_t e : ev) (void)hipEventDestroy(e); }
+    void begin() { n = 0; fam.clear(); failed = false; }
+    void mark(int family, hipStream_t s) {
+        if (failed) return;
+        if (n == ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { failed = true; return; }
+            ev.push_back(e);
+        }
+        if (hipEventRecord(ev[n], s) != hipSuccess) { failed = true; return; }
+        fam.push_back(family);
+        ++n;
+    }
+    static void mark_fn(void* ctx, int family, hipStream_t s) { ((KTimer*)ctx)->mark(family, s); }
+};
+
 struct ppt_plan {
     const ppt_scene* scene = nullptr;
     std::vector<ppt_view> views;
@@ -191,6 +214,8 @@ struct ppt_plan {
     LaunchGrid grid{1, 1, 1, 1};
     const uint8_t* mask = nullptr;
     bool stats = true;
+    bool timing = false;
+    mutable KTimer timer[2];  // most recent render / backward call while timing is enabled
 };
 
 static bool slot_ok(const ppt_scene* s, int32_t slot, int64_t off, int64_t n) {
@@ -415,7 +440,7 @@ static WsLayout ws_layout(const ppt_plan* p, int op) {
     auto take = [&](size_t bytes) { size_t r = at; at = align256(at + bytes); return r; };
     L.table = take(sizeof(CallTable));
     L.stats = take(sizeof(Stats));
-    L.counts = take(16);
+    L.counts = take(32);
     L.ro = take(12 * Q); L.rd = take(12 * Q); L.info = take(4 * Q); L.pix = take(4 * Q); L.smp = take(4 * Q);
     L.hprim = take(4 * Q); L.ht = take(4 * Q); L.hu = take(4 * Q); L.hv = take(4 * Q);
     L.beta = take(op == 0 ? 19 * 4 * Q : 0);
@@ -661,12 +686,17 @@ static int check_ws(const ppt_plan* p, void* ws, size_t ws_bytes, int op, WsLayo
     return PPT_OK;
 }
 
+static LaunchMarker marker(const ppt_plan* p, int op) {
+    return p->timing ? LaunchMarker{&KTimer::mark_fn, &p->timer[op]} : LaunchMarker{nullptr, nullptr};
+}
+
 static int run_chunks(const ppt_plan* p, WArgs a, int mode, hipStream_t s) {
+    const LaunchMarker M = marker(p, mode);
     for (int c = 0; c < p->n_chunks; ++c) {
         a.g0 = (int64_t)c * p->Q;
         a.n_chunk = (int32_t)std::min<int64_t>(p->Q, p->num_paths - a.g0);
         if (a.n_chunk <= 0) break;
-        HIP_TRY(launch_chunk(a, mode, p->grid, s), mode == 0 ? "render launch" : "backward launch");
+        HIP_TRY(launch_chunk(a, mode, p->grid, s, M), mode == 0 ? "render launch" : "backward launch");
     }
     return PPT_OK;
 }
@@ -683,9 +713,14 @@ static int render_impl(const ppt_plan* p, const float* const* params, int32_t n_
     WArgs a = make_args(p, seed, ws, L);
     a.out = out;
     a.sig = sig;
+    const LaunchMarker M = marker(p, 0);
+    if (p->timing) p->timer[0].begin();
+    M(KF_OTHER, s);
     HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), p->stats, s), "setup launch");
     if (out) HIP_TRY(launch_fill_f32(out, p->image_numel, s), "clear launch");
-    return run_chunks(p, a, 0, s);
+    if ((rc = run_chunks(p, a, 0, s))) return rc;
+    M(-1, s);
+    return PPT_OK;
 }
 
 int ppt_render(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed, float* out, void* ws,
@@ -716,10 +751,40 @@ int ppt_backward(const ppt_plan* p, const float* const* params, int32_t n_params
     a.gacc = (double*)((char*)ws + L.gacc);
     a.lds_nd = L.lds_nd;
     a.lds_nf = L.lds_nf;
+    const LaunchMarker M = marker(p, 1);
+    if (p->timing) p->timer[1].begin();
+    M(KF_OTHER, s);
     HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), p->stats, s), "setup launch");
     HIP_TRY(launch_fill_f64(a.gacc, L.gacc_n, s), "clear launch");
     if ((rc = run_chunks(p, a, 1, s))) return rc;
+    M(KF_OTHER, s);
     HIP_TRY(launch_finalize(a.table, a.gacc, n_params, mx, s), "finalize launch");
+    M(-1, s);
+    return PPT_OK;
+}
+
+int ppt_plan_set_timing(ppt_plan* p, int32_t enabled) {
+    if (!p) return fail(PPT_EINVAL, "null plan");
+    p->timing = enabled != 0;
+    p->timer[0].begin();
+    p->timer[1].begin();
+    return PPT_OK;
+}
+
+int ppt_plan_kernel_times(const ppt_plan* p, int32_t op, double* ms, int32_t* launches, int32_t n) {
+    if (!p || !ms || !launches || n < 0) return fail(PPT_EINVAL, "bad argument");
+    if (op < 0 || op > 1) return fail(PPT_EINVAL, "op must be 0 (render) or 1 (backward)");
+    const KTimer& T = p->timer[op];
+    if (T.failed) return fail(PPT_EDEVICE, "event recording failed");
+    if (T.n < 2 || T.fam[T.n - 1] != -1) return fail(PPT_EINVAL, "no timed call of this op recorded");
+    for (int32_t k = 0; k < n; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    HIP_TRY(hipEventSynchronize(T.ev[T.n - 1]), "event sync");
+    for (size_t j = 0; j + 1 < T.n; ++j) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, T.ev[j], T.ev[j + 1]), "event time");
+        int f = T.fam[j];
+        if (f >= 0 && f < n) { ms[f] += t; launches[f] += 1; }
+    }
     return PPT_OK;
 }
 
@@ -730,8 +795,7 @@ int ppt_read_stats(const void* ws, int64_t* out, void* stream) {
     Stats st;
     HIP_TRY(hipMemcpyAsync(&st, (const char*)ws + off, sizeof st, hipMemcpyDeviceToHost, (hipStream_t)stream), "stats copy");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "stats sync");
-    out[0] = (int64_t)st.vertices; out[1] = (int64_t)st.paths; out[2] = (int64_t)st.nodes;
-    out[3] = (int64_t)st.prims; out[4] = (int64_t)st.shadow_rays;
+    for (int k = 0; k < ST_COUNT; ++k) out[k] = (int64_t)st.c[k];
     return PPT_OK;
 }
 

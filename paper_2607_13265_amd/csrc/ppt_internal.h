@@ -82,8 +82,20 @@ struct CallTable {
 constexpr int LDS_GRAD_D = 1024;    // FP64 entries of the workgroup gradient accumulator (small slots)
 constexpr int LDS_GRAD_F = 12800;   // FP32 entries (textures)
 
-struct Stats {                  // accumulated by every launch (64-bit counters)
-    unsigned long long vertices, paths, nodes, prims, shadow_rays;
+// Work counters, accumulated by every launch while enabled (64-bit).  nodes/prims count the
+// closest-hit traversals, shadow_nodes/shadow_prims the next-event (any-hit) traversals.
+enum { ST_VERTICES, ST_PATHS, ST_NODES, ST_PRIMS, ST_SHADOW_RAYS, ST_RAYS, ST_SHADOW_NODES, ST_SHADOW_PRIMS, ST_COUNT };
+struct Stats {
+    unsigned long long c[ST_COUNT];
+};
+
+// Kernel families for the optional per-launch event timing.
+enum { KF_GEN, KF_EXTEND, KF_SHADE, KF_SHADOW, KF_ACCUM, KF_FOLD, KF_REPLAY, KF_OTHER, KF_COUNT };
+// Called before every launch with the family of the kernel about to be launched (may be NULL).
+struct LaunchMarker {
+    void (*fn)(void* ctx, int family, hipStream_t s);
+    void* ctx;
+    void operator()(int family, hipStream_t s) const { if (fn) fn(ctx, family, s); }
 };
 
 // Structure-of-arrays state of the paths of one chunk (capacity Q slots), in the workspace.
@@ -108,7 +120,7 @@ struct PathState {
     int* queue0;    // ray queues (alternating per bounce) and the shadow queue
     int* queue1;
     int* squeue;
-    int* counts;    // 4 ints: queue0, queue1, shadow queue sizes
+    int* counts;    // 8 ints: queue0, queue1, shadow queue, replay queue sizes; replay grab cursor
 };
 
 struct WArgs {

@@ -9,30 +9,35 @@
 // Render (Sec. 3.1, Eq. 2): the state carries the prefix Mueller product beta and the radiance
 // sum; k_accum reduces the samples of each pixel.  Backward (Sec. 3.2, 4.3, Fig. 2): the primal
 // pass caches, per vertex, the weight W_b, the emission + next-event Stokes E_b and a hit record;
-// k_adjoint folds the cache into suffix radiance L[b] = E_b + W_b L[b+1] and replays the path
-// forward from the hit records (no second traversal), differentiating each vertex against the
-// cached L[b+1].  No Mueller matrix is inverted.
+// k_fold folds the cache into suffix radiance L[b] = E_b + W_b L[b+1] and queues the paths;
+// k_replay replays them forward from the hit records (no second traversal), differentiating each
+// vertex against the cached L[b+1].  No Mueller matrix is inverted.
 #include "ppt_device.h"
 
 namespace ppt {
 
 // ============================================================================ wave helpers
-// Workgroup-aggregated counters: one global atomic per workgroup and counter.  Every thread of
-// the workgroup must call it (it synchronizes the workgroup).
-DEV void flush_stats(Stats* st, uint32_t nodes, uint32_t prims, uint32_t shadow, uint32_t verts, uint32_t paths) {
-    if (!st) return;
-    __shared__ uint32_t part[5];
-    if (threadIdx.x < 5) part[threadIdx.x] = 0u;
-    __syncthreads();
-    uint32_t v[5] = {wave_sum_u(nodes), wave_sum_u(prims), wave_sum_u(shadow), wave_sum_u(verts), wave_sum_u(paths)};
-    if (lane_id() == 0)
-        for (int k = 0; k < 5; ++k)
-            if (v[k]) atomicAdd(&part[k], v[k]);
-    __syncthreads();
-    if (threadIdx.x < 5 && part[threadIdx.x]) {
-        unsigned long long* dst[5] = {&st->nodes, &st->prims, &st->shadow_rays, &st->vertices, &st->paths};
-        atomicAdd(dst[threadIdx.x], (unsigned long long)part[threadIdx.x]);
+// Workgroup-aggregated counters: one global atomic per workgroup and nonzero counter.  Every
+// thread of the workgroup must call it (it synchronizes the workgroup).
+struct Count {
+    uint32_t c[ST_COUNT];
+    DEV Count() {
+#pragma unroll
+        for (int k = 0; k < ST_COUNT; ++k) c[k] = 0u;
     }
+};
+DEV void flush_stats(Stats* st, const Count& n) {
+    if (!st) return;
+    __shared__ uint32_t part[ST_COUNT];
+    if (threadIdx.x < ST_COUNT) part[threadIdx.x] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ST_COUNT; ++k) {
+        uint32_t v = wave_sum_u(n.c[k]);
+        if (lane_id() == 0 && v) atomicAdd(&part[k], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_COUNT && part[threadIdx.x]) atomicAdd(&st->c[threadIdx.x], (unsigned long long)part[threadIdx.x]);
 }
 
 // Workgroup queue in LDS: lanes append with one LDS atomic per wavefront; the buffer is copied
@@ -94,7 +99,10 @@ DEV PathId path_id(const DevView* views, int n_views, int64_t g) {
     return r;
 }
 
-// SoA accessors
+// SoA accessors.  ld_off/st_off address component arrays through a wave-uniform base and a 32-bit
+// byte offset (slot * 4), which keeps one offset register for all components of a record.
+DEV float ld_off(const float* base, uint32_t byte_off) { return *(const float*)((const char*)base + byte_off); }
+DEV void st_off(float* base, uint32_t byte_off, float v) { *(float*)((char*)base + byte_off) = v; }
 DEV v3 ld_v3(const float* a, int Q, int i) { return mk(a[i], a[Q + i], a[2 * Q + i]); }
 DEV void st_v3(float* a, int Q, int i, v3 v) { a[i] = v.x; a[Q + i] = v.y; a[2 * Q + i] = v.z; }
 
@@ -103,14 +111,14 @@ DEV int info_make(int nverts, bool prev_delta, int view) { return nverts | (prev
 
 // ============================================================================ chunk start
 __global__ void k_reset_counts(int* counts) {
-    if (threadIdx.x < 4) counts[threadIdx.x] = 0;
+    if (threadIdx.x < 8) counts[threadIdx.x] = 0;
 }
 
 // Camera rays of the chunk's paths (masked paths are marked and skipped by the first bounce).
 __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
-    uint32_t npaths = 0;
+    Count cnt;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
         int64_t g = A.g0 + i;
         PathId id = path_id(A.views, A.n_views, g);
@@ -124,9 +132,9 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
         S.pix[i] = id.pix;
         S.smp[i] = id.smp;
         if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
-        if (live) ++npaths;
+        if (live) ++cnt.c[ST_PATHS];
     }
-    flush_stats(A.stats, 0, 0, 0, 0, npaths);
+    flush_stats(A.stats, cnt);
 }
 
 // ============================================================================ traversal kernels
@@ -141,7 +149,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
     }
     const int* q = A.qin ? S.queue1 : S.queue0;
     const int n = A.first ? A.n_chunk : S.counts[A.qin];
-    uint32_t nodes = 0, prims = 0;
+    Count cnt;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
         int slot = A.first ? i : q[i];
         int info = S.info[slot];
@@ -149,11 +157,13 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
         int v = info >> 12;
         const DevWorld& W = A.worlds[A.views[v].world];
         Hit h;
-        trace<false>(W, ld_v3(S.ro, Q, slot), ld_v3(S.rd, Q, slot), 3.0e38f, h, nodes, prims, stack);
+        ++cnt.c[ST_RAYS];
+        trace<false>(W, ld_v3(S.ro, Q, slot), ld_v3(S.rd, Q, slot), 3.0e38f, h, cnt.c[ST_NODES], cnt.c[ST_PRIMS],
+                     stack);
         S.hprim[slot] = h.prim;
         S.ht[slot] = h.t; S.hu[slot] = h.u; S.hv[slot] = h.v;
     }
-    flush_stats(A.stats, nodes, prims, 0, 0, 0);
+    flush_stats(A.stats, cnt);
 }
 
 template <int MODE>
@@ -163,14 +173,15 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
     const int n = S.counts[2];
-    uint32_t nodes = 0, prims = 0, rays = 0;
+    Count cnt;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
         int slot = S.squeue[i];
         int info = S.info[slot];
         const DevWorld& W = A.worlds[A.views[info >> 12].world];
         Hit h;
-        ++rays;
-        bool occ = trace<true>(W, ld_v3(S.so, Q, slot), ld_v3(S.sd, Q, slot), S.stmax[slot], h, nodes, prims, stack);
+        ++cnt.c[ST_SHADOW_RAYS];
+        bool occ = trace<true>(W, ld_v3(S.so, Q, slot), ld_v3(S.sd, Q, slot), S.stmax[slot], h, cnt.c[ST_SHADOW_NODES],
+                               cnt.c[ST_SHADOW_PRIMS], stack);
         if (MODE == 0) {
             if (!occ)
 #pragma unroll
@@ -187,7 +198,7 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
         }
         if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
     }
-    flush_stats(A.stats, nodes, prims, rays, 0, 0);
+    flush_stats(A.stats, cnt);
 }
 
 // ============================================================================ shading
@@ -202,7 +213,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
     __shared__ BlockQueue qn, qs;
     if (threadIdx.x == 0) { qn.n = 0; qs.n = 0; }
     __syncthreads();
-    uint32_t nverts = 0;
+    Count cnt;
     for (int bb = blockIdx.x * BLOCK; bb < n; bb += gridDim.x * BLOCK) {
         int i = bb + threadIdx.x;
         bool cont = false, shadow = false;
@@ -227,7 +238,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                     for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] = 0.0f;
             } else {
                 int b = nb + 1;
-                ++nverts;
+                ++cnt.c[ST_VERTICES];
                 Vtx x;
                 surface(W, h, o, d, x);
                 v3 so, sd;
@@ -332,7 +343,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
     }
     bq_flush(qn, &S.counts[1 - A.qin], qout, true);
     bq_flush(qs, &S.counts[2], S.squeue, true);
-    flush_stats(A.stats, 0, 0, 0, nverts, 0);
+    flush_stats(A.stats, cnt);
 }
 
 // ============================================================================ render: pixel reduction
@@ -353,15 +364,19 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
         float acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
-        PathId id{};
+        int v = 0, lx = 0, ly = 0;
         if (valid) {
-            int64_t g = A.g0 + i;
-            id = path_id(A.views, A.n_views, g);
-            key = g - id.smp;
-            if (!(S.info[i] & INFO_DEAD)) {
-                const DevView& V = A.views[id.v];
+            // pixel of the path from its stored keys; the segment key is (view, pixel)
+            const int info = S.info[i];
+            v = info >> 12;
+            const DevView& V = A.views[v];
+            const uint32_t pix = S.pix[i], smp = S.smp[i];
+            const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
+            lx = px - V.crop_x0; ly = py - V.crop_y0;
+            key = ((int64_t)v << 32) | (int64_t)pix;
+            if (!(info & INFO_DEAD)) {
                 v3 o, d;
-                camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
+                camera_ray(V, px, py, smp, A.seed, o, d);
                 v3 kc = -d;
                 float Cs, Ss;
                 rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
@@ -382,18 +397,18 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             bool take = lane >= off && kup == key;
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                float v = __shfl_up(acc[k], off, WAVE);
-                if (take) acc[k] += v;
+                float t = __shfl_up(acc[k], off, WAVE);
+                if (take) acc[k] += t;
             }
         }
         int64_t knext = __shfl_down(key, 1, WAVE);
         bool tail = valid && (lane == WAVE - 1 || knext != key);
         if (tail) {
-            const DevView& V = A.views[id.v];
+            const DevView& V = A.views[v];
             float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
             float inv = 1.0f / (float)V.spp;
             int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
-            int64_t ob = V.out_off + ((int64_t)id.ly * V.crop_w + id.lx) * 12;
+            int64_t ob = V.out_off + ((int64_t)ly * V.crop_w + lx) * 12;
             for (int a = 0; a < V.n_analyzers; ++a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -407,8 +422,160 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
     }
 }
 
-// ============================================================================ backward: fold + replay
-__global__ void __launch_bounds__(BLOCK) k_adjoint(WArgs A) {
+// ============================================================================ backward: fold
+// W_c applied to a Stokes vector without branches on the weight's kind (the loads of a record
+// stay together ahead of the arithmetic): the Fresnel form is evaluated and then selected.
+// Entries of kind-0 records are not read into the result.
+DEV void w_apply_select(const WC& w, int c, const float* in, float* out) {
+    float v1 = w.ci * in[1] + w.si * in[2], v2 = -w.si * in[1] + w.ci * in[2];
+    float f0 = w.A * in[0] + w.B * v1, f1 = w.B * in[0] + w.A * v1;
+    float f2 = w.C * v2 + w.D * in[3], f3 = -w.D * v2 + w.C * in[3];
+    const float s = w.rgb[c];
+    const bool fr = w.kind == 2, df = w.kind == 1;
+    out[0] = fr ? s * f0 : (df ? s * in[0] : 0.0f);
+    out[1] = fr ? s * (w.co * f1 + w.so * f2) : 0.0f;
+    out[2] = fr ? s * (-w.so * f1 + w.co * f2) : 0.0f;
+    out[3] = fr ? s * f3 : 0.0f;
+}
+
+// Per path with at least one vertex: folds the cache into the suffix radiance
+// L[b] = E_b + W_b L[b+1] (written over E_b), adds the polarizer-angle term delta^T (dP/dtheta) R_s L[1],
+// and sets up the replay: the adjoint rows a_c = (delta^T A / spp) R_s (into `pend`), the camera ray
+// (into ro/rd) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
+// contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
+// register until the view changes.
+__global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
+    PathState& S = A.S;
+    const int Q = A.Q;
+    Call K{A.table, A.gacc};
+    __shared__ BlockQueue rq;
+    if (threadIdx.x == 0) rq.n = 0;
+    __syncthreads();
+    const int r0 = (int)((int64_t)A.n_chunk * blockIdx.x / gridDim.x);
+    const int r1 = (int)((int64_t)A.n_chunk * (blockIdx.x + 1) / gridDim.x);
+    float gtheta = 0.0f;
+    int tkey = -1;
+    for (int base = r0; base < r1; base += BLOCK) {
+        const int i = base + threadIdx.x;
+        bool push = false;
+        const int info = i < r1 ? S.info[i] : INFO_DEAD;
+        const int B = (info & INFO_DEAD) ? 0 : (info & 255);
+        // the fold runs over wave-uniform record indices, so the record base stays scalar
+        const int Bw = wave_max_i(B);
+        const int v = info >> 12;
+        float gt = 0.0f;
+        if (B > 0) {
+            push = true;
+            const uint32_t pix = S.pix[i], smp = S.smp[i];
+            // fold (records B-1 .. 0).  Each record is loaded whole before any arithmetic so that
+            // its loads are in flight together; record 0 keeps E_1 (the replay reads L[b+1], b >= 1).
+            float L[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) L[k] = 0.0f;
+            const uint32_t boff = (uint32_t)i * 4u;
+#pragma unroll 1
+            for (int b = Bw - 1; b >= 0; --b) {
+                if (b >= B) continue;
+                float* C = S.cache + (size_t)b * CACHE_WORDS * Q;
+                float r[CW_HIT + 1];
+#pragma unroll
+                for (int k = 0; k <= CW_HIT; ++k) r[k] = ld_off(C + (size_t)k * Q, boff);
+                WC w;
+                w.rgb[0] = r[0]; w.rgb[1] = r[1]; w.rgb[2] = r[2];
+                w.A = r[3]; w.B = r[4]; w.C = r[5]; w.D = r[6];
+                w.ci = r[7]; w.si = r[8]; w.co = r[9]; w.so = r[10];
+                w.kind = (__float_as_int(r[CW_HIT]) >> 29) & 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float o4[4];
+                    w_apply_select(w, c, L + 4 * c, o4);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) L[4 * c + k] = r[CW_E + 4 * c + k] + o4[k];
+                }
+                if (b > 0)
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) st_off(C + (size_t)(CW_E + k) * Q, boff, L[k]);
+            }
+            // pixel of the path from its stored keys (no index arithmetic over the batch)
+            const DevView& V = A.views[v];
+            const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
+            const int lx = px - V.crop_x0, ly = py - V.crop_y0;
+            v3 o, d;
+            camera_ray(V, px, py, smp, A.seed, o, d);
+            v3 kc = -d;
+            float Cs, Ss;
+            rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
+            const bool pol = V.sensor == SENSOR_POLARIZER;
+            float theta = pol ? K.p(V.theta_slot, V.theta_off) : 0.0f;
+            // adjoint of the pixel mean in the sensor frame: a_sens_c = sum_a delta_a,c^T A_a / spp;
+            // the polarizer-angle term (one analyzer) is delta^T (dP/dtheta) R_s L[1]
+            const float inv = 1.0f / (float)V.spp;
+            const int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
+            const float* dp = A.dout + V.out_off + ((int64_t)ly * V.crop_w + lx) * 12;
+            float asens[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) asens[k] = 0.0f;
+            for (int a = 0; a < V.n_analyzers; ++a) {
+                float dl[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) dl[k] = dp[a * astride + k] * inv;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float r4[4];
+                    analyzer_row(V.sensor, theta, a, dl + 4 * c, r4);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) asens[4 * c + k] += r4[k];
+                    if (pol && a == 0) {
+                        float l1 = L[4 * c + 1], l2 = L[4 * c + 2];
+                        float ls[4] = {L[4 * c], Cs * l1 + Ss * l2, -Ss * l1 + Cs * l2, L[4 * c + 3]};
+                        gt += polarizer_dtheta(theta, dl + 4 * c, ls);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float a1 = asens[4 * c + 1], a2 = asens[4 * c + 2];
+                S.pend[(4 * c) * Q + i] = asens[4 * c];
+                S.pend[(4 * c + 1) * Q + i] = Cs * a1 - Ss * a2;
+                S.pend[(4 * c + 2) * Q + i] = Ss * a1 + Cs * a2;
+                S.pend[(4 * c + 3) * Q + i] = asens[4 * c + 3];
+            }
+            st_v3(S.ro, Q, i, o);
+            st_v3(S.rd, Q, i, d);
+            if (pol) {
+                if (tkey != v) {
+                    if (tkey >= 0) K.g(A.views[tkey].theta_slot, A.views[tkey].theta_off, gtheta);
+                    gtheta = 0.0f;
+                    tkey = v;
+                }
+                gtheta += gt;
+            }
+        }
+        bq_push(rq, push, i);
+        bq_flush(rq, &S.counts[3], S.queue0, false);
+    }
+    bq_flush(rq, &S.counts[3], S.queue0, true);
+    // polarizer angles: one atomic per distinct view among the wavefront's running sums
+    bool pending = tkey >= 0;
+    while (__ballot(pending)) {
+        unsigned long long m = __ballot(pending);
+        int leader = __ffsll((long long)m) - 1;
+        int key = __shfl(tkey, leader, WAVE);
+        bool mine = pending && tkey == key;
+        float s = wave_sum(mine ? gtheta : 0.0f);
+        if (lane_id() == leader) K.g(A.views[key].theta_slot, A.views[key].theta_off, s);
+        pending = pending && !mine;
+    }
+}
+
+// ============================================================================ backward: replay
+// Persistent replay of the queued paths from their hit records (no second traversal): every lane
+// replays one vertex per iteration and takes the next queued path as soon as its own ends, so
+// short and long paths share a wavefront without idling (wavefronts grab batches of queue entries
+// with one atomic).  At vertex b the lane differentiates E_b + W_b L[b+1] against its adjoint rows,
+// then advances them, a <- a W_b.  Gradients go to workgroup LDS accumulators, flushed at the end.
+constexpr int REPLAY_BATCH = 4 * WAVE;
+__global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
     const int Q = A.Q;
@@ -418,135 +585,100 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(WArgs A) {
     for (int k = threadIdx.x; k < A.lds_nd; k += BLOCK) K.lds_d[k] = 0.0;
     for (int k = threadIdx.x; k < A.lds_nf; k += BLOCK) K.lds_f[k] = 0.0f;
     __syncthreads();
-    for (int base = blockIdx.x * BLOCK + (threadIdx.x & ~(WAVE - 1)); base < A.n_chunk; base += gridDim.x * BLOCK) {
-        int i = base + lane_id();
-        float gtheta = 0.0f;
-        int tkey = -1;
-        if (i < A.n_chunk && !(S.info[i] & INFO_DEAD)) {
-            int64_t g = A.g0 + i;
-            PathId id = path_id(A.views, A.n_views, g);
-            const DevView& V = A.views[id.v];
+    const int n = S.counts[3];
+    int* grab = &S.counts[4];
+    const int lane = lane_id();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int c = 0, cend = 0;  // the wavefront's current batch of queue entries [c, cend)
+    bool exhausted = false;
+    int slot = -1, b = 0, B = 0, v = 0;
+    uint32_t pix = 0, smp = 0;
+    bool prev_delta = false;
+    float av[12];
+    v3 o = mk(0.0f, 0.0f, 0.0f), d = o;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) av[k] = 0.0f;
+    while (true) {
+        // hand queue entries to the lanes without a path
+        const bool need = slot < 0;
+        const unsigned long long m = __ballot(need);
+        const int k = (int)__popcll(m), rank = (int)__popcll(m & lt);
+        const int rem = cend - c;
+        int nb = -1;
+        if (k > rem && !exhausted) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(grab, REPLAY_BATCH);
+            nb = __builtin_amdgcn_readfirstlane(__shfl(base, 0, WAVE));
+        }
+        int idx = -1;
+        if (need) {
+            if (rank < rem) idx = c + rank;
+            else if (nb >= 0 && nb + (rank - rem) < min(nb + REPLAY_BATCH, n)) idx = nb + (rank - rem);
+        }
+        if (nb >= 0) {
+            if (nb >= n) { exhausted = true; c = cend = 0; }
+            else { cend = min(nb + REPLAY_BATCH, n); c = min(nb + (k - rem), cend); }
+        } else {
+            c = min(c + k, cend);
+        }
+        if (idx >= 0) {
+            slot = S.queue0[idx];
+            const int info = S.info[slot];
+            B = info & 255;
+            v = info >> 12;
+            b = 1;
+            prev_delta = false;
+            pix = S.pix[slot];
+            smp = S.smp[slot];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) av[q] = S.pend[q * Q + slot];
+            o = ld_v3(S.ro, Q, slot);
+            d = ld_v3(S.rd, Q, slot);
+        }
+        if (!__any(slot >= 0)) break;
+        if (slot >= 0) {
+            const DevView& V = A.views[v];
             const DevWorld& W = A.worlds[V.world];
-            const int B = S.info[i] & 255;
-            float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
-            // adjoint of the pixel mean in the sensor frame: a_sens_c = sum_a delta_a,c^T A_a / spp
-            float asens[12], dl[12];
-            float inv = 1.0f / (float)V.spp;
-            int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
-            int64_t ob = V.out_off + ((int64_t)id.ly * V.crop_w + id.lx) * 12;
+            const float* C = S.cache + (size_t)(b - 1) * CACHE_WORDS * Q;
+            uint32_t hw = (uint32_t)__float_as_int(C[CW_HIT * Q + slot]);
+            Hit h;
+            h.prim = (int)(hw & ((1u << 26) - 1));
+            int rec_nee = (int)((hw >> 26) & 7);
+            float hu = C[(CW_HIT + 1) * Q + slot];
+            h.u = hu; h.t = hu; h.v = C[(CW_HIT + 2) * Q + slot];
+            Vtx x;
+            surface(W, h, o, d, x);
+            v3 so, sd;
+            float stmax;
+            vertex_setup(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+            if (x.nee == NEE_PENDING) x.nee = rec_nee;
+            float Ln[12];
+            if (b < B) {
+                const float* Cn = C + (size_t)CACHE_WORDS * Q;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) asens[k] = 0.0f;
-            for (int a = 0; a < V.n_analyzers; ++a)
+                for (int q = 0; q < 12; ++q) Ln[q] = Cn[(CW_E + q) * Q + slot];
+            } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float d4[4], r4[4];
+                for (int q = 0; q < 12; ++q) Ln[q] = 0.0f;
+            }
+            WC w;
+            float Ee[12], En[12];
+            eval_vertex<true>(W, K, x, w, Ee, En, av, Ln);
+            if (b >= B || x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) {
+                slot = -1;
+            } else {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) d4[k] = A.dout[ob + a * astride + 4 * c + k] * inv;
-                    if (a == 0) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) dl[4 * c + k] = d4[k];
-                    }
-                    analyzer_row(V.sensor, theta, a, d4, r4);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) asens[4 * c + k] += r4[k];
-                }
-            v3 o, d;
-            camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
-            v3 kc = -d;
-            float Cs, Ss;
-            rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
-            // ---- backward fold over the cache: L[b] = E_b + W_b L[b+1], written over E_b
-            float L[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) L[k] = 0.0f;
-            for (int b = B - 1; b >= 0; --b) {
-                float* C = S.cache + (size_t)b * CACHE_WORDS * Q;
-                WC w;
-                w.rgb[0] = C[0 * Q + i]; w.rgb[1] = C[1 * Q + i]; w.rgb[2] = C[2 * Q + i];
-                w.A = C[3 * Q + i]; w.B = C[4 * Q + i]; w.C = C[5 * Q + i]; w.D = C[6 * Q + i];
-                w.ci = C[7 * Q + i]; w.si = C[8 * Q + i]; w.co = C[9 * Q + i]; w.so = C[10 * Q + i];
-                w.kind = (__float_as_int(C[CW_HIT * Q + i]) >> 29) & 3;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int cc = 0; cc < 3; ++cc) {
                     float o4[4];
-                    w_apply(w, c, L + 4 * c, o4);
+                    w_row(w, cc, av + 4 * cc, o4);
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        L[4 * c + k] = C[(CW_E + 4 * c + k) * Q + i] + o4[k];
-                        C[(CW_E + 4 * c + k) * Q + i] = L[4 * c + k];
-                    }
-                }
-            }
-            // polarizer-angle term: delta^T (dP/dtheta) R_s L[1]
-            if (V.sensor == SENSOR_POLARIZER) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float l1 = L[4 * c + 1], l2 = L[4 * c + 2];
-                    float ls[4] = {L[4 * c], Cs * l1 + Ss * l2, -Ss * l1 + Cs * l2, L[4 * c + 3]};
-                    gtheta += polarizer_dtheta(theta, dl + 4 * c, ls);
-                }
-                tkey = id.v;
-            }
-            // ---- replay from the hit records: a_c = a_sens_c R_s, then vertex by vertex
-            float av[12];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float a1 = asens[4 * c + 1], a2 = asens[4 * c + 2];
-                av[4 * c] = asens[4 * c];
-                av[4 * c + 1] = Cs * a1 - Ss * a2;
-                av[4 * c + 2] = Ss * a1 + Cs * a2;
-                av[4 * c + 3] = asens[4 * c + 3];
-            }
-            bool prev_delta = false;
-            for (int b = 1; b <= B; ++b) {
-                const float* C = S.cache + (size_t)(b - 1) * CACHE_WORDS * Q;
-                uint32_t hw = (uint32_t)__float_as_int(C[CW_HIT * Q + i]);
-                Hit h;
-                h.prim = (int)(hw & ((1u << 26) - 1));
-                int rec_nee = (int)((hw >> 26) & 7);
-                float hu = C[(CW_HIT + 1) * Q + i];
-                h.u = hu; h.t = hu; h.v = C[(CW_HIT + 2) * Q + i];
-                Vtx x;
-                surface(W, h, o, d, x);
-                v3 so, sd;
-                float stmax;
-                vertex_setup(W, K, V, A.seed, id.pix, id.smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
-                if (x.nee == NEE_PENDING) x.nee = rec_nee;
-                float Ln[12];
-                if (b < B) {
-                    const float* Cn = S.cache + (size_t)b * CACHE_WORDS * Q;
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) Ln[k] = Cn[(CW_E + k) * Q + i];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) Ln[k] = 0.0f;
-                }
-                WC w;
-                float Ee[12], En[12];
-                eval_vertex<true>(W, K, x, w, Ee, En, av, Ln);
-                if (x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) break;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float o4[4];
-                    w_row(w, c, av + 4 * c, o4);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) av[4 * c + k] = o4[k];
+                    for (int q = 0; q < 4; ++q) av[4 * cc + q] = o4[q];
                 }
                 prev_delta = is_delta(W.mats[x.mat].type);
                 o = spawn(x.p, x.ng, x.wi);
                 d = x.wi;
+                ++b;
             }
-        }
-        // polarizer angles: one atomic per distinct view in the wavefront
-        bool pending = tkey >= 0;
-        while (__ballot(pending)) {
-            unsigned long long m = __ballot(pending);
-            int leader = __ffsll((long long)m) - 1;
-            int key = __shfl(tkey, leader, WAVE);
-            bool mine = pending && tkey == key;
-            float s = wave_sum(mine ? gtheta : 0.0f);
-            if (lane_id() == leader) K.g(A.views[key].theta_slot, A.views[key].theta_off, s);
-            pending = pending && !mine;
         }
     }
     // flush the workgroup accumulators into the global FP64 accumulator
@@ -555,10 +687,10 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(WArgs A) {
     for (int s = 0; s < MAX_SLOTS; ++s) {
         int od = T->lds_d[s], of = T->lds_f[s];
         if (od < 0 && of < 0) continue;
-        int64_t go = T->goff[s], n = T->numel[s];
-        for (int64_t k = threadIdx.x; k < n; k += BLOCK) {
-            double v = od >= 0 ? K.lds_d[od + k] : (double)K.lds_f[of + k];
-            if (v != 0.0) unsafeAtomicAdd(A.gacc + go + k, v);
+        int64_t go = T->goff[s], nn = T->numel[s];
+        for (int64_t q = threadIdx.x; q < nn; q += BLOCK) {
+            double val = od >= 0 ? K.lds_d[od + q] : (double)K.lds_f[of + q];
+            if (val != 0.0) unsafeAtomicAdd(A.gacc + go + q, val);
         }
     }
 }
@@ -574,7 +706,7 @@ __global__ void k_setup(CallTable tab, CallTable* dst, Stats* stats, int reset_s
         dst->lds_d[i] = tab.lds_d[i];
         dst->lds_f[i] = tab.lds_f[i];
     }
-    if (i == 0 && reset_stats) stats->vertices = stats->paths = stats->nodes = stats->prims = stats->shadow_rays = 0ull;
+    if (i < ST_COUNT && reset_stats) stats->c[i] = 0ull;
 }
 __global__ void k_fill_f32(float* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -633,29 +765,38 @@ hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t
     return hipGetLastError();
 }
 
-// One chunk of paths through every bounce.  mode 0: render, 1: backward.
-hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s) {
+// One chunk of paths through every bounce.  mode 0: render, 1: backward.  M is told the family
+// of every kernel before its launch (event timing).
+hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M) {
     size_t lds = (size_t)a.stack_cap * BLOCK * sizeof(int);
+    M(KF_OTHER, s);
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, s, a.S.counts);
     int gb = blocks_for(a.n_chunk, G.other);
+    M(KF_GEN, s);
     hipLaunchKernelGGL(k_gen, dim3(gb), dim3(BLOCK), 0, s, a);
     for (int b = 1; b <= a.max_depth; ++b) {
         a.qin = (b - 1) & 1;
         a.first = b == 1;
+        M(KF_EXTEND, s);
         hipLaunchKernelGGL(k_extend, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
-        if (mode == 0) {
-            hipLaunchKernelGGL(k_shade<0>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
-            hipLaunchKernelGGL(k_shadow<0>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
-        } else {
-            hipLaunchKernelGGL(k_shade<1>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
-            hipLaunchKernelGGL(k_shadow<1>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
-        }
+        M(KF_SHADE, s);
+        if (mode == 0) hipLaunchKernelGGL(k_shade<0>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL(k_shade<1>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
+        M(KF_SHADOW, s);
+        if (mode == 0) hipLaunchKernelGGL(k_shadow<0>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
+        else hipLaunchKernelGGL(k_shadow<1>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
     }
     if (mode == 0) {
-        if (a.out) hipLaunchKernelGGL(k_accum, dim3(gb), dim3(BLOCK), 0, s, a);
+        if (a.out) {
+            M(KF_ACCUM, s);
+            hipLaunchKernelGGL(k_accum, dim3(gb), dim3(BLOCK), 0, s, a);
+        }
     } else {
         size_t glds = (size_t)a.lds_nd * sizeof(double) + (size_t)a.lds_nf * sizeof(float);
-        hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
+        M(KF_FOLD, s);
+        hipLaunchKernelGGL(k_fold, dim3(gb), dim3(BLOCK), 0, s, a);
+        M(KF_REPLAY, s);
+        hipLaunchKernelGGL(k_replay, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
     }
     return hipGetLastError();
 }
@@ -667,7 +808,7 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend, BLOCK, lds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1>, BLOCK, 0)) != hipSuccess) return r;
     size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_adjoint, BLOCK, glds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay, BLOCK, glds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_gen, BLOCK, 0)) != hipSuccess) return r;
     G->extend = (e > 0 ? e : 1) * cu;
     G->shade = (sh > 0 ? sh : 1) * cu;

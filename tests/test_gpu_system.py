@@ -203,6 +203,42 @@ def test_plan_and_call_errors():
         plan.render(params, 1, ws=small)
 
 
+# ----------------------------------------------------------------------------- counters and timing
+def test_counters_and_kernel_timing():
+    ppt = _ppt()
+    wl = _small_batch()
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = _params(wl.scene)
+    plan = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=2048)
+    n_chunks = plan.launch_info()["n_chunks"]
+    with pytest.raises(ppt.PPTError, match="EINVAL"):
+        plan.kernel_times(0)  # nothing timed yet
+    plan.set_timing(True)
+    plan.render(params, 5)
+    d = torch.randn(plan.image_numel, device="cuda")
+    plan.backward(params, 5, d)
+    tr, tb = plan.kernel_times(0), plan.kernel_times(1)
+    st_r, st_b = plan.stats(0), plan.stats(1)
+    plan.set_timing(False)
+    # launches per family: one per chunk and bounce for the bounce kernels
+    assert tr["extend"][1] == tr["shade"][1] == tr["shadow"][1] == n_chunks * wl.max_depth
+    assert tr["camera"][1] == tr["accum"][1] == n_chunks and tr["fold"][1] == tr["replay"][1] == 0
+    assert tb["fold"][1] == tb["replay"][1] == n_chunks and tb["accum"][1] == 0
+    for t in (tr, tb):
+        assert all(ms >= 0.0 for ms, _ in t.values()) and sum(ms for ms, _ in t.values()) > 0.0
+    # the backward's primal pass retraces exactly the render's paths (same seed); node and
+    # primitive counts depend on which rays share a wavefront (speculative leaf postponement),
+    # and the queues of later bounces are filled in a different order, so they only agree closely
+    for k in ("vertices", "paths", "rays", "shadow_rays"):
+        assert st_r[k] == st_b[k], k
+    for k in ("nodes", "prim_tests", "shadow_nodes", "shadow_prim_tests"):
+        assert abs(st_r[k] - st_b[k]) <= 0.05 * st_r[k], k
+    assert st_r["paths"] == plan.num_paths
+    assert st_r["vertices"] <= st_r["rays"] <= st_r["paths"] * wl.max_depth
+    assert 0 < st_r["shadow_rays"] <= st_r["vertices"]
+    assert st_r["nodes"] >= st_r["rays"] and st_r["shadow_nodes"] >= st_r["shadow_rays"]
+
+
 # ----------------------------------------------------------------------------- autograd
 def test_autograd_function_matches_backward():
     ppt = _ppt()
