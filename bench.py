@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # files whose content decides whether stored hardware counters still describe the kernels
 KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_device.h",
                   "paper_2607_13265_amd/csrc/ppt_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batched128.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_{}.md")
 KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "shadow": "ppt::k_shadow",
                  "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}
 
@@ -53,13 +53,14 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str, chunk: int):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when there is
-    none for this kernel and chunk size or the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def stored_traffic(workload: str, kernel: str, chunk: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary of the workload, or None
+    when there is none for this kernel and chunk size or the kernel sources changed since."""
+    path = TRAFFIC_FILE.format(workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("    ") and ":" in line:
                 k, v = line.strip().split(":", 1)
@@ -85,6 +86,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=32, help="full views in the oracle sample")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
+    ap.add_argument("--workload", choices=("batched128", "uneven8", "optimise"), default="batched128",
+                    help="batched128: 128 views of one scene (the headline); uneven8: eight worlds of uneven size; "
+                         "optimise: Adam recovery of textures and lights through the autograd wrapper")
+    ap.add_argument("--opt-steps", type=int, default=200)
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--spp", type=int, default=32)
     ap.add_argument("--chunk-paths", type=int, default=0, help="0: autotuned (cached per workload)")
@@ -99,11 +104,95 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def optimise(args, torch, ppt, sg, dev):
+    """Inverse rendering through PolarizedRender: 8 polarizer angles, 512x512, 16 spp, depth 6;
+    Adam on the hidden 256x256 albedo and roughness maps and the two lights' RGB intensities,
+    with a decorrelated backward seed every step.  Reports the loss curve, the time per step and
+    the peak device memory of the chunked PRB backward next to a stored-record reverse pass that
+    keeps every path's per-vertex records at once."""
+    wl = sg.config4(truth=False)
+    truth = sg.config4(truth=True)
+    scene = ppt.Scene(wl.scene.to_blob())
+    names = wl.scene.slot_names
+    p_true = [torch.from_numpy(p).to(dev) for p in truth.scene.params()]
+    chunk = args.chunk_paths or (1 << 23)
+    plan = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=chunk)
+    plan.set_stats(False)
+    target = plan.render(p_true, 777_777).clone()
+    opt_names = ("albedo_tex", "roughness_tex", "light_Le")
+    params = [torch.from_numpy(p).to(dev).requires_grad_(n in opt_names) for n, p in zip(names, wl.scene.params())]
+    lr = {"albedo_tex": 0.02, "roughness_tex": 0.02, "light_Le": 0.1}
+    opt = torch.optim.Adam([{"params": [params[names.index(n)]], "lr": lr[n]} for n in opt_names])
+    bounds = {"albedo_tex": (0.0, 1.0), "roughness_tex": (0.01, 1.0), "light_Le": (0.0, 100.0)}
+
+    def errors():
+        return {n: float((params[names.index(n)].detach() - p_true[names.index(n)]).pow(2).mean().sqrt())
+                for n in opt_names}
+
+    err0 = errors()
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    losses, times = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for it in range(args.opt_steps):
+        e0.record()
+        opt.zero_grad(set_to_none=True)
+        img = ppt.render(plan, params, 1 + it, backward_seed=1_000_003 + it)
+        loss = (img - target).pow(2).mean()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            for n in opt_names:
+                params[names.index(n)].clamp_(*bounds[n])
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        losses.append(float(loss.detach()))
+        if it % 20 == 0 or it == args.opt_steps - 1:
+            log(f"[optimise] step {it}: loss {losses[-1]:.6e}, {times[-1]:.1f} ms")
+    peak_prb = torch.cuda.max_memory_allocated(dev)
+    err1 = errors()
+    # one backward with every path's per-vertex records held at once (a stored-record reverse pass)
+    n_paths = plan.num_paths
+    del opt
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)
+    d = (2.0 / target.numel()) * (plan.render([p.detach() for p in params], 1) - target)
+    store = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=((n_paths + 63) // 64) * 64)
+    store.set_stats(False)
+    ws_bytes = store.workspace_bytes(1)
+    e0.record()
+    store.backward([p.detach() for p in params], 1, d, want=[n in opt_names for n in names])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_store = e0.elapsed_time(e1)
+    peak_store = torch.cuda.max_memory_allocated(dev)
+    res = {
+        "metric": "inverse rendering: Adam steps through the autograd wrapper (render + PRB backward)",
+        "workload": f"{len(wl.views)} polarizer angles, 512x512, 16 spp, depth {wl.max_depth}, 40.96k triangles, "
+                    "2 lights; recover 256x256x3 albedo, 256x256 roughness, 6 light intensities",
+        "steps": args.opt_steps, "paths_per_step": int(n_paths), "chunk_paths": plan.launch_info()["chunk_paths"],
+        "ms_per_step_median": float(np.median(times)), "loss_first": losses[0], "loss_last": losses[-1],
+        "loss_curve": [round(x, 9) for x in losses],
+        "rmse_to_truth_start": err0, "rmse_to_truth_end": err1,
+        "peak_device_memory_gb": {"prb_chunked": round(peak_prb / 1e9, 3),
+                                  "stored_records_all_paths": round(peak_store / 1e9, 3)},
+        "stored_records_workspace_gb": round(ws_bytes / 1e9, 3),
+        "stored_records_backward_ms": round(ms_store, 2),
+        "prb_workspace_gb": {"render": round(plan.workspace_bytes(0) / 1e9, 3),
+                             "backward": round(plan.workspace_bytes(1) / 1e9, 3)},
+    }
+    line = json.dumps(res)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -121,8 +210,21 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copied {args.copy_calibration} MiB three times")
         return
-    wl = sg.config3(res=args.res, spp=args.spp)
-    log(f"[bench] workload {wl.name}: {len(wl.views)} views {args.res}^2 x {args.spp} spp, depth {wl.max_depth}")
+    if args.workload == "optimise":
+        return optimise(args, torch, ppt, sg, dev)
+    if args.workload == "batched128":
+        wl = sg.config3(res=args.res, spp=args.spp)
+        desc = (f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), {args.res}x{args.res}, "
+                f"{args.spp} spp, depth {wl.max_depth}, 20.5k-triangle icosphere scene, render + PRB backward, "
+                "HIP-graph replay")
+    else:
+        wl = sg.config5()
+        res_l = [int(v["width"]) for v in wl.views]
+        spp_l = [int(v["spp"]) for v in wl.views]
+        desc = (f"uneven batch: {len(wl.views)} worlds (Perlin terrain 1e5..1e6 triangles + icospheres), "
+                f"resolutions {res_l}, spp {spp_l}, depth {wl.max_depth}, 4 analyzers, render + PRB backward, "
+                "HIP-graph replay")
+    log(f"[bench] workload {wl.name}: {desc}")
     blob = wl.scene.to_blob()
     scene = ppt.Scene(blob)
     params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
@@ -136,7 +238,7 @@ def main():
         log(f"[bench] autotuned chunk {chunk}: {tuned}")
     plan = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, chunk_paths=chunk)
     info = plan.launch_info()
-    rng = np.random.default_rng(wl.meta["delta_seed"])
+    rng = np.random.default_rng(wl.meta.get("delta_seed", 5005))
     d = torch.from_numpy(rng.standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
     want = [n in wl.grad_slots for n in wl.scene.slot_names]
     out = torch.empty(plan.image_numel, dtype=torch.float32, device=dev)
@@ -198,10 +300,9 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "Mpath-vertices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), "
-                               f"{args.res}x{args.res}, {args.spp} spp, depth {wl.max_depth}, 20.5k-triangle "
-                               "icosphere scene, render + PRB backward, HIP-graph replay",
-                   "views": len(wl.views), "resolution": args.res, "spp": args.spp, "max_depth": wl.max_depth,
+        "config": {"workload": desc,
+                   "views": len(wl.views), "resolution": [int(v["width"]) for v in wl.views],
+                   "spp": [int(v["spp"]) for v in wl.views], "max_depth": wl.max_depth,
                    "vertices_per_step": verts, "paths_per_step": st_r["paths"],
                    "chunk_paths": info["chunk_paths"], "chunks": info["n_chunks"],
                    "autotune_ms": tuned},
@@ -279,7 +380,7 @@ def main():
     dom = max(fams, key=lambda f: fams[f]["ms_per_step"])
     D = fams[dom]
     result["roofline"] = {"bound": D["bound"], "achieved": D["achieved"], "peak": D["peak"], "unit": D["unit"],
-                          "frac": D["frac"], "traffic": stored_traffic(KERNEL_SYMBOL[dom], info["chunk_paths"]),
+                          "frac": D["frac"], "traffic": stored_traffic(args.workload, KERNEL_SYMBOL[dom], info["chunk_paths"]),
                           "kernel": KERNEL_SYMBOL[dom], "avg_launch_ms": D["avg_launch_ms"],
                           "launches_per_step": D["launches_per_step"],
                           "algorithmic_per_launch": D["work_per_launch"],
@@ -290,7 +391,14 @@ def main():
     if not args.no_cpu:
         import oracle
         nthreads = min(16, os.cpu_count() or 1)
-        sample_views = wl.views[:max(1, min(args.cpu_views, len(wl.views)))]
+        if args.workload == "batched128":
+            sample_views = wl.views[:max(1, min(args.cpu_views, len(wl.views)))]
+            sample_desc = f"{len(sample_views)} of the {len(wl.views)} views, whole {args.res}x{args.res} images"
+        else:
+            sample_views = sg.crop_views(wl.views, 0, 0, 64, 64)
+            sample_views["crop_x0"] = (sample_views["width"] - 64) // 2
+            sample_views["crop_y0"] = (sample_views["height"] - 64) // 2
+            sample_desc = f"the central 64x64 crop of each of the {len(wl.views)} views"
         osc = oracle.OracleScene.from_scene(wl.scene)
         p64 = [p.astype(np.float64) for p in wl.scene.params()]
         dd = np.random.default_rng(1).standard_normal(sg.image_numel(sample_views))
@@ -301,8 +409,7 @@ def main():
         tc = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(r["n_vertices"] / tc / 1e6, 4), "unit": "Mpath-vertices/s",
                                   "cores": nthreads, "kind": "oracle",
-                                  "sample": f"{len(sample_views)} of the {len(wl.views)} views, whole "
-                                            f"{args.res}x{args.res} images x {args.spp} spp, depth {wl.max_depth} "
+                                  "sample": f"{sample_desc} at full spp, depth {wl.max_depth} "
                                             f"({r['n_paths']} paths, {r['n_vertices']} vertices): FP64 render + "
                                             f"cached-suffix replay, {tc:.1f} s"}
         log(f"[bench] cpu oracle: {result['cpu_baseline']}")

@@ -317,23 +317,27 @@ DEV cf ior(const Call& K, const DevMaterial& m) {
 // ============================================================================ traversal
 struct Hit { int prim; float t, u, v; };
 
+// Scene arrays live in device global memory: reading them through global-address-space pointers
+// gives global (not flat) loads, whose completion is not tied to the LDS traversal stack.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+DEV float4 ldg4(const float4* p, int i) {
+    f32x4 v = ((const __attribute__((address_space(1))) f32x4*)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 DEV v3 safe_inv(v3 d) {
     const float e = 1e-20f;
     return mk(1.0f / (fabsf(d.x) > e ? d.x : copysignf(e, d.x)), 1.0f / (fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
               1.0f / (fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
 }
 
-// Closest hit (ANY = false) or any hit (ANY = true) with 0 < t < tmax.
-// Closest hit (ANY = false) or any hit (ANY = true) with 0 < t < tmax.
-// While-while traversal with speculative leaf postponement (Aila & Laine 2009): a lane that
-// reaches a leaf parks it and keeps descending until every lane of the wavefront still in the
-// node loop holds a leaf; then the wavefront tests primitives together.
-// stack: this thread's slot in a workgroup-shared array, entry k at stack[k * BLOCK].
+// Intersection of primitive i (triangle or sphere) with the ray; accepted when 0 < t < tb, which
+// then shrinks to t.
 DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
     const float4* pr = prims + 3 * i;
-    float4 A = pr[0], B = pr[1];
+    float4 A = ldg4(pr, 0), B = ldg4(pr, 1);
     if (__float_as_int(B.w) == 0) {
-        float4 C = pr[2];
+        float4 C = ldg4(pr, 2);
         v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
         v3 p = cross(d, e2);
         float det = dot(e1, p);
@@ -363,69 +367,89 @@ DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
     return true;
 }
 
+// Resumable traversal state of one ray (the stack lives in LDS, entry k at stack[k * BLOCK]).
+constexpr int TRAV_DONE = 0x7fffffff;
+struct Trav {
+    v3 o, d, id, ood;
+    float tb;
+    int ref;   // >= 0 inner node, < 0 leaf, TRAV_DONE when the stack is exhausted
+    int leaf;  // parked leaf (< 0) or none
+    int sp;
+    Hit h;
+    const float4* nodes;
+    const float4* prims;
+};
+DEV void trav_begin(Trav& T, const DevWorld& W, v3 o, v3 d, float tmax) {
+    T.o = o; T.d = d;
+    T.id = safe_inv(d);
+    T.ood = mk(o.x * T.id.x, o.y * T.id.y, o.z * T.id.z);
+    T.tb = tmax;
+    T.sp = 0;
+    T.h.prim = -1; T.h.t = 0.0f; T.h.u = 0.0f; T.h.v = 0.0f;
+    T.nodes = W.nodes;
+    T.prims = W.prims;
+    T.leaf = 0;
+    T.ref = W.n_prims == 0 ? TRAV_DONE : W.root;
+    if (T.ref < 0) { T.leaf = T.ref; T.ref = TRAV_DONE; }
+}
+// One round of while-while traversal with speculative leaf postponement (Aila & Laine 2009):
+// the lanes of the wavefront in this call descend, a lane that reaches a leaf parks it and keeps
+// descending until every such lane holds a leaf, then the parked leaves are tested.  Returns true
+// when the ray is finished: closest hit in T.h (ANY = false), or the first hit (ANY = true).
 template <bool ANY>
-DEV bool trace(const DevWorld& W, v3 o, v3 d, float tmax, Hit& h, uint32_t& n_nodes, uint32_t& n_prims,
-                int* stack) {
-    h.prim = -1;
-    if (W.n_prims == 0) return false;
-    constexpr int DONE = 0x7fffffff;
-    v3 id = safe_inv(d);
-    v3 ood = mk(o.x * id.x, o.y * id.y, o.z * id.z);
-    int sp = 0;
-    int ref = W.root;  // >= 0 inner node, < 0 leaf, DONE when the stack is exhausted
-    int leaf = 0;      // parked leaf (< 0) or none
-    float tb = tmax;
-    if (ref < 0) { leaf = ref; ref = DONE; }
-    while (true) {
-        while (ref != DONE && ref >= 0) {
-            ++n_nodes;
-            const float4* nd = W.nodes + 4 * ref;
-            float4 q0 = nd[0], q1 = nd[1], q2 = nd[2], q3 = nd[3];
-            float a0 = fmaf(q0.x, id.x, -ood.x), a1 = fmaf(q0.y, id.x, -ood.x);
-            float b0 = fmaf(q0.z, id.y, -ood.y), b1 = fmaf(q0.w, id.y, -ood.y);
-            float c0 = fmaf(q2.x, id.z, -ood.z), c1 = fmaf(q2.y, id.z, -ood.z);
-            float tnL = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
-            float txL = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), tb));
-            float e0 = fmaf(q1.x, id.x, -ood.x), e1 = fmaf(q1.y, id.x, -ood.x);
-            float f0 = fmaf(q1.z, id.y, -ood.y), f1 = fmaf(q1.w, id.y, -ood.y);
-            float g0 = fmaf(q2.z, id.z, -ood.z), g1 = fmaf(q2.w, id.z, -ood.z);
-            float tnR = fmaxf(fmaxf(fminf(e0, e1), fminf(f0, f1)), fmaxf(fminf(g0, g1), 0.0f));
-            float txR = fminf(fminf(fmaxf(e0, e1), fmaxf(f0, f1)), fminf(fmaxf(g0, g1), tb));
-            bool hL = tnL <= txL, hR = tnR <= txR;
-            int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
-            if (hL && hR) {
-                if (tnR < tnL) { int t = rL; rL = rR; rR = t; }
-                stack[(sp++) * BLOCK] = rR;
-                ref = rL;
-            } else if (hL) {
-                ref = rL;
-            } else if (hR) {
-                ref = rR;
-            } else {
-                ref = sp ? stack[(--sp) * BLOCK] : DONE;
-            }
-            if (ref < 0 && leaf == 0) {  // park the leaf, keep descending
-                leaf = ref;
-                ref = sp ? stack[(--sp) * BLOCK] : DONE;
-            }
-            if (!__any(leaf == 0)) break;  // every lane in this loop holds a leaf
+DEV bool trav_round(Trav& T, uint32_t& n_nodes, uint32_t& n_prims, int* stack) {
+    while (T.ref != TRAV_DONE && T.ref >= 0) {
+        ++n_nodes;
+        const float4* nd = T.nodes + 4 * T.ref;
+        float4 q0 = ldg4(nd, 0), q1 = ldg4(nd, 1), q2 = ldg4(nd, 2), q3 = ldg4(nd, 3);
+        const v3 id = T.id, ood = T.ood;
+        float a0 = fmaf(q0.x, id.x, -ood.x), a1 = fmaf(q0.y, id.x, -ood.x);
+        float b0 = fmaf(q0.z, id.y, -ood.y), b1 = fmaf(q0.w, id.y, -ood.y);
+        float c0 = fmaf(q2.x, id.z, -ood.z), c1 = fmaf(q2.y, id.z, -ood.z);
+        float tnL = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
+        float txL = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), T.tb));
+        float e0 = fmaf(q1.x, id.x, -ood.x), e1 = fmaf(q1.y, id.x, -ood.x);
+        float f0 = fmaf(q1.z, id.y, -ood.y), f1 = fmaf(q1.w, id.y, -ood.y);
+        float g0 = fmaf(q2.z, id.z, -ood.z), g1 = fmaf(q2.w, id.z, -ood.z);
+        float tnR = fmaxf(fmaxf(fminf(e0, e1), fminf(f0, f1)), fmaxf(fminf(g0, g1), 0.0f));
+        float txR = fminf(fminf(fmaxf(e0, e1), fmaxf(f0, f1)), fminf(fmaxf(g0, g1), T.tb));
+        bool hL = tnL <= txL, hR = tnR <= txR;
+        int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
+        if (hL && hR) {
+            if (tnR < tnL) { int t = rL; rL = rR; rR = t; }
+            stack[(T.sp++) * BLOCK] = rR;
+            T.ref = rL;
+        } else if (hL) {
+            T.ref = rL;
+        } else if (hR) {
+            T.ref = rR;
+        } else {
+            T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
         }
-        while (leaf < 0) {
-            int enc = ~leaf;
-            int first = enc >> 3, cnt = (enc & 7) + 1;
-            for (int k = 0; k < cnt; ++k) {
-                ++n_prims;
-                if (hit_prim(W.prims, first + k, o, d, tb, h) && ANY) return true;
-            }
-            leaf = 0;
-            if (ref < 0) {  // the node loop stopped on a second leaf
-                leaf = ref;
-                ref = sp ? stack[(--sp) * BLOCK] : DONE;
-            }
+        if (T.ref < 0 && T.leaf == 0) {  // park the leaf, keep descending
+            T.leaf = T.ref;
+            T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
         }
-        if (ref == DONE) break;
+        if (!__any(T.leaf == 0)) break;  // every lane in this loop holds a leaf
     }
-    return h.prim >= 0;
+    while (T.leaf < 0) {
+        int enc = ~T.leaf;
+        int first = enc >> 3, cnt = (enc & 7) + 1;
+        for (int k = 0; k < cnt; ++k) {
+            ++n_prims;
+            if (hit_prim(T.prims, first + k, T.o, T.d, T.tb, T.h) && ANY) {
+                T.leaf = 0;
+                T.ref = TRAV_DONE;
+                return true;
+            }
+        }
+        T.leaf = 0;
+        if (T.ref < 0) {  // the node loop stopped on a second leaf
+            T.leaf = T.ref;
+            T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
+        }
+    }
+    return T.ref == TRAV_DONE;
 }
 
 DEV float offset_eps(v3 p) { return 1e-4f * (1.0f + fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z))); }
@@ -462,7 +486,7 @@ DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
     float4 A = pr[0], B = pr[1];
     x.orig = __float_as_int(A.w);
     if (__float_as_int(B.w) == 0) {
-        float4 C = pr[2];
+        float4 C = ldg4(pr, 2);
         v3 e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
         x.p = mk(A.x, A.y, A.z) + e1 * h.u + e2 * h.v;
         x.ng = normalize(cross(e1, e2));

@@ -429,7 +429,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
 struct WsLayout {
     size_t table, stats, counts, gacc, total;
     int lds_nd = 0, lds_nf = 0;
-    size_t ro, rd, info, pix, smp, hprim, ht, hu, hv, beta, Lo, pend, so, sd, stmax, cache, q0, q1, sq;
+    size_t ray, shd, acc, cache, q0, q1, sq;
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -441,13 +441,10 @@ static WsLayout ws_layout(const ppt_plan* p, int op) {
     L.table = take(sizeof(CallTable));
     L.stats = take(sizeof(Stats));
     L.counts = take(32);
-    L.ro = take(12 * Q); L.rd = take(12 * Q); L.info = take(4 * Q); L.pix = take(4 * Q); L.smp = take(4 * Q);
-    L.hprim = take(4 * Q); L.ht = take(4 * Q); L.hu = take(4 * Q); L.hv = take(4 * Q);
-    L.beta = take(op == 0 ? 19 * 4 * Q : 0);
-    L.Lo = take(op == 0 ? 12 * 4 * Q : 0);
-    L.pend = take(12 * 4 * Q);
-    L.so = take(12 * Q); L.sd = take(12 * Q); L.stmax = take(4 * Q);
-    L.cache = take(op == 1 ? (size_t)p->max_depth * CACHE_WORDS * 4 * Q : 0);
+    L.ray = take(RAY_F4 * 16 * Q);
+    L.shd = take(SHD_F4 * 16 * Q);
+    L.acc = take(op == 0 ? ACC_F4 * 16 * Q : 0);
+    L.cache = take(op == 1 ? (size_t)p->max_depth * CACHE_F4 * 16 * Q : 0);
     L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q);
     L.gacc_n = 0;
     if (op == 1)
@@ -459,12 +456,10 @@ static WsLayout ws_layout(const ppt_plan* p, int op) {
 static PathState path_state(void* ws, const WsLayout& L) {
     char* w = (char*)ws;
     PathState S;
-    S.ro = (float*)(w + L.ro); S.rd = (float*)(w + L.rd); S.info = (int*)(w + L.info);
-    S.pix = (uint32_t*)(w + L.pix); S.smp = (uint32_t*)(w + L.smp);
-    S.hprim = (int*)(w + L.hprim); S.ht = (float*)(w + L.ht); S.hu = (float*)(w + L.hu); S.hv = (float*)(w + L.hv);
-    S.beta = (float*)(w + L.beta); S.Lo = (float*)(w + L.Lo);
-    S.pend = (float*)(w + L.pend); S.so = (float*)(w + L.so); S.sd = (float*)(w + L.sd); S.stmax = (float*)(w + L.stmax);
-    S.cache = (float*)(w + L.cache);
+    S.ray = (float4*)(w + L.ray);
+    S.shd = (float4*)(w + L.shd);
+    S.acc = (float4*)(w + L.acc);
+    S.cache = (float4*)(w + L.cache);
     S.queue0 = (int*)(w + L.q0); S.queue1 = (int*)(w + L.q1); S.squeue = (int*)(w + L.sq);
     S.counts = (int*)(w + L.counts);
     return S;

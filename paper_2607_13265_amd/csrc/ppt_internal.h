@@ -12,11 +12,20 @@ constexpr int BLOCK = 256;      // 4 wavefronts per workgroup
 constexpr int MAX_DEPTH = 64;
 constexpr int STACK = 64;       // BVH traversal stack entries per lane
 
-// per-vertex cache record of the backward pass (32-bit words, one SoA array per word)
-constexpr int CW_W = 0;         // 11 words: compact Mueller weight (rgb[3], a, b, c, d, Cin, Sin, Cout, Sout)
-constexpr int CW_E = 11;        // 12 words: E_b per channel, overwritten by the suffix L[b] in the fold
-constexpr int CW_HIT = 23;      // 3 words: prim | flags, barycentric u (or t), barycentric v
-constexpr int CACHE_WORDS = 26;
+// Per-path records in the workspace (one record per slot, 16-byte vectors; a path touches only
+// its own cache lines even when the ray queues have scattered the live slots).
+//   ray record, RAY_F4 = 4 vectors (64 B):
+//     [0] ro.x ro.y ro.z rd.x   [1] rd.y rd.z t u   [2] v prim - -   [3] info pix smp -
+//   shadow record, SHD_F4 = 8 vectors (128 B):
+//     [0] so.x so.y so.z tmax   [1] sd.x sd.y sd.z -   [2..4] 12 Stokes words: the pending next-event
+//     contribution (forward passes), then the adjoint rows of the replay (backward)
+//   accumulator record (render), ACC_F4 = 8 vectors (128 B):
+//     [0..3] prefix Mueller product beta (16)   [4] beta RGB scales (3)   [5..7] radiance Lo (12)
+//   cache record (backward), one per (vertex b, slot), CACHE_F4 = 8 vectors (128 B):
+//     [0] rgb0 rgb1 rgb2 A   [1] B C D Cin   [2] Sin Cout Sout hitword   [3] u-or-t v - -
+//     [4..6] E_b (12 words), overwritten by the suffix radiance L[b] in the fold
+//   hitword = prim | next-event state << 26 | weight kind << 29
+constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8;
 
 enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
                          MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };
@@ -98,28 +107,15 @@ struct LaunchMarker {
     void operator()(int family, hipStream_t s) const { if (fn) fn(ctx, family, s); }
 };
 
-// Structure-of-arrays state of the paths of one chunk (capacity Q slots), in the workspace.
-// Arrays of k components store component j of slot i at [j * Q + i].
+// State of the paths of one chunk (capacity Q slots) in the workspace, as per-slot records.
 struct PathState {
-    float* ro;      // 3: ray origin
-    float* rd;      // 3: ray direction
-    int* info;      // vertices so far (bits 0-7), previous vertex delta (bit 8), masked (bit 9), view (bits 12+)
-    uint32_t* pix;  // pixel index in the full image (random-stream key)
-    uint32_t* smp;  // sample index
-    int* hprim;     // closest hit: primitive (BVH order) or -1
-    float* ht;
-    float* hu;
-    float* hv;
-    float* beta;    // render: 16 shared prefix-Mueller entries + 3 RGB scales (set at the first vertex)
-    float* Lo;      // render: 12 accumulated Stokes components (canonical frame of the camera ray)
-    float* pend;    // 12: next-event contribution awaiting its visibility test
-    float* so;      // 3: shadow ray origin
-    float* sd;      // 3: shadow ray direction
-    float* stmax;   // shadow ray length
-    float* cache;   // backward: [max_depth][CACHE_WORDS][Q] per-vertex cache
-    int* queue0;    // ray queues (alternating per bounce) and the shadow queue
+    float4* ray;    // [Q][RAY_F4]
+    float4* shd;    // [Q][SHD_F4]
+    float4* acc;    // [Q][ACC_F4] (render)
+    float4* cache;  // [max_depth][Q][CACHE_F4] (backward)
+    int* queue0;    // ray queues (alternating per bounce; queue0 is the replay queue after the fold)
     int* queue1;
-    int* squeue;
+    int* squeue;    // shadow-ray queue
     int* counts;    // 8 ints: queue0, queue1, shadow queue, replay queue sizes; replay grab cursor
 };
 

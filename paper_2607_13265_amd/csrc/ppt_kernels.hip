@@ -74,6 +74,56 @@ DEV void sig_add(uint64_t& h, uint32_t x) {
     for (int i = 0; i < 4; ++i) { h ^= (x >> (8 * i)) & 0xffu; h *= 1099511628211ull; }
 }
 
+// Work distribution of the persistent kernels.  Only the first ceil(n / BLOCK) workgroups take
+// part (fetch_active; the others leave at once).  Active wavefront w first takes the static batch
+// [w * s, (w + 1) * s) with s = n / active wavefronts rounded down to whole wavefronts and kept in
+// [FETCH_MIN, FETCH_BATCH]; positions beyond all static batches are handed out in batches of
+// FETCH_BATCH through one atomic on a counter that the previous kernel cleared.  A short queue is
+// thus covered by the static batches alone, with no atomic.  A wavefront gives its positions, in
+// order, to its lanes that have no work; every lane of the wavefront must call take().
+constexpr int FETCH_MIN = WAVE, FETCH_BATCH = 4 * WAVE;
+DEV int fetch_blocks(int n) { return max(1, min((int)gridDim.x, (n + BLOCK - 1) / BLOCK)); }
+DEV bool fetch_active(int n) { return (int)blockIdx.x < fetch_blocks(n); }
+struct WaveFetch {
+    int c, cend;    // the wavefront's current batch [c, cend)
+    int stat;       // positions covered by the static batches
+    bool exhausted;
+    DEV explicit WaveFetch(int n) {
+        const int waves = fetch_blocks(n) * (BLOCK / WAVE);
+        const int w = blockIdx.x * (BLOCK / WAVE) + (int)(threadIdx.x / WAVE);
+        int sb = (n / waves) / WAVE * WAVE;
+        sb = sb < FETCH_MIN ? FETCH_MIN : (sb > FETCH_BATCH ? FETCH_BATCH : sb);
+        stat = waves * sb;
+        c = min(w * sb, n);
+        cend = min(c + sb, n);
+        exhausted = n <= stat;
+    }
+    DEV int take(bool need, int n, int* grab) {
+        const unsigned long long m = __ballot(need);
+        const int k = (int)__popcll(m), rank = (int)__popcll(m & ((1ull << lane_id()) - 1ull));
+        const int rem = cend - c;
+        int nb = -1;
+        if (k > rem && !exhausted) {
+            int base = 0;
+            if (lane_id() == 0) base = atomicAdd(grab, FETCH_BATCH);
+            nb = stat + __builtin_amdgcn_readfirstlane(__shfl(base, 0, WAVE));
+        }
+        int idx = -1;
+        if (need) {
+            if (rank < rem) idx = c + rank;
+            else if (nb >= 0 && nb + (rank - rem) < min(nb + FETCH_BATCH, n)) idx = nb + (rank - rem);
+        }
+        if (nb >= 0) {
+            if (nb >= n) { exhausted = true; c = cend = 0; }
+            else { cend = min(nb + FETCH_BATCH, n); c = min(nb + (k - rem), cend); }
+        } else {
+            c = min(c + k, cend);
+        }
+        return idx;
+    }
+    DEV bool more() const { return !exhausted || c < cend; }  // wave-uniform
+};
+
 // view of a global path index (views are few; binary search over their path offsets)
 DEV int find_view(const DevView* views, int n_views, int64_t g) {
     int lo = 0, hi = n_views - 1;
@@ -99,12 +149,32 @@ DEV PathId path_id(const DevView* views, int n_views, int64_t g) {
     return r;
 }
 
-// SoA accessors.  ld_off/st_off address component arrays through a wave-uniform base and a 32-bit
-// byte offset (slot * 4), which keeps one offset register for all components of a record.
-DEV float ld_off(const float* base, uint32_t byte_off) { return *(const float*)((const char*)base + byte_off); }
-DEV void st_off(float* base, uint32_t byte_off, float v) { *(float*)((char*)base + byte_off) = v; }
-DEV v3 ld_v3(const float* a, int Q, int i) { return mk(a[i], a[Q + i], a[2 * Q + i]); }
-DEV void st_v3(float* a, int Q, int i, v3 v) { a[i] = v.x; a[Q + i] = v.y; a[2 * Q + i] = v.z; }
+// Record accessors (layouts in ppt_internal.h).
+DEV float4* ray_rec(const PathState& S, int i) { return S.ray + (size_t)i * RAY_F4; }
+DEV float4* shd_rec(const PathState& S, int i) { return S.shd + (size_t)i * SHD_F4; }
+DEV float4* acc_rec(const PathState& S, int i) { return S.acc + (size_t)i * ACC_F4; }
+DEV float4* cache_rec(const PathState& S, int Q, int b0, int i) {  // b0: 0-based vertex index
+    return S.cache + ((size_t)b0 * Q + i) * CACHE_F4;
+}
+DEV float4 f4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+DEV void ld12(const float4* r, float* v) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { float4 t = r[k]; v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w; }
+}
+DEV void st12(float4* r, const float* v) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = f4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+}
+// ray record: origin and direction ([0], [1].xy); keys in [3]
+DEV void ray_od(const float4* R, v3& o, v3& d) {
+    float4 a = R[0], b = R[1];
+    o = mk(a.x, a.y, a.z);
+    d = mk(a.w, b.x, b.y);
+}
+DEV void ray_set(float4* R, v3 o, v3 d) {
+    R[0] = f4(o.x, o.y, o.z, d.x);
+    R[1] = f4(d.y, d.z, 0.0f, 0.0f);
+}
 
 constexpr int INFO_DEAD = 1 << 9;
 DEV int info_make(int nverts, bool prev_delta, int view) { return nverts | (prev_delta ? 256 : 0) | (view << 12); }
@@ -117,7 +187,6 @@ __global__ void k_reset_counts(int* counts) {
 // Camera rays of the chunk's paths (masked paths are marked and skipped by the first bounce).
 __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
     PathState& S = A.S;
-    const int Q = A.Q;
     Count cnt;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
         int64_t g = A.g0 + i;
@@ -126,11 +195,10 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
         bool live = !(A.mask && !A.mask[g]);
         v3 o, d;
         camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
-        st_v3(S.ro, Q, i, o);
-        st_v3(S.rd, Q, i, d);
-        S.info[i] = info_make(0, false, id.v) | (live ? 0 : INFO_DEAD);
-        S.pix[i] = id.pix;
-        S.smp[i] = id.smp;
+        float4* R = ray_rec(S, i);
+        ray_set(R, o, d);
+        R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
+                  __uint_as_float(id.smp), 0.0f);
         if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
         if (live) ++cnt.c[ST_PATHS];
     }
@@ -138,30 +206,48 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
 }
 
 // ============================================================================ traversal kernels
+// Persistent traversal: each lane traces one ray at a time and takes the next queued ray as soon
+// as its own is finished, so rays of very different cost share a wavefront without idling.
+// counts[5] / counts[6] are the fetch counters of k_extend / k_shadow; each kernel clears the
+// other's for its next launch (the chunk start clears both).
 __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
     extern __shared__ int lds_stack[];
     int* stack = lds_stack + threadIdx.x;
     PathState& S = A.S;
-    const int Q = A.Q;
     if (blockIdx.x == 0 && threadIdx.x == 0) {  // the queues the following shade kernel appends to
         S.counts[1 - A.qin] = 0;
         S.counts[2] = 0;
+        S.counts[6] = 0;
     }
     const int* q = A.qin ? S.queue1 : S.queue0;
     const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    if (!fetch_active(n)) return;
     Count cnt;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-        int slot = A.first ? i : q[i];
-        int info = S.info[slot];
-        if (info & INFO_DEAD) continue;
-        int v = info >> 12;
-        const DevWorld& W = A.worlds[A.views[v].world];
-        Hit h;
-        ++cnt.c[ST_RAYS];
-        trace<false>(W, ld_v3(S.ro, Q, slot), ld_v3(S.rd, Q, slot), 3.0e38f, h, cnt.c[ST_NODES], cnt.c[ST_PRIMS],
-                     stack);
-        S.hprim[slot] = h.prim;
-        S.ht[slot] = h.t; S.hu[slot] = h.u; S.hv[slot] = h.v;
+    WaveFetch F(n);
+    Trav T;
+    bool alive = false;
+    int slot = -1;
+    while (true) {
+        const int idx = F.take(!alive, n, &S.counts[5]);
+        if (idx >= 0) {
+            slot = A.first ? idx : q[idx];
+            const float4* R = ray_rec(S, slot);
+            const int info = __float_as_int(R[3].x);
+            if (!(info & INFO_DEAD)) {
+                v3 o, d;
+                ray_od(R, o, d);
+                trav_begin(T, A.worlds[A.views[info >> 12].world], o, d, 3.0e38f);
+                alive = true;
+                ++cnt.c[ST_RAYS];
+            }
+        }
+        if (!__any(alive) && !F.more()) break;
+        if (alive && trav_round<false>(T, cnt.c[ST_NODES], cnt.c[ST_PRIMS], stack)) {
+            float4* R = ray_rec(S, slot);
+            ((float2*)(R + 1))[1] = make_float2(T.h.t, T.h.u);
+            ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
+            alive = false;
+        }
     }
     flush_stats(A.stats, cnt);
 }
@@ -172,31 +258,45 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
     int* stack = lds_stack + threadIdx.x;
     PathState& S = A.S;
     const int Q = A.Q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.counts[5] = 0;
     const int n = S.counts[2];
+    if (!fetch_active(n)) return;
     Count cnt;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-        int slot = S.squeue[i];
-        int info = S.info[slot];
-        const DevWorld& W = A.worlds[A.views[info >> 12].world];
-        Hit h;
-        ++cnt.c[ST_SHADOW_RAYS];
-        bool occ = trace<true>(W, ld_v3(S.so, Q, slot), ld_v3(S.sd, Q, slot), S.stmax[slot], h, cnt.c[ST_SHADOW_NODES],
-                               cnt.c[ST_SHADOW_PRIMS], stack);
-        if (MODE == 0) {
-            if (!occ)
-#pragma unroll
-                for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] += S.pend[k * Q + slot];
-        } else {
-            int b = (info & 255) - 1;  // the vertex whose light sample this is
-            float* C = S.cache + (size_t)b * CACHE_WORDS * Q;
-            if (!occ)
-#pragma unroll
-                for (int k = 0; k < 12; ++k) C[(CW_E + k) * Q + slot] += S.pend[k * Q + slot];
-            uint32_t hw = (uint32_t)__float_as_int(C[CW_HIT * Q + slot]);
-            hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
-            C[CW_HIT * Q + slot] = __int_as_float((int)hw);
+    WaveFetch F(n);
+    Trav T;
+    bool alive = false;
+    int slot = -1, info = 0;
+    while (true) {
+        const int idx = F.take(!alive, n, &S.counts[6]);
+        if (idx >= 0) {
+            slot = S.squeue[idx];
+            info = __float_as_int(ray_rec(S, slot)[3].x);
+            const float4* H = shd_rec(S, slot);
+            const float4 s0 = H[0], s1 = H[1];
+            trav_begin(T, A.worlds[A.views[info >> 12].world], mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
+            alive = true;
+            ++cnt.c[ST_SHADOW_RAYS];
         }
-        if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
+        if (!__any(alive) && !F.more()) break;
+        if (alive && trav_round<true>(T, cnt.c[ST_SHADOW_NODES], cnt.c[ST_SHADOW_PRIMS], stack)) {
+            alive = false;
+            const bool occ = T.h.prim >= 0;
+            const float4* H = shd_rec(S, slot);
+            float4* dst = MODE == 0 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+            if (!occ)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float4 a = dst[k], p = H[2 + k];
+                    dst[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
+                }
+            if (MODE == 1) {  // record the visibility in the hit word of the vertex whose light sample this is
+                float* hwp = &cache_rec(S, Q, (info & 255) - 1, slot)[2].w;
+                uint32_t hw = (uint32_t)__float_as_int(*hwp);
+                hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
+                *hwp = __int_as_float((int)hw);
+            }
+            if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
+        }
     }
     flush_stats(A.stats, cnt);
 }
@@ -219,23 +319,27 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
         bool cont = false, shadow = false;
         int slot = 0;
         if (i < n) slot = A.first ? i : qin[i];
-        if (i < n && !(S.info[slot] & INFO_DEAD)) {
-            int info = S.info[slot];
+        const float4* R = ray_rec(S, slot);
+        const float4 r3 = i < n ? R[3] : f4(__int_as_float(INFO_DEAD), 0.0f, 0.0f, 0.0f);
+        const int info = __float_as_int(r3.x);
+        if (!(info & INFO_DEAD)) {
             int nb = info & 255, v = info >> 12;
             bool prev_delta = (info >> 8) & 1;
             int64_t g = A.g0 + slot;
-            const uint32_t pix = S.pix[slot], smp = S.smp[slot];
+            const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
             const DevView& V = A.views[v];
             const DevWorld& W = A.worlds[V.world];
+            const float4 r0 = R[0], r1 = R[1], r2 = R[2];
             Hit h;
-            h.prim = S.hprim[slot];
-            h.t = S.ht[slot]; h.u = S.hu[slot]; h.v = S.hv[slot];
-            v3 o = ld_v3(S.ro, Q, slot), d = ld_v3(S.rd, Q, slot);
+            h.prim = __float_as_int(r2.y);
+            h.t = r1.z; h.u = r1.w; h.v = r2.x;
+            v3 o = mk(r0.x, r0.y, r0.z), d = mk(r0.w, r1.x, r1.y);
             if (h.prim < 0) {
                 if (A.sig) sig_add(A.sig[g], 0xffffffffu);
-                if (MODE == 0 && nb == 0)
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] = 0.0f;
+                if (MODE == 0 && nb == 0) {
+                    float4* AC = acc_rec(S, slot);
+                    AC[5] = AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
             } else {
                 int b = nb + 1;
                 ++cnt.c[ST_VERTICES];
@@ -256,7 +360,9 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                 eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
                 cont = x.lobe != LOBE_NONE && x.lobe != LOBE_INVALID;
                 shadow = x.nee == NEE_PENDING;
+                float4* H = shd_rec(S, slot);
                 if (MODE == 0) {
+                    float4* AC = acc_rec(S, slot);
                     float beta[16], brgb[3], Lo[12];
                     if (nb == 0) {  // first vertex: beta = I, no radiance yet
 #pragma unroll
@@ -267,13 +373,16 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                         for (int k = 0; k < 12; ++k) Lo[k] = 0.0f;
                     } else {
 #pragma unroll
-                        for (int k = 0; k < 16; ++k) beta[k] = S.beta[k * Q + slot];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) brgb[c] = S.beta[(16 + c) * Q + slot];
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) Lo[k] = S.Lo[k * Q + slot];
+                        for (int k = 0; k < 4; ++k) {
+                            float4 t = AC[k];
+                            beta[4 * k] = t.x; beta[4 * k + 1] = t.y; beta[4 * k + 2] = t.z; beta[4 * k + 3] = t.w;
+                        }
+                        float4 t = AC[4];
+                        brgb[0] = t.x; brgb[1] = t.y; brgb[2] = t.z;
+                        ld12(AC + 5, Lo);
                     }
                     // Lo_c += brgb_c beta Ee_c; the pending next-event part likewise
+                    float pn[12];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -281,15 +390,13 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                             float se = beta[4 * r] * Ee[4 * c] + beta[4 * r + 1] * Ee[4 * c + 1] +
                                        beta[4 * r + 2] * Ee[4 * c + 2] + beta[4 * r + 3] * Ee[4 * c + 3];
                             Lo[4 * c + r] += brgb[c] * se;
-                            if (shadow) {
-                                float sn = beta[4 * r] * En[4 * c] + beta[4 * r + 1] * En[4 * c + 1] +
-                                           beta[4 * r + 2] * En[4 * c + 2] + beta[4 * r + 3] * En[4 * c + 3];
-                                S.pend[(4 * c + r) * Q + slot] = brgb[c] * sn;
-                            }
+                            float sn = beta[4 * r] * En[4 * c] + beta[4 * r + 1] * En[4 * c + 1] +
+                                       beta[4 * r + 2] * En[4 * c + 2] + beta[4 * r + 3] * En[4 * c + 3];
+                            pn[4 * c + r] = brgb[c] * sn;
                         }
                     }
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) S.Lo[k * Q + slot] = Lo[k];
+                    if (shadow) st12(H + 2, pn);
+                    st12(AC + 5, Lo);
                     if (cont) {
                         if (w.kind == 1) {
 #pragma unroll
@@ -305,35 +412,26 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                             }
                         }
 #pragma unroll
-                        for (int k = 0; k < 16; ++k) S.beta[k * Q + slot] = beta[k];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) S.beta[(16 + c) * Q + slot] = brgb[c] * w.rgb[c];
+                        for (int k = 0; k < 4; ++k) AC[k] = f4(beta[4 * k], beta[4 * k + 1], beta[4 * k + 2], beta[4 * k + 3]);
+                        AC[4] = f4(brgb[0] * w.rgb[0], brgb[1] * w.rgb[1], brgb[2] * w.rgb[2], 0.0f);
                     }
                 } else {
-                    float* C = S.cache + (size_t)(b - 1) * CACHE_WORDS * Q;
-                    C[0 * Q + slot] = w.rgb[0]; C[1 * Q + slot] = w.rgb[1]; C[2 * Q + slot] = w.rgb[2];
-                    C[3 * Q + slot] = w.A; C[4 * Q + slot] = w.B; C[5 * Q + slot] = w.C; C[6 * Q + slot] = w.D;
-                    C[7 * Q + slot] = w.ci; C[8 * Q + slot] = w.si; C[9 * Q + slot] = w.co; C[10 * Q + slot] = w.so;
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) C[(CW_E + k) * Q + slot] = Ee[k];
-                    if (shadow)
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) S.pend[k * Q + slot] = En[k];
+                    float4* C = cache_rec(S, A.Q, b - 1, slot);
                     bool sphere = __float_as_int(W.prims[3 * h.prim + 1].w) != 0;
-                    C[CW_HIT * Q + slot] = __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29));
-                    C[(CW_HIT + 1) * Q + slot] = sphere ? h.t : h.u;
-                    C[(CW_HIT + 2) * Q + slot] = h.v;
+                    C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
+                    C[1] = f4(w.B, w.C, w.D, w.ci);
+                    C[2] = f4(w.si, w.co, w.so, __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29)));
+                    C[3] = f4(sphere ? h.t : h.u, h.v, 0.0f, 0.0f);
+                    st12(C + 4, Ee);
+                    if (shadow) st12(H + 2, En);
                 }
                 if (shadow) {
-                    st_v3(S.so, Q, slot, so);
-                    st_v3(S.sd, Q, slot, sd);
-                    S.stmax[slot] = stmax;
+                    H[0] = f4(so.x, so.y, so.z, stmax);
+                    H[1] = f4(sd.x, sd.y, sd.z, 0.0f);
                 }
-                if (cont) {
-                    st_v3(S.ro, Q, slot, spawn(x.p, x.ng, x.wi));
-                    st_v3(S.rd, Q, slot, x.wi);
-                }
-                S.info[slot] = info_make(b, is_delta(W.mats[x.mat].type), v);
+                float4* Rw = ray_rec(S, slot);
+                if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi);
+                Rw[3].x = __int_as_float(info_make(b, is_delta(W.mats[x.mat].type), v));
             }
         }
         bq_push(qn, cont, slot);
@@ -354,7 +452,6 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
 __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
     if (!A.out) return;  // signature-only runs produce no image
     PathState& S = A.S;
-    const int Q = A.Q;
     Call K{A.table, nullptr};
     const int lane = lane_id();
     for (int base = blockIdx.x * BLOCK + (threadIdx.x & ~(WAVE - 1)); base < A.n_chunk; base += gridDim.x * BLOCK) {
@@ -367,10 +464,11 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
         int v = 0, lx = 0, ly = 0;
         if (valid) {
             // pixel of the path from its stored keys; the segment key is (view, pixel)
-            const int info = S.info[i];
+            const float4 r3 = ray_rec(S, i)[3];
+            const int info = __float_as_int(r3.x);
             v = info >> 12;
             const DevView& V = A.views[v];
-            const uint32_t pix = S.pix[i], smp = S.smp[i];
+            const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
             lx = px - V.crop_x0; ly = py - V.crop_y0;
             key = ((int64_t)v << 32) | (int64_t)pix;
@@ -380,13 +478,15 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
                 v3 kc = -d;
                 float Cs, Ss;
                 rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
+                float Lo[12];
+                ld12(acc_rec(S, i) + 5, Lo);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    float l1 = S.Lo[(4 * c + 1) * Q + i], l2 = S.Lo[(4 * c + 2) * Q + i];
-                    acc[4 * c] = S.Lo[(4 * c) * Q + i];
+                    float l1 = Lo[4 * c + 1], l2 = Lo[4 * c + 2];
+                    acc[4 * c] = Lo[4 * c];
                     acc[4 * c + 1] = Cs * l1 + Ss * l2;
                     acc[4 * c + 2] = -Ss * l1 + Cs * l2;
-                    acc[4 * c + 3] = S.Lo[(4 * c + 3) * Q + i];
+                    acc[4 * c + 3] = Lo[4 * c + 3];
                 }
             }
         }
@@ -458,43 +558,36 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
     for (int base = r0; base < r1; base += BLOCK) {
         const int i = base + threadIdx.x;
         bool push = false;
-        const int info = i < r1 ? S.info[i] : INFO_DEAD;
+        const float4 r3 = i < r1 ? ray_rec(S, i)[3] : f4(__int_as_float(INFO_DEAD), 0.0f, 0.0f, 0.0f);
+        const int info = __float_as_int(r3.x);
         const int B = (info & INFO_DEAD) ? 0 : (info & 255);
-        // the fold runs over wave-uniform record indices, so the record base stays scalar
-        const int Bw = wave_max_i(B);
         const int v = info >> 12;
         float gt = 0.0f;
         if (B > 0) {
             push = true;
-            const uint32_t pix = S.pix[i], smp = S.smp[i];
-            // fold (records B-1 .. 0).  Each record is loaded whole before any arithmetic so that
-            // its loads are in flight together; record 0 keeps E_1 (the replay reads L[b+1], b >= 1).
+            const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
+            // fold (records B-1 .. 0), record 0 keeps E_1 (the replay reads L[b+1], b >= 1)
             float L[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) L[k] = 0.0f;
-            const uint32_t boff = (uint32_t)i * 4u;
-#pragma unroll 1
-            for (int b = Bw - 1; b >= 0; --b) {
-                if (b >= B) continue;
-                float* C = S.cache + (size_t)b * CACHE_WORDS * Q;
-                float r[CW_HIT + 1];
-#pragma unroll
-                for (int k = 0; k <= CW_HIT; ++k) r[k] = ld_off(C + (size_t)k * Q, boff);
+            for (int b = B - 1; b >= 0; --b) {
+                float4* C = cache_rec(S, Q, b, i);
+                const float4 c0 = C[0], c1 = C[1], c2 = C[2];
+                float e[12];
+                ld12(C + 4, e);
                 WC w;
-                w.rgb[0] = r[0]; w.rgb[1] = r[1]; w.rgb[2] = r[2];
-                w.A = r[3]; w.B = r[4]; w.C = r[5]; w.D = r[6];
-                w.ci = r[7]; w.si = r[8]; w.co = r[9]; w.so = r[10];
-                w.kind = (__float_as_int(r[CW_HIT]) >> 29) & 3;
+                w.rgb[0] = c0.x; w.rgb[1] = c0.y; w.rgb[2] = c0.z;
+                w.A = c0.w; w.B = c1.x; w.C = c1.y; w.D = c1.z;
+                w.ci = c1.w; w.si = c2.x; w.co = c2.y; w.so = c2.z;
+                w.kind = (__float_as_int(c2.w) >> 29) & 3;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     float o4[4];
                     w_apply_select(w, c, L + 4 * c, o4);
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) L[4 * c + k] = r[CW_E + 4 * c + k] + o4[k];
+                    for (int k = 0; k < 4; ++k) L[4 * c + k] = e[4 * c + k] + o4[k];
                 }
-                if (b > 0)
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) st_off(C + (size_t)(CW_E + k) * Q, boff, L[k]);
+                if (b > 0) st12(C + 4, L);
             }
             // pixel of the path from its stored keys (no index arithmetic over the batch)
             const DevView& V = A.views[v];
@@ -532,16 +625,17 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
                     }
                 }
             }
+            float av[12];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float a1 = asens[4 * c + 1], a2 = asens[4 * c + 2];
-                S.pend[(4 * c) * Q + i] = asens[4 * c];
-                S.pend[(4 * c + 1) * Q + i] = Cs * a1 - Ss * a2;
-                S.pend[(4 * c + 2) * Q + i] = Ss * a1 + Cs * a2;
-                S.pend[(4 * c + 3) * Q + i] = asens[4 * c + 3];
+                av[4 * c] = asens[4 * c];
+                av[4 * c + 1] = Cs * a1 - Ss * a2;
+                av[4 * c + 2] = Ss * a1 + Cs * a2;
+                av[4 * c + 3] = asens[4 * c + 3];
             }
-            st_v3(S.ro, Q, i, o);
-            st_v3(S.rd, Q, i, d);
+            st12(shd_rec(S, i) + 2, av);
+            ray_set(ray_rec(S, i), o, d);
             if (pol) {
                 if (tkey != v) {
                     if (tkey >= 0) K.g(A.views[tkey].theta_slot, A.views[tkey].theta_off, gtheta);
@@ -571,10 +665,8 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
 // ============================================================================ backward: replay
 // Persistent replay of the queued paths from their hit records (no second traversal): every lane
 // replays one vertex per iteration and takes the next queued path as soon as its own ends, so
-// short and long paths share a wavefront without idling (wavefronts grab batches of queue entries
-// with one atomic).  At vertex b the lane differentiates E_b + W_b L[b+1] against its adjoint rows,
+// short and long paths share a wavefront without idling.  At vertex b the lane differentiates E_b + W_b L[b+1] against its adjoint rows,
 // then advances them, a <- a W_b.  Gradients go to workgroup LDS accumulators, flushed at the end.
-constexpr int REPLAY_BATCH = 4 * WAVE;
 __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
@@ -586,11 +678,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     for (int k = threadIdx.x; k < A.lds_nf; k += BLOCK) K.lds_f[k] = 0.0f;
     __syncthreads();
     const int n = S.counts[3];
-    int* grab = &S.counts[4];
-    const int lane = lane_id();
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    int c = 0, cend = 0;  // the wavefront's current batch of queue entries [c, cend)
-    bool exhausted = false;
+    WaveFetch F(n);
     int slot = -1, b = 0, B = 0, v = 0;
     uint32_t pix = 0, smp = 0;
     bool prev_delta = false;
@@ -600,52 +688,32 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     for (int k = 0; k < 12; ++k) av[k] = 0.0f;
     while (true) {
         // hand queue entries to the lanes without a path
-        const bool need = slot < 0;
-        const unsigned long long m = __ballot(need);
-        const int k = (int)__popcll(m), rank = (int)__popcll(m & lt);
-        const int rem = cend - c;
-        int nb = -1;
-        if (k > rem && !exhausted) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(grab, REPLAY_BATCH);
-            nb = __builtin_amdgcn_readfirstlane(__shfl(base, 0, WAVE));
-        }
-        int idx = -1;
-        if (need) {
-            if (rank < rem) idx = c + rank;
-            else if (nb >= 0 && nb + (rank - rem) < min(nb + REPLAY_BATCH, n)) idx = nb + (rank - rem);
-        }
-        if (nb >= 0) {
-            if (nb >= n) { exhausted = true; c = cend = 0; }
-            else { cend = min(nb + REPLAY_BATCH, n); c = min(nb + (k - rem), cend); }
-        } else {
-            c = min(c + k, cend);
-        }
+        const int idx = F.take(slot < 0, n, &S.counts[4]);
         if (idx >= 0) {
             slot = S.queue0[idx];
-            const int info = S.info[slot];
+            const float4* R = ray_rec(S, slot);
+            const float4 r3 = R[3];
+            const int info = __float_as_int(r3.x);
             B = info & 255;
             v = info >> 12;
             b = 1;
             prev_delta = false;
-            pix = S.pix[slot];
-            smp = S.smp[slot];
-#pragma unroll
-            for (int q = 0; q < 12; ++q) av[q] = S.pend[q * Q + slot];
-            o = ld_v3(S.ro, Q, slot);
-            d = ld_v3(S.rd, Q, slot);
+            pix = __float_as_uint(r3.y);
+            smp = __float_as_uint(r3.z);
+            ld12(shd_rec(S, slot) + 2, av);
+            ray_od(R, o, d);
         }
         if (!__any(slot >= 0)) break;
         if (slot >= 0) {
             const DevView& V = A.views[v];
             const DevWorld& W = A.worlds[V.world];
-            const float* C = S.cache + (size_t)(b - 1) * CACHE_WORDS * Q;
-            uint32_t hw = (uint32_t)__float_as_int(C[CW_HIT * Q + slot]);
+            const float4* C = cache_rec(S, Q, b - 1, slot);
+            const float4 c2 = C[2], c3 = C[3];
+            uint32_t hw = (uint32_t)__float_as_int(c2.w);
             Hit h;
             h.prim = (int)(hw & ((1u << 26) - 1));
             int rec_nee = (int)((hw >> 26) & 7);
-            float hu = C[(CW_HIT + 1) * Q + slot];
-            h.u = hu; h.t = hu; h.v = C[(CW_HIT + 2) * Q + slot];
+            h.u = c3.x; h.t = c3.x; h.v = c3.y;
             Vtx x;
             surface(W, h, o, d, x);
             v3 so, sd;
@@ -654,9 +722,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             if (x.nee == NEE_PENDING) x.nee = rec_nee;
             float Ln[12];
             if (b < B) {
-                const float* Cn = C + (size_t)CACHE_WORDS * Q;
-#pragma unroll
-                for (int q = 0; q < 12; ++q) Ln[q] = Cn[(CW_E + q) * Q + slot];
+                ld12(cache_rec(S, Q, b, slot) + 4, Ln);
             } else {
 #pragma unroll
                 for (int q = 0; q < 12; ++q) Ln[q] = 0.0f;

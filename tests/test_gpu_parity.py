@@ -73,3 +73,17 @@ def test_c2_crop_parity_full_spp_depth():
     wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)  # ragged: 2 x 2 tiles, partially filled
     res = run(wl, pixel_grad_slots=("theta", "roughness", "ior", "cond_n", "cond_k"))
     _check(res, gate_groups=("albedo_tex", "light_Le"))
+
+
+def test_c5_uneven_multiworld_crops():
+    # eight seeded worlds (terrain of 1e5..1e6 triangles + icospheres), four analyzers, depth 12,
+    # uneven resolutions and spp; the central 32x32 crop of every view in one batched plan.
+    # dL/dI weights the analyzer intensities (s0 of every analyzer output) positively, so each
+    # aggregate gradient group sums contributions without sign cancellation.
+    wl = sg.config5(crop=(32, 32))
+    n = sg.image_numel(wl.views)
+    w = np.random.default_rng(505).uniform(0.5, 1.5, n).astype(np.float32)
+    d = np.where(np.arange(n) % 4 == 0, w, 0.0).astype(np.float32)
+    res = run(wl, d=d, oracle_mode=oracle.MODE_CACHED_PRB)
+    _check(res)
+    assert len(res["grad_rel"]) == len(wl.scene.slot_names)
