@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_device.h",
                   "paper_2607_13265_amd/csrc/ppt_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_{}.md")
-KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "shadow": "ppt::k_shadow",
+KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "shadow": "ppt::k_shadow", "compact": "ppt::k_compact",
                  "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}
 
 
@@ -86,9 +86,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=32, help="full views in the oracle sample")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
-    ap.add_argument("--workload", choices=("batched128", "uneven8", "optimise"), default="batched128",
+    ap.add_argument("--workload", choices=("batched128", "uneven8", "optimise", "depth_sweep"), default="batched128",
                     help="batched128: 128 views of one scene (the headline); uneven8: eight worlds of uneven size; "
-                         "optimise: Adam recovery of textures and lights through the autograd wrapper")
+                         "optimise: Adam recovery of textures and lights through the autograd wrapper; "
+                         "depth_sweep: time and memory against the maximum depth behind an 85-sheet polarizer stack")
     ap.add_argument("--opt-steps", type=int, default=200)
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--spp", type=int, default=32)
@@ -189,6 +190,57 @@ def optimise(args, torch, ppt, sg, dev):
             f.write(line + "\n")
 
 
+def depth_sweep(args, torch, ppt, sg, dev):
+    """Render + PRB backward (gradient of the floor albedo) of the 1280x720, 1 spp scene behind 85
+    polarizer sheets for maximum depths 1..128: time, vertices, workspace and peak device memory,
+    with all paths in one chunk and with 128k-path chunks."""
+    rows = []
+    for D in (1, 2, 4, 8, 16, 32, 48, 64, 86, 96, 112, 128):
+        wl = sg.polarizer_stack(max_depth=D)
+        scene = ppt.Scene(wl.scene.to_blob())
+        params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
+        want = [n in wl.grad_slots for n in wl.scene.slot_names]
+        for chunk in (0, 1 << 17):
+            plan = ppt.Plan(scene, wl.views, D, chunk_paths=chunk or wl.n_paths())
+            d = torch.from_numpy(np.random.default_rng(D).standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats(dev)
+            base = torch.cuda.memory_allocated(dev)
+            plan.render(params, wl.seed)
+            plan.backward(params, wl.seed, d, want=want)
+            torch.cuda.synchronize()
+            st = plan.stats(1)
+            plan.set_stats(False)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            tr, tb = [], []
+            for _ in range(3):
+                e0.record()
+                plan.render(params, wl.seed)
+                e1.record()
+                plan.backward(params, wl.seed, d, want=want)
+                e2.record()
+                torch.cuda.synchronize()
+                tr.append(e0.elapsed_time(e1)); tb.append(e1.elapsed_time(e2))
+            rows.append({"max_depth": D, "chunk_paths": plan.launch_info()["chunk_paths"],
+                         "vertices": st["vertices"], "render_ms": round(float(np.median(tr)), 3),
+                         "backward_ms": round(float(np.median(tb)), 3),
+                         "workspace_gb": {"render": round(plan.workspace_bytes(0) / 1e9, 4),
+                                          "backward": round(plan.workspace_bytes(1) / 1e9, 4)},
+                         "peak_gb": round((torch.cuda.max_memory_allocated(dev) - base) / 1e9, 4)})
+            log(f"[depth] {rows[-1]}")
+            del plan
+    res = {"metric": "render + PRB backward time and device memory against the maximum path depth",
+           "workload": "1280x720, 1 spp, 85 linear polarizer sheets (axes 1 degree apart) in front of a Lambertian "
+                       "floor and wall under an area light; gradient of the floor albedo",
+           "rows": rows}
+    line = json.dumps(res)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -212,6 +264,8 @@ def main():
         return
     if args.workload == "optimise":
         return optimise(args, torch, ppt, sg, dev)
+    if args.workload == "depth_sweep":
+        return depth_sweep(args, torch, ppt, sg, dev)
     if args.workload == "batched128":
         wl = sg.config3(res=args.res, spp=args.spp)
         desc = (f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), {args.res}x{args.res}, "

@@ -98,7 +98,7 @@ void ppt_scene_destroy(ppt_scene* scene);
 /* Number of parameter slots; if numel_out is not NULL it receives min(cap, n) element counts. */
 int ppt_scene_slots(const ppt_scene* scene, int32_t* n_slots, int64_t* numel_out, int32_t cap);
 
-/* Fix the views, the maximum path depth (1..64 surface interactions) and the flags of a
+/* Fix the views, the maximum path depth (1..128 surface interactions) and the flags of a
  * family of calls.  All paths of all views form one index space that is processed in chunks
  * of chunk_paths paths (one launch sequence covers the whole batch of views, also views of
  * different worlds, resolutions and sample counts).  views: host array of n_views records. */
@@ -113,9 +113,9 @@ int64_t ppt_plan_image_numel(const ppt_plan* plan);
 int64_t ppt_plan_num_paths(const ppt_plan* plan);
 
 /* Device workspace bytes needed by ppt_render (op = 0) or ppt_backward (op = 1): the
- * structure-of-arrays state of one chunk of paths (for the backward pass including the
- * per-vertex cache of max_depth records per path of the chunk), independent of the total
- * number of paths, and the FP64 gradient accumulators. */
+ * per-path records of one chunk of paths (for the backward pass including the per-vertex cache
+ * of max_depth 128-byte records per path of the chunk), independent of the total number of
+ * paths, and the FP64 gradient accumulators. */
 size_t ppt_plan_workspace_bytes(const ppt_plan* plan, int32_t op);
 
 /* Optional per-path mask (device, one byte per path, NULL = all paths).  A path whose byte is
@@ -160,7 +160,7 @@ int ppt_read_stats(const void* ws, int64_t* out, void* stream);
  * writes, for kernel family k < n, the summed time between an event and the next (ms[k], in
  * milliseconds) and the number of launches (launches[k]).  Families: 0 camera rays,
  * 1 closest-hit traversal, 2 shading, 3 shadow rays, 4 pixel reduction, 5 suffix fold,
- * 6 adjoint replay, 7 setup / clearing / finalization.  Enabling or disabling clears the
+ * 6 adjoint replay, 7 setup / clearing / finalization, 8 hit compaction.  Enabling or disabling clears the
  * records.  Not for use under stream capture; calls on one plan must not overlap while
  * enabled.  Errors: PPT_EINVAL when no timed call of `op` was made, PPT_EDEVICE on HIP errors. */
 int ppt_plan_set_timing(ppt_plan* plan, int32_t enabled);

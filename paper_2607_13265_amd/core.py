@@ -22,7 +22,7 @@ VIEW_DTYPE = np.dtype([
 # counters of ppt_read_stats and kernel families of ppt_plan_kernel_times, in ABI order
 STAT_KEYS = ("vertices", "paths", "nodes", "prim_tests", "shadow_rays", "rays", "shadow_nodes",
              "shadow_prim_tests")
-KERNEL_FAMILIES = ("camera", "extend", "shade", "shadow", "accum", "fold", "replay", "other")
+KERNEL_FAMILIES = ("camera", "extend", "shade", "shadow", "accum", "fold", "replay", "other", "compact")
 
 
 def _stream(stream=None):

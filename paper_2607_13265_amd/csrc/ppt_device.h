@@ -236,7 +236,30 @@ struct Call {
             if (o >= 0) { atomicAdd(lds_f + o + idx, v); return; }
         }
         int64_t o = tab->goff[slot];
-        if (o >= 0) unsafeAtomicAdd(gacc + o + idx, (double)v);
+        if (o >= 0) global_add(gacc + o + idx, v);
+    }
+    // FP64 global accumulation.  Lanes of the wavefront that add to the address of the first
+    // active lane (neighbouring samples landing on the same texel) are summed through readlane
+    // and added by one atomic; the other lanes add their own values.
+    DEV static void global_add(double* a, float v) {
+        const uint64_t ad = (uint64_t)a;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)ad);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(ad >> 32));
+        const bool lead = (uint32_t)ad == lo && (uint32_t)(ad >> 32) == hi;
+        unsigned long long same = __ballot(lead);
+        if (__popcll(same) < 4) { unsafeAtomicAdd(a, (double)v); return; }
+        if (lead) {
+            const int first = __ffsll((long long)same) - 1;
+            float sum = 0.0f;
+            while (same) {
+                const int l = __ffsll((long long)same) - 1;
+                sum += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+                same &= same - 1ull;
+            }
+            if ((int)lane_id() == first) unsafeAtomicAdd(a, (double)sum);
+        } else {
+            unsafeAtomicAdd(a, (double)v);
+        }
     }
 };
 

@@ -429,7 +429,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
 struct WsLayout {
     size_t table, stats, counts, gacc, total;
     int lds_nd = 0, lds_nf = 0;
-    size_t ray, shd, acc, cache, q0, q1, sq;
+    size_t ray, shd, acc, cache, q0, q1, sq, hq;
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -445,7 +445,7 @@ static WsLayout ws_layout(const ppt_plan* p, int op) {
     L.shd = take(SHD_F4 * 16 * Q);
     L.acc = take(op == 0 ? ACC_F4 * 16 * Q : 0);
     L.cache = take(op == 1 ? (size_t)p->max_depth * CACHE_F4 * 16 * Q : 0);
-    L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q);
+    L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q); L.hq = take(4 * Q);
     L.gacc_n = 0;
     if (op == 1)
         for (int64_t n : p->scene->slot_numel) L.gacc_n += n;
@@ -460,7 +460,7 @@ static PathState path_state(void* ws, const WsLayout& L) {
     S.shd = (float4*)(w + L.shd);
     S.acc = (float4*)(w + L.acc);
     S.cache = (float4*)(w + L.cache);
-    S.queue0 = (int*)(w + L.q0); S.queue1 = (int*)(w + L.q1); S.squeue = (int*)(w + L.sq);
+    S.queue0 = (int*)(w + L.q0); S.queue1 = (int*)(w + L.q1); S.squeue = (int*)(w + L.sq); S.hqueue = (int*)(w + L.hq);
     S.counts = (int*)(w + L.counts);
     return S;
 }
@@ -530,7 +530,7 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
                     const ppt_plan_opts* opts, ppt_plan** out) {
     if (!sc || !views || !out || n_views < 1) return fail(PPT_EINVAL, "null argument or no views");
     *out = nullptr;
-    if (max_depth < 1 || max_depth > MAX_DEPTH) return fail(PPT_EUNSUPPORTED, "max_depth must be in [1, 64]");
+    if (max_depth < 1 || max_depth > MAX_DEPTH) return fail(PPT_EUNSUPPORTED, "max_depth must be in [1, 128]");
     if (flags & ~PPT_FLAG_NO_NEE) return fail(PPT_EINVAL, "unknown flags");
     ppt_plan* P = new ppt_plan();
     P->scene = sc;

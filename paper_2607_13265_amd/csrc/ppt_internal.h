@@ -9,7 +9,7 @@ namespace ppt {
 constexpr int MAX_SLOTS = 64;   // parameter tensors per scene
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;      // 4 wavefronts per workgroup
-constexpr int MAX_DEPTH = 64;
+constexpr int MAX_DEPTH = 128;
 constexpr int STACK = 64;       // BVH traversal stack entries per lane
 
 // Per-path records in the workspace (one record per slot, 16-byte vectors; a path touches only
@@ -99,7 +99,7 @@ struct Stats {
 };
 
 // Kernel families for the optional per-launch event timing.
-enum { KF_GEN, KF_EXTEND, KF_SHADE, KF_SHADOW, KF_ACCUM, KF_FOLD, KF_REPLAY, KF_OTHER, KF_COUNT };
+enum { KF_GEN, KF_EXTEND, KF_SHADE, KF_SHADOW, KF_ACCUM, KF_FOLD, KF_REPLAY, KF_OTHER, KF_COMPACT, KF_COUNT };
 // Called before every launch with the family of the kernel about to be launched (may be NULL).
 struct LaunchMarker {
     void (*fn)(void* ctx, int family, hipStream_t s);
@@ -116,7 +116,9 @@ struct PathState {
     int* queue0;    // ray queues (alternating per bounce; queue0 is the replay queue after the fold)
     int* queue1;
     int* squeue;    // shadow-ray queue
-    int* counts;    // 8 ints: queue0, queue1, shadow queue, replay queue sizes; replay grab cursor
+    int* hqueue;    // queue of the rays of this bounce that hit a surface (input of the shading kernel)
+    int* counts;    // 8 ints: sizes of queue0, queue1, the shadow queue, the replay queue; fetch counters of
+                    // the replay, closest-hit and shadow kernels; size of the hit queue
 };
 
 struct WArgs {

@@ -214,10 +214,11 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
     extern __shared__ int lds_stack[];
     int* stack = lds_stack + threadIdx.x;
     PathState& S = A.S;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the queues the following shade kernel appends to
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the queues the following kernels append to
         S.counts[1 - A.qin] = 0;
         S.counts[2] = 0;
         S.counts[6] = 0;
+        S.counts[7] = 0;
     }
     const int* q = A.qin ? S.queue1 : S.queue0;
     const int n = A.first ? A.n_chunk : S.counts[A.qin];
@@ -301,15 +302,51 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
     flush_stats(A.stats, cnt);
 }
 
+// ============================================================================ hit compaction
+// Splits the rays of this bounce: misses end their path here (signature, and the render's empty
+// radiance for a camera ray that escapes), hits go to the hit queue that the shading kernel reads,
+// so its lanes all hold a vertex.
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
+    PathState& S = A.S;
+    const int* qin = A.qin ? S.queue1 : S.queue0;
+    const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    __shared__ BlockQueue qh;
+    if (threadIdx.x == 0) qh.n = 0;
+    __syncthreads();
+    for (int bb = blockIdx.x * BLOCK; bb < n; bb += gridDim.x * BLOCK) {
+        const int i = bb + threadIdx.x;
+        bool hit = false;
+        int slot = 0;
+        if (i < n) {
+            slot = A.first ? i : qin[i];
+            const float4* R = ray_rec(S, slot);
+            const int info = __float_as_int(R[3].x);
+            if (!(info & INFO_DEAD)) {
+                hit = __float_as_int(R[2].y) >= 0;
+                if (!hit) {
+                    if (A.sig) sig_add(A.sig[A.g0 + slot], 0xffffffffu);
+                    if (MODE == 0 && (info & 255) == 0) {
+                        float4* AC = acc_rec(S, slot);
+                        AC[5] = AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+                    }
+                }
+            }
+        }
+        bq_push(qh, hit, slot);
+        bq_flush(qh, &S.counts[7], S.hqueue, false);
+    }
+    bq_flush(qh, &S.counts[7], S.hqueue, true);
+}
+
 // ============================================================================ shading
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
     Call K{A.table, nullptr};
-    const int* qin = A.qin ? S.queue1 : S.queue0;
     int* qout = A.qin ? S.queue0 : S.queue1;
-    const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    const int n = S.counts[7];
     __shared__ BlockQueue qn, qs;
     if (threadIdx.x == 0) { qn.n = 0; qs.n = 0; }
     __syncthreads();
@@ -318,7 +355,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
         int i = bb + threadIdx.x;
         bool cont = false, shadow = false;
         int slot = 0;
-        if (i < n) slot = A.first ? i : qin[i];
+        if (i < n) slot = S.hqueue[i];
         const float4* R = ray_rec(S, slot);
         const float4 r3 = i < n ? R[3] : f4(__int_as_float(INFO_DEAD), 0.0f, 0.0f, 0.0f);
         const int info = __float_as_int(r3.x);
@@ -334,13 +371,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
             h.prim = __float_as_int(r2.y);
             h.t = r1.z; h.u = r1.w; h.v = r2.x;
             v3 o = mk(r0.x, r0.y, r0.z), d = mk(r0.w, r1.x, r1.y);
-            if (h.prim < 0) {
-                if (A.sig) sig_add(A.sig[g], 0xffffffffu);
-                if (MODE == 0 && nb == 0) {
-                    float4* AC = acc_rec(S, slot);
-                    AC[5] = AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
-                }
-            } else {
+            {  // every queued ray hit a surface
                 int b = nb + 1;
                 ++cnt.c[ST_VERTICES];
                 Vtx x;
@@ -845,6 +876,9 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         a.first = b == 1;
         M(KF_EXTEND, s);
         hipLaunchKernelGGL(k_extend, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
+        M(KF_COMPACT, s);
+        if (mode == 0) hipLaunchKernelGGL(k_compact<0>, dim3(gb), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL(k_compact<1>, dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_SHADE, s);
         if (mode == 0) hipLaunchKernelGGL(k_shade<0>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL(k_shade<1>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);

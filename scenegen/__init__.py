@@ -522,6 +522,33 @@ def config5(seeds=range(50, 58), crop=None):
     return Workload("c5_uneven", merged, views, max_depth=12, seed=50, grad_slots=grad)
 
 
+def polarizer_stack(n_sheets: int = 85, width: int = 1280, height: int = 720, spp: int = 1, step_deg: float = 1.0,
+                    max_depth: int = 128) -> Workload:
+    """Deep-path benchmark scene: a Lambertian floor (RGB albedo parameter) and back wall under an
+    area light, seen through a stack of linear polarizer sheets whose axes turn by step_deg from
+    one sheet to the next, so that a camera path crosses n_sheets delta vertices before its first
+    diffuse vertex.  1280x720 at 1 spp by default."""
+    sc = Scene()
+    s_alb = sc.add_slot("floor_albedo", [0.6, 0.5, 0.4])
+    s_wall = sc.add_slot("wall_albedo", [0.7, 0.7, 0.7])
+    s_le = sc.add_slot("light_Le", [20.0, 20.0, 20.0])
+    w = sc.add_world()
+    m_floor = w.add_material(type=MAT_LAMBERT, albedo_slot=s_alb)
+    m_wall = w.add_material(type=MAT_LAMBERT, albedo_slot=s_wall)
+    _ground(w, 0.0, 12.0, m_floor, uv=False)
+    w.add_quad((-12, 0, -3), (24, 0, 0), (0, 12, 0), m_wall)  # back wall facing +z
+    w.add_light((-1.5, 6.0, -1.5), (3.0, 0, 0), (0, 0, 3.0), s_le)  # facing -y (eu x ev = -y)
+    for i in range(n_sheets):
+        z = 6.0 - 4.0 * i / max(n_sheets - 1, 1)
+        a = np.deg2rad(step_deg * i)
+        m = w.add_material(type=MAT_SHEET, axis=(np.cos(a), np.sin(a), 0.0))
+        w.add_quad((-3.0, -1.0, z), (6.0, 0, 0), (0, 6.0, 0), m)
+    views = np.asarray([make_view(0, width, height, spp, (0.0, 2.0, 9.0), (0.0, 1.5, 0.0), (0, 1, 0), 45.0,
+                                  SENSOR_NONE)], VIEW_DTYPE)
+    return Workload("polarizer_stack", sc, views, max_depth=max_depth, seed=7,
+                    grad_slots=("floor_albedo",))
+
+
 # ----------------------------------------------------------------------------- closed-form test scenes
 def emitter_wall_scene(le=10.0, sheets=(), z_light=-5.0, size=50.0):
     """Camera at the origin looking down -z at a huge one-sided emitter; optional polarizer

@@ -191,7 +191,7 @@ def test_plan_and_call_errors():
     bad = wl.views.copy(); bad["theta_slot"] = 9
     with pytest.raises(ppt.PPTError, match="EINVAL"):
         ppt.Plan(scene, bad, 3)
-    for depth in (0, 65):
+    for depth in (0, 129):
         with pytest.raises(ppt.PPTError, match="EUNSUPPORTED"):
             ppt.Plan(scene, wl.views, depth)
     plan = ppt.Plan(scene, wl.views, 3)
@@ -221,7 +221,7 @@ def test_counters_and_kernel_timing():
     st_r, st_b = plan.stats(0), plan.stats(1)
     plan.set_timing(False)
     # launches per family: one per chunk and bounce for the bounce kernels
-    assert tr["extend"][1] == tr["shade"][1] == tr["shadow"][1] == n_chunks * wl.max_depth
+    assert tr["extend"][1] == tr["compact"][1] == tr["shade"][1] == tr["shadow"][1] == n_chunks * wl.max_depth
     assert tr["camera"][1] == tr["accum"][1] == n_chunks and tr["fold"][1] == tr["replay"][1] == 0
     assert tb["fold"][1] == tb["replay"][1] == n_chunks and tb["accum"][1] == 0
     for t in (tr, tb):
@@ -311,3 +311,30 @@ def test_full_size_batched_sampled_parity():
         r = rel(g[s(name)].cpu().numpy(), gr[s(name)], floor=1e-12)
         print(name, r)
         assert r <= GRAD_TOL
+
+
+def test_deep_polarizer_stack_closed_form():
+    # 85 sheets whose axes turn by 1 degree each, in front of an unpolarized emitter wall: the
+    # camera sees Le/2 prod cos^2(1 deg) (Malus along the chain), fully linearly polarized along
+    # the first sheet's axis; 86 vertices per path, past the 64 of the default plans.  The
+    # gradient of the image sum with respect to Le is the image sum over Le.
+    ppt = _ppt()
+    n = 85
+    step = np.deg2rad(1.0)
+    angles = [k * step for k in range(n)]
+    sc, _ = sg.emitter_wall_scene(le=10.0, sheets=tuple(angles), z_light=-(n * 0.05 + 4.0))
+    v = np.asarray([sg.make_view(0, 8, 8, 2, (0, 0, 0), (0, 0, -1), (0, 1, 0), 0.01, sg.SENSOR_NONE)], sg.VIEW_DTYPE)
+    for depth in (n + 1, 128):
+        plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, depth)
+        params = _params(sc)
+        img = plan.render(params, 3).cpu().numpy().reshape(-1, 3, 4)
+        e = 5.0 * np.cos(step) ** (2 * (n - 1))
+        assert np.allclose(img[..., 0], e, rtol=2e-5)
+        assert np.allclose(np.hypot(img[..., 1], img[..., 2]), e, rtol=2e-5)
+        assert np.allclose(img[..., 3], 0.0, atol=1e-6)
+        d = torch.zeros(plan.image_numel, device="cuda")
+        d[0::4] = 1.0
+        g = plan.backward(params, 3, d)[sc.slot("light_Le")].double().sum().item()
+        assert abs(g - img[..., 0].sum() / 10.0) <= 2e-5 * abs(g)
+    plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, n)  # one vertex short of the emitter: black
+    assert float(plan.render(_params(sc), 3).abs().max()) == 0.0
