@@ -28,12 +28,12 @@ METRIC = "Mpath-vertices/s fwd+PRB adjoint; batched vs per-view launch, grad rel
 
 # Algorithmic FP32 operations (an FMA counts 2) per unit of work, read off the kernel source;
 # the design notes itemise them.
-FLOP_NODE = 47          # one two-box BVH node test
+FLOP_NODE = 51          # one two-box BVH node test: 12 FMA + 24 min/max + 3 compares
 FLOP_PRIM = 52          # one Moller-Trumbore triangle test
 FLOP_SHADE = 450        # one vertex in the shading kernel (sampling, Fresnel/GGX weight, next-event setup)
 FLOP_REPLAY = 950       # one vertex of the adjoint replay (re-evaluation + vector-Jacobian products)
 BYTES_FOLD_VERTEX = 144  # fold: 24 cache words read + 12 written back per vertex
-BYTES_FOLD_PATH = 84     # fold: keys read, adjoint rows + camera ray written per folded path
+BYTES_FOLD_PATH = 96     # fold: keys read (16), adjoint rows (48) + camera ray (32) written per folded path
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 64 lanes x FMA x packed)
 PEAK_HBM_GBS = 8000.0
 # files whose content decides whether stored hardware counters still describe the kernels

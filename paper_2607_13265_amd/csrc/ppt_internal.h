@@ -23,7 +23,8 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [0..3] prefix Mueller product beta (16)   [4] beta RGB scales (3)   [5..7] radiance Lo (12)
 //   cache record (backward), one per (vertex b, slot), CACHE_F4 = 8 vectors (128 B):
 //     [0] rgb0 rgb1 rgb2 A   [1] B C D Cin   [2] Sin Cout Sout hitword   [3] u-or-t v - -
-//     [4..6] E_b (12 words), overwritten by the suffix radiance L[b] in the fold
+//     [4..6] E_b (12 words), overwritten by the fold with the suffix radiance beyond the vertex,
+//     L[b+1], which is what the replay of vertex b reads (not stored for a path's last vertex)
 //   hitword = prim | next-event state << 26 | weight kind << 29
 constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8;
 

@@ -243,7 +243,8 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
             }
         }
         if (!__any(alive) && !F.more()) break;
-        if (alive && trav_round<false>(T, cnt.c[ST_NODES], cnt.c[ST_PRIMS], stack)) {
+        const bool refill = F.more();
+        if (alive && trav_round<false>(T, cnt.c[ST_NODES], cnt.c[ST_PRIMS], stack, refill)) {
             float4* R = ray_rec(S, slot);
             ((float2*)(R + 1))[1] = make_float2(T.h.t, T.h.u);
             ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
@@ -279,7 +280,8 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
             ++cnt.c[ST_SHADOW_RAYS];
         }
         if (!__any(alive) && !F.more()) break;
-        if (alive && trav_round<true>(T, cnt.c[ST_SHADOW_NODES], cnt.c[ST_SHADOW_PRIMS], stack)) {
+        const bool refill = F.more();
+        if (alive && trav_round<true>(T, cnt.c[ST_SHADOW_NODES], cnt.c[ST_SHADOW_PRIMS], stack, refill)) {
             alive = false;
             const bool occ = T.h.prim >= 0;
             const float4* H = shd_rec(S, slot);
@@ -570,7 +572,8 @@ DEV void w_apply_select(const WC& w, int c, const float* in, float* out) {
 }
 
 // Per path with at least one vertex: folds the cache into the suffix radiance
-// L[b] = E_b + W_b L[b+1] (written over E_b), adds the polarizer-angle term delta^T (dP/dtheta) R_s L[1],
+// L[b] = E_b + W_b L[b+1] (L[b+1] written over E_b), adds the polarizer-angle term
+// delta^T (dP/dtheta) R_s L[1],
 // and sets up the replay: the adjoint rows a_c = (delta^T A / spp) R_s (into `pend`), the camera ray
 // (into ro/rd) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
 // contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
@@ -597,7 +600,9 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
         if (B > 0) {
             push = true;
             const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
-            // fold (records B-1 .. 0), record 0 keeps E_1 (the replay reads L[b+1], b >= 1)
+            // fold over records B-1 .. 0 (record r holds vertex r+1): the record's E words receive
+            // the suffix beyond its vertex, L[r+2], so the replay of a vertex reads one record (the
+            // last vertex's suffix is zero and is not stored)
             float L[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) L[k] = 0.0f;
@@ -606,6 +611,7 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
                 const float4 c0 = C[0], c1 = C[1], c2 = C[2];
                 float e[12];
                 ld12(C + 4, e);
+                if (b < B - 1) st12(C + 4, L);
                 WC w;
                 w.rgb[0] = c0.x; w.rgb[1] = c0.y; w.rgb[2] = c0.z;
                 w.A = c0.w; w.B = c1.x; w.C = c1.y; w.D = c1.z;
@@ -618,7 +624,6 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) L[4 * c + k] = e[4 * c + k] + o4[k];
                 }
-                if (b > 0) st12(C + 4, L);
             }
             // pixel of the path from its stored keys (no index arithmetic over the batch)
             const DevView& V = A.views[v];
@@ -696,8 +701,9 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
 // ============================================================================ backward: replay
 // Persistent replay of the queued paths from their hit records (no second traversal): every lane
 // replays one vertex per iteration and takes the next queued path as soon as its own ends, so
-// short and long paths share a wavefront without idling.  At vertex b the lane differentiates E_b + W_b L[b+1] against its adjoint rows,
-// then advances them, a <- a W_b.  Gradients go to workgroup LDS accumulators, flushed at the end.
+// short and long paths share a wavefront without idling.  At vertex b the lane differentiates
+// E_b + W_b L[b+1] against its adjoint rows, then advances them, a <- a W_b.  Gradients go to
+// workgroup LDS accumulators, flushed at the end.
 __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
@@ -751,9 +757,9 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             float stmax;
             vertex_setup(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
             if (x.nee == NEE_PENDING) x.nee = rec_nee;
-            float Ln[12];
+            float Ln[12];  // L[b+1], stored in this vertex's record by the fold (zero after the last)
             if (b < B) {
-                ld12(cache_rec(S, Q, b, slot) + 4, Ln);
+                ld12(C + 4, Ln);
             } else {
 #pragma unroll
                 for (int q = 0; q < 12; ++q) Ln[q] = 0.0f;
