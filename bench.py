@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--per-view-steps", type=int, default=2)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=32, help="full views in the oracle sample")
+    ap.add_argument("--cpu-views", type=int, default=48, help="full views in the oracle sample")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
     ap.add_argument("--workload", choices=("batched128", "uneven8", "optimise", "depth_sweep"), default="batched128",
                     help="batched128: 128 views of one scene (the headline); uneven8: eight worlds of uneven size; "

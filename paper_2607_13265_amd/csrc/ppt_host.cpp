@@ -71,6 +71,9 @@ struct BPrim { float lo[3], hi[3], c[3]; };
 struct BNode { float lo[3], hi[3]; int left, right, first, count; };
 
 struct Builder {
+    static constexpr int NB = 16;          // SAH bins per axis
+    static constexpr float C_TRAV = 0.5f;  // cost of a node visit relative to a primitive test
+    static constexpr int MAX_LEAF = 8;     // primitives per leaf (the leaf reference holds count - 1 in 3 bits)
     std::vector<BPrim> prims;
     std::vector<int> idx;
     std::vector<BNode> nodes;
@@ -99,7 +102,6 @@ struct Builder {
         nodes[id].first = first; nodes[id].count = count;
         if (count <= 2) return id;
         // binned SAH over the three axes
-        constexpr int NB = 16;
         float best_cost = 1e30f;
         int best_axis = -1, best_bin = -1;
         for (int a = 0; a < 3; ++a) {
@@ -138,8 +140,8 @@ struct Builder {
             }
         }
         float leaf_cost = area(n.lo, n.hi) * count;
-        float split_cost = best_axis >= 0 ? 0.5f * area(n.lo, n.hi) + best_cost : 1e30f;
-        if (count <= 8 && leaf_cost <= split_cost) return id;
+        float split_cost = best_axis >= 0 ? C_TRAV * area(n.lo, n.hi) + best_cost : 1e30f;
+        if (count <= MAX_LEAF && leaf_cost <= split_cost) return id;
         int mid;
         if (best_axis < 0) {
             mid = first + count / 2;  // all centroids coincide: split the list in half
