@@ -44,6 +44,10 @@ KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "shadow": "
                  "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}
 
 
+def one_or_list(xs):
+    return xs[0] if len(set(xs)) == 1 else xs
+
+
 def kernel_source_digest() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -355,8 +359,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc,
-                   "views": len(wl.views), "resolution": [int(v["width"]) for v in wl.views],
-                   "spp": [int(v["spp"]) for v in wl.views], "max_depth": wl.max_depth,
+                   "views": len(wl.views), "resolution": one_or_list([int(v["width"]) for v in wl.views]),
+                   "spp": one_or_list([int(v["spp"]) for v in wl.views]), "max_depth": wl.max_depth,
                    "vertices_per_step": verts, "paths_per_step": st_r["paths"],
                    "chunk_paths": info["chunk_paths"], "chunks": info["n_chunks"],
                    "autotune_ms": tuned},
