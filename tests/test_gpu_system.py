@@ -338,3 +338,48 @@ def test_deep_polarizer_stack_closed_form():
         assert abs(g - img[..., 0].sum() / 10.0) <= 2e-5 * abs(g)
     plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, n)  # one vertex short of the emitter: black
     assert float(plan.render(_params(sc), 3).abs().max()) == 0.0
+
+
+def test_adam_through_autograd_reduces_loss():
+    # inverse rendering in miniature: recover the config-1 albedo from a target rendered with the
+    # true albedo, through PolarizedRender with a decorrelated backward seed every step
+    ppt = _ppt()
+    wl = sg.config1()
+    plan = ppt.Plan(ppt.Scene(wl.scene.to_blob()), wl.views, wl.max_depth)
+    truth = _params(wl.scene)
+    target = sum(plan.render(truth, 100 + k) for k in range(8)) / 8.0
+    si = wl.scene.slot("albedo")
+    params = [p.clone() for p in truth]
+    params[si] = torch.full_like(truth[si], 0.5).requires_grad_(True)
+    opt = torch.optim.Adam([params[si]], lr=0.05)
+    losses = []
+    for it in range(40):
+        opt.zero_grad()
+        img = ppt.render(plan, params, 1 + it, backward_seed=10_000 + it)
+        loss = (img - target).pow(2).mean()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            params[si].clamp_(0.0, 1.0)
+        losses.append(float(loss.detach()))
+    err0 = float((torch.full_like(truth[si], 0.5) - truth[si]).abs().max())
+    err1 = float((params[si].detach() - truth[si]).abs().max())
+    assert np.mean(losses[-5:]) < np.mean(losses[:5])
+    assert err1 < 0.5 * err0
+
+
+def test_workspace_depends_on_chunk_and_depth_only():
+    # the backward workspace holds one chunk of paths with D cache records each: it grows with
+    # the chunk and the depth, not with the number of views or paths
+    ppt = _ppt()
+    wl = _small_batch(n_views=6)
+    scene = ppt.Scene(wl.scene.to_blob())
+    q = 4096
+    ws = {}
+    for nv in (2, 6):
+        for D in (2, 6):
+            plan = ppt.Plan(scene, wl.views[:nv], D, chunk_paths=q)
+            assert plan.num_paths > q
+            ws[(nv, D)] = plan.workspace_bytes(1)
+    assert ws[(2, 2)] == ws[(6, 2)] and ws[(2, 6)] == ws[(6, 6)]
+    assert abs((ws[(6, 6)] - ws[(6, 2)]) - 4 * q * 128) <= 256
