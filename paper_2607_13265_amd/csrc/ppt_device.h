@@ -221,12 +221,26 @@ DEV float smith_dlnG1(float cw, float a) {
 // Parameter reads and gradient writes of one call.  Gradients go to a workgroup-local LDS
 // accumulator when the slot has one (FP64 for small slots, FP32 for textures), else to the
 // global FP64 accumulator.
+// Reads of device global memory through global-address-space pointers: the loads are global
+// (not flat) loads, whose completion the compiler does not have to wait for together with LDS.
+#define PPT_GLOBAL __attribute__((address_space(1)))
+template <class T>
+DEV T gval(const T* p, size_t i) {
+    static_assert(sizeof(T) % 4 == 0, "records of 32-bit words");
+    T r;
+    const PPT_GLOBAL uint32_t* src = (const PPT_GLOBAL uint32_t*)(p + i);
+    uint32_t* dst = (uint32_t*)&r;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return r;
+}
+
 struct Call {
     const CallTable* tab;
     double* gacc;
     double* lds_d = nullptr;
     float* lds_f = nullptr;
-    DEV float p(int slot, int idx) const { return tab->p[slot][idx]; }
+    DEV float p(int slot, int idx) const { return gval(tab->p[slot], (size_t)idx); }
     DEV void g(int slot, int idx, float v) const {
         if (v == 0.0f) return;
         if (lds_d) {
@@ -510,7 +524,7 @@ DEV bool is_delta(int t) { return t == MAT_DIELECTRIC || t == MAT_SHEET; }
 // Surface data of a hit (identical whether the hit comes from traversal or from a record).
 DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
     const float4* pr = W.prims + 3 * h.prim;
-    float4 A = pr[0], B = pr[1];
+    float4 A = ldg4(pr, 0), B = ldg4(pr, 1);
     x.orig = __float_as_int(A.w);
     if (__float_as_int(B.w) == 0) {
         float4 C = ldg4(pr, 2);
@@ -519,8 +533,8 @@ DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
         x.ng = normalize(cross(e1, e2));
         const float* t = W.tri_uv + 6 * (size_t)x.orig;
         float b0 = 1.0f - h.u - h.v;
-        x.u = b0 * t[0] + h.u * t[2] + h.v * t[4];
-        x.v = b0 * t[1] + h.u * t[3] + h.v * t[5];
+        x.u = b0 * gval(t, 0) + h.u * gval(t, 2) + h.v * gval(t, 4);
+        x.v = b0 * gval(t, 1) + h.u * gval(t, 3) + h.v * gval(t, 5);
     } else {
         x.p = o + d * h.t;
         v3 nout = normalize(x.p - mk(A.x, A.y, A.z));
@@ -528,7 +542,7 @@ DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
         x.u = 0.5f + atan2f(nout.z, nout.x) * (0.5f / PI_F);
         x.v = acosf(fminf(fmaxf(nout.y, -1.0f), 1.0f)) * (1.0f / PI_F);
     }
-    x.mat = W.prim_mat[x.orig];
+    x.mat = gval(W.prim_mat, (size_t)x.orig);
 }
 
 DEV int sample_glossy(v3 ns, v3 wo, float alpha, float u1, float u2, v3& wi, float& pdf) {
@@ -574,7 +588,7 @@ constexpr int NEE_NONE = 0, NEE_VISIBLE = 1, NEE_OCCLUDED = 2, NEE_ZERO = 3, NEE
 DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64_t seed, uint32_t pix, uint32_t smp,
                       int b, int max_depth, uint32_t flags, bool prev_delta, v3 d, Vtx& x, v3& so, v3& sd,
                       float& stmax) {
-    const DevMaterial& m = W.mats[x.mat];
+    const DevMaterial m = gval(W.mats, (size_t)x.mat);
     x.wo = -d;
     x.front = dot(x.ng, x.wo) > 0.0f;
     x.ns = x.front ? x.ng : -x.ng;
@@ -589,7 +603,7 @@ DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64
     if (!is_delta(m.type) && !(flags & FLAG_NO_NEE) && W.n_lights > 0) {
         int nl = W.n_lights;
         int li = min((int)(ua[3] * (float)nl), nl - 1);
-        const DevLight& L = W.lights[li];
+        const DevLight L = gval(W.lights, (size_t)li);
         v3 y = ld3(L.p0) + ld3(L.eu) * ub[0] + ld3(L.ev) * ub[1];
         v3 dv = y - x.p;
         float dist2 = dot(dv, dv), dist = sqrtf(dist2);
@@ -753,7 +767,7 @@ DEV void ggx_backprop(const Vtx& x, cf eta, const GGXv& g, float s, float gA, fl
 template <bool GRAD>
 DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, float* Eemit, float* Enee, const float* a,
                      const float* Ln) {
-    const DevMaterial& m = W.mats[x.mat];
+    const DevMaterial m = gval(W.mats, (size_t)x.mat);
 #pragma unroll
     for (int i = 0; i < 12; ++i) { Eemit[i] = 0.0f; Enee[i] = 0.0f; }
     GradVtx gv;
@@ -768,7 +782,7 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
     }
     // next-event estimation: E_c += f_c e0 * cos_x * geom * Le_c
     if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
-        const DevLight& L = W.lights[x.light];
+        const DevLight L = gval(W.lights, (size_t)x.light);
         float cx = dot(x.ns, x.wl);
         float gs = cx * x.nee_geom;
         float le[3];
@@ -896,7 +910,7 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
         if (m.eta_slot >= 0) K.g(m.eta_slot, m.eta_off, gv.eta);
         if (m.kap_slot >= 0) K.g(m.kap_slot, m.kap_off, gv.kap);
         if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
-            const DevLight& L = W.lights[x.light];
+            const DevLight L = gval(W.lights, (size_t)x.light);
             for (int c = 0; c < 3; ++c) K.g(L.le_slot, L.le_off + c, gv.le[c]);
         }
         if (m.emit_slot >= 0)

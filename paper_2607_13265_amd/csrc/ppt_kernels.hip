@@ -149,6 +149,14 @@ DEV PathId path_id(const DevView* views, int n_views, int64_t g) {
     return r;
 }
 
+// The call table (parameter pointers, gradient routing) is read for every parameter access; a
+// copy in LDS turns those dependent global loads into LDS reads.  All threads call it, followed by
+// a workgroup barrier before first use.
+DEV void table_to_lds(CallTable* dst, const CallTable* src) {
+    const int n = (int)(sizeof(CallTable) / sizeof(int));
+    for (int k = threadIdx.x; k < n; k += BLOCK) ((int*)dst)[k] = ((const int*)src)[k];
+}
+
 // Record accessors (layouts in ppt_internal.h).
 DEV float4* ray_rec(const PathState& S, int i) { return S.ray + (size_t)i * RAY_F4; }
 DEV float4* shd_rec(const PathState& S, int i) { return S.shd + (size_t)i * SHD_F4; }
@@ -237,7 +245,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
             if (!(info & INFO_DEAD)) {
                 v3 o, d;
                 ray_od(R, o, d);
-                trav_begin(T, A.worlds[A.views[info >> 12].world], o, d, 3.0e38f);
+                trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world), o, d, 3.0e38f);
                 alive = true;
                 ++cnt.c[ST_RAYS];
             }
@@ -275,7 +283,8 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
             info = __float_as_int(ray_rec(S, slot)[3].x);
             const float4* H = shd_rec(S, slot);
             const float4 s0 = H[0], s1 = H[1];
-            trav_begin(T, A.worlds[A.views[info >> 12].world], mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
+            trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world), mk(s0.x, s0.y, s0.z),
+                       mk(s1.x, s1.y, s1.z), s0.w);
             alive = true;
             ++cnt.c[ST_SHADOW_RAYS];
         }
@@ -350,6 +359,9 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
     int* qout = A.qin ? S.queue0 : S.queue1;
     const int n = S.counts[7];
     __shared__ BlockQueue qn, qs;
+    __shared__ CallTable tab;
+    table_to_lds(&tab, A.table);
+    K.tab = &tab;
     if (threadIdx.x == 0) { qn.n = 0; qs.n = 0; }
     __syncthreads();
     Count cnt;
@@ -366,8 +378,8 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
             bool prev_delta = (info >> 8) & 1;
             int64_t g = A.g0 + slot;
             const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
-            const DevView& V = A.views[v];
-            const DevWorld& W = A.worlds[V.world];
+            const DevView V = gval(A.views, (size_t)v);
+            const DevWorld W = gval(A.worlds, (size_t)V.world);
             const float4 r0 = R[0], r1 = R[1], r2 = R[2];
             Hit h;
             h.prim = __float_as_int(r2.y);
@@ -450,7 +462,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                     }
                 } else {
                     float4* C = cache_rec(S, A.Q, b - 1, slot);
-                    bool sphere = __float_as_int(W.prims[3 * h.prim + 1].w) != 0;
+                    bool sphere = __float_as_int(ldg4(W.prims, 3 * h.prim + 1).w) != 0;
                     C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
                     C[1] = f4(w.B, w.C, w.D, w.ci);
                     C[2] = f4(w.si, w.co, w.so, __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29)));
@@ -464,7 +476,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                 }
                 float4* Rw = ray_rec(S, slot);
                 if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi);
-                Rw[3].x = __int_as_float(info_make(b, is_delta(W.mats[x.mat].type), v));
+                Rw[3].x = __int_as_float(info_make(b, is_delta(gval(W.mats, (size_t)x.mat).type), v));
             }
         }
         bq_push(qn, cont, slot);
@@ -500,7 +512,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             const float4 r3 = ray_rec(S, i)[3];
             const int info = __float_as_int(r3.x);
             v = info >> 12;
-            const DevView& V = A.views[v];
+            const DevView V = gval(A.views, (size_t)v);
             const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
             lx = px - V.crop_x0; ly = py - V.crop_y0;
@@ -537,7 +549,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
         int64_t knext = __shfl_down(key, 1, WAVE);
         bool tail = valid && (lane == WAVE - 1 || knext != key);
         if (tail) {
-            const DevView& V = A.views[v];
+            const DevView V = gval(A.views, (size_t)v);
             float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
             float inv = 1.0f / (float)V.spp;
             int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
@@ -626,7 +638,7 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
                 }
             }
             // pixel of the path from its stored keys (no index arithmetic over the batch)
-            const DevView& V = A.views[v];
+            const DevView V = gval(A.views, (size_t)v);
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
             const int lx = px - V.crop_x0, ly = py - V.crop_y0;
             v3 o, d;
@@ -709,6 +721,9 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
     Call K{A.table, A.gacc};
+    __shared__ CallTable tab;
+    table_to_lds(&tab, A.table);
+    K.tab = &tab;
     K.lds_d = lds_grad;
     K.lds_f = (float*)(lds_grad + A.lds_nd);
     for (int k = threadIdx.x; k < A.lds_nd; k += BLOCK) K.lds_d[k] = 0.0;
@@ -742,8 +757,8 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
         }
         if (!__any(slot >= 0)) break;
         if (slot >= 0) {
-            const DevView& V = A.views[v];
-            const DevWorld& W = A.worlds[V.world];
+            const DevView V = gval(A.views, (size_t)v);
+            const DevWorld W = gval(A.worlds, (size_t)V.world);
             const float4* C = cache_rec(S, Q, b - 1, slot);
             const float4 c2 = C[2], c3 = C[3];
             uint32_t hw = (uint32_t)__float_as_int(c2.w);
@@ -777,7 +792,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) av[4 * cc + q] = o4[q];
                 }
-                prev_delta = is_delta(W.mats[x.mat].type);
+                prev_delta = is_delta(gval(W.mats, (size_t)x.mat).type);
                 o = spawn(x.p, x.ng, x.wi);
                 d = x.wi;
                 ++b;
