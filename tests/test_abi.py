@@ -50,3 +50,29 @@ def test_view_layout_matches_generators():
     import scenegen as sg
     from paper_2607_13265_amd.core import VIEW_DTYPE
     assert VIEW_DTYPE == sg.VIEW_DTYPE and VIEW_DTYPE.itemsize == 88
+
+
+C_PROGRAM = os.path.join(ROOT, "tests", "c", "abi_render.c")
+
+
+def build_c_program(out_dir):
+    """Compiles the plain-C user of the ABI (tests/c/abi_render.c) against the built library."""
+    import shutil
+    import subprocess
+
+    from paper_2607_13265_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH) or not shutil.which("gcc"):
+        pytest.skip("HIP library not built or no C compiler")
+    exe = os.path.join(str(out_dir), "abi_render")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", C_PROGRAM, "-L", libdir, "-lppt", "-L", "/opt/rocm/lib", "-lamdhip64",
+           f"-Wl,-rpath,{libdir}", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_c_program_builds_against_the_abi(tmp_path):
+    # the ABI is usable from C alone: the header compiles as C99 and the library links
+    assert os.path.exists(build_c_program(tmp_path))

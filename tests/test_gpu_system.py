@@ -383,3 +383,31 @@ def test_workspace_depends_on_chunk_and_depth_only():
             ws[(nv, D)] = plan.workspace_bytes(1)
     assert ws[(2, 2)] == ws[(6, 2)] and ws[(2, 6)] == ws[(6, 6)]
     assert abs((ws[(6, 6)] - ws[(6, 2)]) - 4 * q * 128) <= 256
+
+
+def test_plain_c_caller_matches_binding(tmp_path):
+    # a C program (tests/c/abi_render.c) drives scene creation, render and backward through the
+    # C ABI with its own hipMalloc'ed buffers; its image and gradients equal the binding's
+    import subprocess
+
+    from test_abi import build_c_program
+    ppt = _ppt()
+    exe = build_c_program(tmp_path)
+    wl = sg.config1()
+    blob = wl.scene.to_blob()
+    (tmp_path / "scene.blob").write_bytes(blob)
+    (tmp_path / "views.bin").write_bytes(np.ascontiguousarray(wl.views).tobytes())
+    params = wl.scene.params()
+    (tmp_path / "params.bin").write_bytes(b"".join(np.ascontiguousarray(p, np.float32).tobytes() for p in params))
+    out = tmp_path / "out.bin"
+    r = subprocess.run([exe, str(tmp_path / "scene.blob"), str(tmp_path / "views.bin"), str(tmp_path / "params.bin"),
+                        str(wl.seed), str(wl.max_depth), str(out)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    got = np.fromfile(str(out), np.float32)
+    plan = ppt.Plan(ppt.Scene(blob), wl.views, wl.max_depth)
+    tp = _params(wl.scene)
+    img = plan.render(tp, wl.seed).cpu().numpy()
+    grads = plan.backward(tp, wl.seed, torch.ones(plan.image_numel, device="cuda"))
+    ref = np.concatenate([img] + [g.cpu().numpy() for g in grads])
+    assert got.shape == ref.shape
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-6)
