@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "ppt_oracle.cpp")
 LIB_PATH = os.path.join(_HERE, "libppt_oracle.so")
 
-MODE_RENDER, MODE_TAPE_AD, MODE_CACHED_PRB, MODE_BASIC_PRB = 0, 1, 2, 3
+MODE_RENDER, MODE_TAPE_AD, MODE_CACHED_PRB, MODE_BASIC_PRB, MODE_HYBRID = 0, 1, 2, 3, 4
 FLAG_NO_NEE = 1
 FLAG_GAUGE = 1 << 16
 
@@ -51,7 +51,7 @@ def lib():
         L.ppto_scene_counts.argtypes = [vp, c_int, vp]
         L.ppto_run.restype = c_int
         L.ppto_run.argtypes = [vp, vp, vp, c_int, vp, c_int, c_int, ctypes.c_uint32, c_u64, c_int,
-                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp]
+                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp, c_int]
         L.ppto_philox.argtypes = [c_u64, vp, vp]
         L.ppto_philox_n.argtypes = [c_u64, vp, vp, ctypes.c_int64]
         L.ppto_fresnel.argtypes = [c_dbl, c_dbl, c_dbl, vp, vp]
@@ -103,13 +103,15 @@ class OracleScene:
         return out
 
     def run(self, params, views, max_depth, seed, flags=0, mode=MODE_RENDER, d_image=None, params_val=None,
-            grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0, pixel_grad_slot=None):
+            grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0, pixel_grad_slot=None,
+            ckpt=1):
         """Run the oracle.  ``params`` (and ``params_val``) are per-slot arrays (converted to float64).
 
         Returns a dict with ``image`` (float64, [V][A][h][w][3][4] flattened per view),
         ``grads`` (list per slot, None where not requested), ``sig`` (uint64 per path),
         ``n_vertices`` and ``n_paths``; with ``pixel_grad_slot`` also ``pixel_grad``: that slot's
         gradient split by pixel (the gradient image of Sec. 5.1), one value per (view, crop pixel).
+        ``ckpt``: checkpoint interval k of the hybrid replay (``MODE_HYBRID``).
         """
         from scenegen import VIEW_DTYPE, image_numel  # input-layout helpers only
 
@@ -139,7 +141,8 @@ class OracleScene:
                             None if image is None else _ptr(image), pgr,
                             None if sig is None else _ptr(sig), None if mk is None else _ptr(mk),
                             _ptr(stats), int(nthreads), err, 256,
-                            -1 if pixel_grad_slot is None else int(pixel_grad_slot), None if pg is None else _ptr(pg))
+                            -1 if pixel_grad_slot is None else int(pixel_grad_slot), None if pg is None else _ptr(pg),
+                            int(ckpt))
         if rc != 0:
             raise ValueError("oracle run failed: " + err.value.decode())
         return {"image": image, "grads": grads, "sig": sig, "n_vertices": int(stats[0]), "n_paths": int(stats[1]),

@@ -22,7 +22,12 @@
 //               L[b+1] -- automatic differentiation only inside the loop body (Sec. 3.2);
 //       mode 3  basic polarized PRB (Sec. 4.1, Alg. 2): the suffix is recovered by inverting
 //               the sampled Mueller weight; kept only as the negative control the paper
-//               describes for rank-deficient operators.
+//               describes for rank-deficient operators;
+//       mode 4  hybrid cached replay (Sec. 4.4) with checkpoint interval k: only the suffix
+//               values at vertices 0, k, 2k, ... are kept; any other one is recovered by
+//               recomputing the vertices up to the next checkpoint and folding back from it
+//               (the recomputation branch of Eq. 3, which is exact; the scalar-PRB and
+//               inversion branches need thresholds the text does not give).
 //
 // Conventions that the paper delegates to its renderer (Sec. 3.3) are fixed here as
 // plain textbook definitions (Stokes frames, rotators, Fresnel amplitudes in the Born &
@@ -965,6 +970,7 @@ struct RunArgs {
     uint32_t flags;
     uint64_t seed;
     int mode;
+    int ckpt;                 // hybrid replay (mode 4): checkpoint interval k >= 1
     const double* d_image;
     double* image;
     uint64_t* sig;
@@ -1002,7 +1008,7 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
     const int B = (int)g.v.size();
     std::memset(C, 0, sizeof(double) * 48);
 
-    if (A.mode == 0 || A.mode == 2 || A.mode == 3) {
+    if (A.mode == 0 || A.mode == 2 || A.mode == 3 || A.mode == 4) {
         // primal: per-vertex W_b, E_b; forward sum and backward fold
         std::vector<VEval<double>> ev(B);
         for (int b = 0; b < B; ++b) eval_vertex(w, g.v[b], PVd, ev[b]);
@@ -1045,16 +1051,43 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
                 for (int j = 0; j < 4; ++j)
                     for (int i = 0; i < 4; ++i) av[c][j] += dC[(a * 3 + c) * 4 + i] * S[a].m[i][j];
 
+        // hybrid cached replay (Sec. 4.4): only the suffix values at the checkpoints b = 0, k, 2k, ...
+        // are kept from the fold; the full fold is dropped before the replay
+        const int K = A.ckpt > 0 ? A.ckpt : 1;
+        std::vector<std::array<S4<double>, 3>> Lck;
+        if (A.mode == 4) {
+            for (int b = 0; b < B; b += K) Lck.push_back(L[b]);
+            L.clear();
+        }
+
         // replay: the same RNG stream re-traces the same path
         PathGeom g2;
         trace_path(w, vw, px, py, s, A.seed, A.max_depth, A.flags, PP, g2);
         const int B2 = (int)g2.v.size();
-        // suffix source: cached fold (mode 2) or inversion of the sampled weight (mode 3)
-        std::array<S4<double>, 3> Lcur = L[0];
+        // suffix source: cached fold (mode 2), inversion of the sampled weight (mode 3), or the
+        // next checkpoint folded back over the recomputed vertices in between (mode 4)
+        std::array<S4<double>, 3> Lcur;
+        for (int ch = 0; ch < 3; ++ch) Lcur[ch] = A.mode == 4 ? szero<double>() : L[0][ch];
         for (int b = 0; b < B2; ++b) {
             std::array<S4<double>, 3> Lnext;
             if (A.mode == 2) {
                 Lnext = L[b + 1];
+            } else if (A.mode == 4) {
+                // suffix beyond vertex b: start at the first checkpoint c >= b + 1 (zero past the
+                // last vertex) and recompute L[v] = E_v + W_v L[v+1] for v = c-1 .. b+1
+                const int nb = b + 1;
+                int c = ((nb + K - 1) / K) * K;
+                if (c >= B2) {
+                    c = B2;
+                    for (int ch = 0; ch < 3; ++ch) Lnext[ch] = szero<double>();
+                } else {
+                    Lnext = Lck[c / K];
+                }
+                for (int v = c - 1; v >= nb; --v) {
+                    VEval<double> ev2;
+                    eval_vertex(w, g2.v[v], PVd, ev2);
+                    for (int ch = 0; ch < 3; ++ch) Lnext[ch] = sadd(ev2.E[ch], mvec(ev2.W[ch], Lnext[ch]));
+                }
             } else {
                 bool cont = g2.v[b].lobe != LOBE_NONE && g2.v[b].lobe != LOBE_INVALID;
                 for (int c = 0; c < 3; ++c) {
@@ -1191,12 +1224,13 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
              const void* views_, int n_views, int max_depth, uint32_t flags, uint64_t seed, int mode,
              const double* d_image, double* image_out, double* const* grads_out, uint64_t* sig_out,
              const uint8_t* path_mask, int64_t* stats, int nthreads, char* err, int errlen, int pix_slot,
-             double* pix_grad) {
+             double* pix_grad, int ckpt_interval) {
     Scene* sc = (Scene*)scene;
     const View* views = (const View*)views_;
     if (!sc || n_slots != (int)sc->slot_numel.size()) { set_err(err, errlen, "slot count mismatch"); return -1; }
     if (max_depth < 1 || max_depth > 200) { set_err(err, errlen, "max_depth out of range"); return -1; }
-    if (mode < 0 || mode > 3 || (mode > 0 && !d_image)) { set_err(err, errlen, "bad mode"); return -1; }
+    if (mode < 0 || mode > 4 || (mode > 0 && !d_image)) { set_err(err, errlen, "bad mode"); return -1; }
+    if (mode == 4 && ckpt_interval < 1) { set_err(err, errlen, "checkpoint interval must be >= 1"); return -1; }
     std::vector<int64_t> img_off(n_views + 1, 0), path_off(n_views + 1, 0);
     for (int v = 0; v < n_views; ++v) {
         const View& vw = views[v];
@@ -1215,7 +1249,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
     }
     g_gauge = (flags & FLAG_GAUGE) ? 1 : 0;
     RunArgs A{sc, params_path, params_val ? params_val : params_path, views, n_views, max_depth, flags, seed, mode,
-              d_image, image_out, sig_out, path_mask};
+              ckpt_interval, d_image, image_out, sig_out, path_mask};
     // per-pixel index (view, crop row, crop column) for the gradient-image output
     std::vector<int64_t> pix_off(n_views + 1, 0);
     for (int v = 0; v < n_views; ++v) pix_off[v + 1] = pix_off[v] + (int64_t)views[v].crop_w * views[v].crop_h;

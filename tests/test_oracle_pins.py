@@ -397,3 +397,50 @@ def test_basic_polarized_prb_breaks_down(oracle_lib):
     bad = [not np.all(np.isfinite(g[s(n)])) or not np.allclose(g[s(n)], ref[s(n)], rtol=1e-3)
            for n in ("theta", "albedo")]
     assert any(bad)
+
+
+# ----------------------------------------------------------------------------- hybrid cached replay
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_hybrid_replay_equals_cached_and_tape_c2_crop(oracle_lib, k):
+    # Sec. 4.4 with the recomputation branch of Eq. 3: keeping suffix values only every k vertices
+    # and recomputing the ones in between gives the cached method's gradient exactly (the same
+    # floating-point recursion from a stored checkpoint) and hence conventional AD's
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 120, 150, 6, 5)
+    wl.views["spp"] = 8
+    osc = oracle.OracleScene.from_scene(wl.scene)
+    d = np.random.default_rng(6).normal(size=sg.image_numel(wl.views))
+    p = wl.scene.params()
+    # one thread: the per-thread gradient sums are then added in a fixed order
+    gc = osc.run(p, wl.views, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=d, nthreads=1)["grads"]
+    gh = osc.run(p, wl.views, wl.max_depth, wl.seed, mode=oracle.MODE_HYBRID, d_image=d, ckpt=k, nthreads=1)["grads"]
+    gt = osc.run(p, wl.views, wl.max_depth, wl.seed, mode=oracle.MODE_TAPE_AD, d_image=d)["grads"]
+    for a, b, t in zip(gc, gh, gt):
+        assert np.array_equal(a, b)
+        scale = max(np.abs(t).max(), 1e-30)
+        assert np.allclose(b, t, rtol=1e-9, atol=1e-11 * scale)
+
+
+def test_hybrid_replay_deep_polarizer_stack(oracle_lib):
+    # 85 delta vertices before the first diffuse one: checkpoints every 16 vertices (the deep-path
+    # case the variant is for) still give the cached gradient of the floor albedo exactly
+    wl = sg.polarizer_stack(width=32, height=18, spp=2)
+    v = sg.crop_views(wl.views, 12, 6, 6, 6)
+    osc = oracle.OracleScene.from_scene(wl.scene)
+    d = np.random.default_rng(9).normal(size=sg.image_numel(v))
+    p = wl.scene.params()
+    r = osc.run(p, v, 128, wl.seed)
+    assert r["n_vertices"] > 80 * r["n_paths"]
+    gc = osc.run(p, v, 128, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=d, nthreads=1)["grads"]
+    for k in (16, 200):
+        gh = osc.run(p, v, 128, wl.seed, mode=oracle.MODE_HYBRID, d_image=d, ckpt=k, nthreads=1)["grads"]
+        for a, b in zip(gc, gh):
+            assert np.array_equal(a, b)
+    assert np.abs(gc[wl.scene.slot("floor_albedo")]).max() > 0
+
+
+def test_hybrid_replay_rejects_zero_interval(oracle_lib):
+    wl, osc = _c1()
+    d = np.zeros(sg.image_numel(wl.views))
+    with pytest.raises(ValueError, match="checkpoint"):
+        osc.run(wl.scene.params(), wl.views, wl.max_depth, wl.seed, mode=oracle.MODE_HYBRID, d_image=d, ckpt=0)
