@@ -197,15 +197,16 @@ def optimise(args, torch, ppt, sg, dev):
 def depth_sweep(args, torch, ppt, sg, dev):
     """Render + PRB backward (gradient of the floor albedo) of the 1280x720, 1 spp scene behind 85
     polarizer sheets for maximum depths 1..128: time, vertices, workspace and peak device memory,
-    with all paths in one chunk and with 128k-path chunks."""
+    with all paths in one chunk and with 128k-path chunks (cached suffix replay), and with all
+    paths in one chunk under the hybrid replay with checkpoints every 16 vertices."""
     rows = []
     for D in (1, 2, 4, 8, 16, 32, 48, 64, 86, 96, 112, 128):
         wl = sg.polarizer_stack(max_depth=D)
         scene = ppt.Scene(wl.scene.to_blob())
         params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
         want = [n in wl.grad_slots for n in wl.scene.slot_names]
-        for chunk in (0, 1 << 17):
-            plan = ppt.Plan(scene, wl.views, D, chunk_paths=chunk or wl.n_paths())
+        for chunk, kc in ((0, 0), (1 << 17, 0), (0, 16)):
+            plan = ppt.Plan(scene, wl.views, D, chunk_paths=chunk or wl.n_paths(), checkpoint_interval=kc)
             d = torch.from_numpy(np.random.default_rng(D).standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
@@ -227,6 +228,7 @@ def depth_sweep(args, torch, ppt, sg, dev):
                 torch.cuda.synchronize()
                 tr.append(e0.elapsed_time(e1)); tb.append(e1.elapsed_time(e2))
             rows.append({"max_depth": D, "chunk_paths": plan.launch_info()["chunk_paths"],
+                         "replay": f"hybrid k={kc}" if kc else "cached",
                          "vertices": st["vertices"], "render_ms": round(float(np.median(tr)), 3),
                          "backward_ms": round(float(np.median(tb)), 3),
                          "workspace_gb": {"render": round(plan.workspace_bytes(0) / 1e9, 4),

@@ -62,8 +62,12 @@ typedef struct ppt_view {
 } ppt_view;
 
 typedef struct ppt_plan_opts {
-    int64_t chunk_paths;      /* paths in flight per chunk (path-state capacity); 0 = min(all, 16M) */
-    int64_t reserved;         /* must be 0 */
+    int64_t chunk_paths;          /* paths in flight per chunk (path-state capacity); 0 = min(all, 16M) */
+    int64_t checkpoint_interval;  /* backward replay (Sec. 4.4): 0 = cached suffix replay, every vertex
+                                   * keeps W_b, E_b and its suffix (128 B); k >= 1 = hybrid cached
+                                   * replay, only a 16-byte hit record per vertex, the suffix every k
+                                   * vertices, and the vertices in between recomputed from it (exact;
+                                   * less workspace for deep paths, more arithmetic).  k <= 128. */
 } ppt_plan_opts;
 
 typedef struct ppt_scene ppt_scene;

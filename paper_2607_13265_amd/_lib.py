@@ -43,7 +43,7 @@ class PPTError(RuntimeError):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("chunk_paths", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+    _fields_ = [("chunk_paths", ctypes.c_int64), ("checkpoint_interval", ctypes.c_int64)]
 
 
 _lib = None

@@ -56,14 +56,16 @@ class Scene:
 
 
 class Plan:
-    """Views + max depth + flags; paths of all views are processed in chunks of chunk_paths."""
+    """Views + max depth + flags; paths of all views are processed in chunks of chunk_paths.
+    checkpoint_interval k > 0 selects the hybrid cached replay for the backward pass."""
 
-    def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, chunk_paths: int = 0):
+    def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, chunk_paths: int = 0,
+                 checkpoint_interval: int = 0):
         self.scene = scene
         self.views = np.ascontiguousarray(views, VIEW_DTYPE)
         self.max_depth = int(max_depth)
         self.flags = int(flags)
-        opts = PlanOpts(int(chunk_paths), 0)
+        opts = PlanOpts(int(chunk_paths), int(checkpoint_interval))
         h = ctypes.c_void_p()
         check(lib().ppt_plan_create(scene.handle, self.views.ctypes.data_as(ctypes.c_void_p), len(self.views),
                                     self.max_depth, self.flags, ctypes.byref(opts), ctypes.byref(h)))

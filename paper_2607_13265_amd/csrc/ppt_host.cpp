@@ -217,6 +217,7 @@ struct ppt_plan {
     const uint8_t* mask = nullptr;
     bool stats = true;
     bool timing = false;
+    int32_t ckpt = 0;           // hybrid replay checkpoint interval, 0 = cached
     mutable KTimer timer[2];  // most recent render / backward call while timing is enabled
 };
 
@@ -431,7 +432,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
 struct WsLayout {
     size_t table, stats, counts, gacc, total;
     int lds_nd = 0, lds_nf = 0;
-    size_t ray, shd, acc, cache, q0, q1, sq, hq;
+    size_t ray, shd, acc, cache, hits, ckpt, q0, q1, sq, hq;
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -446,7 +447,11 @@ static WsLayout ws_layout(const ppt_plan* p, int op) {
     L.ray = take(RAY_F4 * 16 * Q);
     L.shd = take(SHD_F4 * 16 * Q);
     L.acc = take(op == 0 ? ACC_F4 * 16 * Q : 0);
-    L.cache = take(op == 1 ? (size_t)p->max_depth * CACHE_F4 * 16 * Q : 0);
+    const bool hybrid = op == 1 && p->ckpt > 0;
+    const size_t records = hybrid ? (size_t)std::min(p->ckpt, p->max_depth) : (size_t)p->max_depth;
+    L.cache = take(op == 1 ? records * CACHE_F4 * 16 * Q : 0);
+    L.hits = take(hybrid ? (size_t)p->max_depth * 16 * Q : 0);
+    L.ckpt = take(hybrid ? (size_t)((p->max_depth + p->ckpt - 1) / p->ckpt) * CKPT_F4 * 16 * Q : 0);
     L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q); L.hq = take(4 * Q);
     L.gacc_n = 0;
     if (op == 1)
@@ -462,6 +467,8 @@ static PathState path_state(void* ws, const WsLayout& L) {
     S.shd = (float4*)(w + L.shd);
     S.acc = (float4*)(w + L.acc);
     S.cache = (float4*)(w + L.cache);
+    S.hits = (float4*)(w + L.hits);
+    S.ckpt = (float4*)(w + L.ckpt);
     S.queue0 = (int*)(w + L.q0); S.queue1 = (int*)(w + L.q1); S.squeue = (int*)(w + L.sq); S.hqueue = (int*)(w + L.hq);
     S.counts = (int*)(w + L.counts);
     return S;
@@ -588,6 +595,11 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
     P->image_numel = out_off;
     P->num_paths = path_off;
     // chunk of paths in flight: all paths up to 16M by default, a multiple of the wavefront size
+    if (opts && (opts->checkpoint_interval < 0 || opts->checkpoint_interval > MAX_DEPTH)) {
+        delete P;
+        return fail(PPT_EINVAL, "checkpoint_interval must be in [0, 128]");
+    }
+    P->ckpt = opts ? (int32_t)opts->checkpoint_interval : 0;
     int64_t q = opts && opts->chunk_paths > 0 ? opts->chunk_paths : (int64_t)1 << 24;
     q = std::min<int64_t>(q, std::max<int64_t>(path_off, 1));
     q = ((q + WAVE - 1) / WAVE) * WAVE;
@@ -748,6 +760,7 @@ int ppt_backward(const ppt_plan* p, const float* const* params, int32_t n_params
     a.gacc = (double*)((char*)ws + L.gacc);
     a.lds_nd = L.lds_nd;
     a.lds_nf = L.lds_nf;
+    a.ckpt = p->ckpt;
     const LaunchMarker M = marker(p, 1);
     if (p->timing) p->timer[1].begin();
     M(KF_OTHER, s);

@@ -26,7 +26,12 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [4..6] E_b (12 words), overwritten by the fold with the suffix radiance beyond the vertex,
 //     L[b+1], which is what the replay of vertex b reads (not stored for a path's last vertex)
 //   hitword = prim | next-event state << 26 | weight kind << 29
-constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8;
+//   hybrid replay (checkpoint interval k): per vertex a hit record [hitword, u-or-t, v, -] (16 B);
+//   per block of k vertices a checkpoint record, CKPT_F4 = 5 vectors (80 B):
+//     [0] o.x o.y o.z prev-delta   [1] d.x d.y d.z -   (the ray into the block's first vertex)
+//     [2..4] suffix radiance beyond the block's last vertex (written by the fold);
+//   and k cache records of scratch for the block being re-evaluated.
+constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8, CKPT_F4 = 5;
 
 enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
                          MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };
@@ -113,7 +118,9 @@ struct PathState {
     float4* ray;    // [Q][RAY_F4]
     float4* shd;    // [Q][SHD_F4]
     float4* acc;    // [Q][ACC_F4] (render)
-    float4* cache;  // [max_depth][Q][CACHE_F4] (backward)
+    float4* cache;  // [max_depth or k][Q][CACHE_F4] (backward; per block scratch in the hybrid replay)
+    float4* hits;   // [max_depth][Q] hit records (hybrid replay)
+    float4* ckpt;   // [ceil(max_depth / k)][Q][CKPT_F4] checkpoint records (hybrid replay)
     int* queue0;    // ray queues (alternating per bounce; queue0 is the replay queue after the fold)
     int* queue1;
     int* squeue;    // shadow-ray queue
@@ -139,6 +146,7 @@ struct WArgs {
     int32_t qin;            // ray queue read in this bounce (0/1)
     int32_t first;          // first bounce: the queue is the identity over the chunk's slots
     int32_t lds_nd, lds_nf;  // used entries of the workgroup gradient accumulators
+    int32_t ckpt;           // hybrid replay checkpoint interval k, 0 = cached suffix replay
     float* out;             // render output
     const float* dout;      // backward: dL/dStokes
     double* gacc;           // backward: FP64 gradient accumulators

@@ -164,6 +164,8 @@ DEV float4* acc_rec(const PathState& S, int i) { return S.acc + (size_t)i * ACC_
 DEV float4* cache_rec(const PathState& S, int Q, int b0, int i) {  // b0: 0-based vertex index
     return S.cache + ((size_t)b0 * Q + i) * CACHE_F4;
 }
+DEV float4* hit_rec(const PathState& S, int Q, int b0, int i) { return S.hits + ((size_t)b0 * Q + i); }
+DEV float4* ckpt_rec(const PathState& S, int Q, int blk, int i) { return S.ckpt + ((size_t)blk * Q + i) * CKPT_F4; }
 DEV float4 f4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
 DEV void ld12(const float4* r, float* v) {
 #pragma unroll
@@ -294,15 +296,18 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
             alive = false;
             const bool occ = T.h.prim >= 0;
             const float4* H = shd_rec(S, slot);
-            float4* dst = MODE == 0 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
-            if (!occ)
+            if (MODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
+                float4* dst = MODE == 0 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+                if (!occ)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    float4 a = dst[k], p = H[2 + k];
-                    dst[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
-                }
-            if (MODE == 1) {  // record the visibility in the hit word of the vertex whose light sample this is
-                float* hwp = &cache_rec(S, Q, (info & 255) - 1, slot)[2].w;
+                    for (int k = 0; k < 3; ++k) {
+                        float4 a = dst[k], p = H[2 + k];
+                        dst[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
+                    }
+            }
+            if (MODE != 0) {  // record the visibility in the hit word of the vertex whose light sample this is
+                float* hwp = MODE == 1 ? &cache_rec(S, Q, (info & 255) - 1, slot)[2].w
+                                       : &hit_rec(S, Q, (info & 255) - 1, slot)->x;
                 uint32_t hw = (uint32_t)__float_as_int(*hwp);
                 hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
                 *hwp = __int_as_float((int)hw);
@@ -401,12 +406,22 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                     A.sig[g] = sg;
                 }
                 WC w;
+                w.kind = 0;
                 float Ee[12], En[12];
-                eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
+                if (MODE != 2) eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
                 cont = x.lobe != LOBE_NONE && x.lobe != LOBE_INVALID;
                 shadow = x.nee == NEE_PENDING;
                 float4* H = shd_rec(S, slot);
-                if (MODE == 0) {
+                if (MODE == 2) {
+                    // hybrid replay: the hit record, and at a block start the ray into this vertex
+                    bool sphere = __float_as_int(ldg4(W.prims, 3 * h.prim + 1).w) != 0;
+                    *hit_rec(S, A.Q, b - 1, slot) = f4(__int_as_float(h.prim | (x.nee << 26)), sphere ? h.t : h.u, h.v, 0.0f);
+                    if ((b - 1) % A.ckpt == 0) {
+                        float4* CK = ckpt_rec(S, A.Q, (b - 1) / A.ckpt, slot);
+                        CK[0] = f4(o.x, o.y, o.z, prev_delta ? 1.0f : 0.0f);
+                        CK[1] = f4(d.x, d.y, d.z, 0.0f);
+                    }
+                } else if (MODE == 0) {
                     float4* AC = acc_rec(S, slot);
                     float beta[16], brgb[3], Lo[12];
                     if (nb == 0) {  // first vertex: beta = I, no radiance yet
@@ -460,7 +475,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                         for (int k = 0; k < 4; ++k) AC[k] = f4(beta[4 * k], beta[4 * k + 1], beta[4 * k + 2], beta[4 * k + 3]);
                         AC[4] = f4(brgb[0] * w.rgb[0], brgb[1] * w.rgb[1], brgb[2] * w.rgb[2], 0.0f);
                     }
-                } else {
+                } else {  // MODE 1
                     float4* C = cache_rec(S, A.Q, b - 1, slot);
                     bool sphere = __float_as_int(ldg4(W.prims, 3 * h.prim + 1).w) != 0;
                     C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
@@ -567,7 +582,6 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
     }
 }
 
-// ============================================================================ backward: fold
 // W_c applied to a Stokes vector without branches on the weight's kind (the loads of a record
 // stay together ahead of the arithmetic): the Fresnel form is evaluated and then selected.
 // Entries of kind-0 records are not read into the result.
@@ -583,6 +597,69 @@ DEV void w_apply_select(const WC& w, int c, const float* in, float* out) {
     out[3] = fr ? s * f3 : 0.0f;
 }
 
+// ============================================================================ hybrid replay blocks
+// Hybrid cached replay (Sec. 4.4): the primal pass keeps a hit record per vertex and, every k
+// vertices, the ray into the block's first vertex; suffix values are kept only at block ends.
+// block_eval re-evaluates vertices [s, e) of the path in `slot` from the ray (o, d) into vertex s,
+// with each vertex's recorded next-event visibility, into the scratch cache records 0 .. e-s-1
+// (W_b and E_b); block_fold then folds them back from the suffix L beyond the block's last vertex,
+// leaving in L the suffix at its first vertex (with store_suffix, each record's E words receive
+// the suffix beyond its vertex, which the replay reads).
+DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWorld& W, int slot, uint32_t pix,
+                    uint32_t smp, int s, int e, v3 o, v3 d, bool prev_delta) {
+    const PathState& S = A.S;
+    const int Q = A.Q;
+    for (int v = s; v < e; ++v) {
+        const float4 hr = *hit_rec(S, Q, v, slot);
+        const uint32_t hw = __float_as_uint(hr.x);
+        Hit h;
+        h.prim = (int)(hw & ((1u << 26) - 1));
+        h.u = hr.y; h.t = hr.y; h.v = hr.z;
+        Vtx x;
+        surface(W, h, o, d, x);
+        v3 so, sd;
+        float stmax;
+        vertex_setup(W, K, V, A.seed, pix, smp, v + 1, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+        if (x.nee == NEE_PENDING) x.nee = (int)((hw >> 26) & 7);
+        WC w;
+        float Ee[12], En[12];
+        eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
+        float4* C = cache_rec(S, Q, v - s, slot);
+        C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
+        C[1] = f4(w.B, w.C, w.D, w.ci);
+        C[2] = f4(w.si, w.co, w.so, __int_as_float(w.kind << 29));
+#pragma unroll
+        for (int q = 0; q < 12; ++q) Ee[q] += En[q];
+        st12(C + 4, Ee);
+        prev_delta = is_delta(gval(W.mats, (size_t)x.mat).type);
+        o = spawn(x.p, x.ng, x.wi);
+        d = x.wi;
+    }
+}
+DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool store_suffix) {
+    for (int u = n - 1; u >= 0; --u) {
+        float4* C = cache_rec(S, Q, u, slot);
+        const float4 c0 = C[0], c1 = C[1], c2 = C[2];
+        float e[12];
+        ld12(C + 4, e);
+        if (store_suffix) st12(C + 4, L);
+        WC w;
+        w.rgb[0] = c0.x; w.rgb[1] = c0.y; w.rgb[2] = c0.z;
+        w.A = c0.w; w.B = c1.x; w.C = c1.y; w.D = c1.z;
+        w.ci = c1.w; w.si = c2.x; w.co = c2.y; w.so = c2.z;
+        w.kind = (__float_as_int(c2.w) >> 29) & 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float o4[4];
+            w_apply_select(w, c, L + 4 * c, o4);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L[4 * c + k] = e[4 * c + k] + o4[k];
+        }
+    }
+}
+
+// ============================================================================ backward: fold
+
 // Per path with at least one vertex: folds the cache into the suffix radiance
 // L[b] = E_b + W_b L[b+1] (L[b+1] written over E_b), adds the polarizer-angle term
 // delta^T (dP/dtheta) R_s L[1],
@@ -590,6 +667,7 @@ DEV void w_apply_select(const WC& w, int c, const float* in, float* out) {
 // (into ro/rd) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
 // contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
 // register until the view changes.
+template <bool HYB>
 __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
@@ -618,7 +696,23 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
             float L[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) L[k] = 0.0f;
-            for (int b = B - 1; b >= 0; --b) {
+            if (HYB) {
+                // blocks from the last to the first: re-evaluate from the block's checkpoint ray,
+                // store the suffix beyond the block, fold back to the block's first vertex
+                const DevView Vh = gval(A.views, (size_t)v);
+                const DevWorld Wh = gval(A.worlds, (size_t)Vh.world);
+                const int kc = A.ckpt;
+                for (int j = (B + kc - 1) / kc - 1; j >= 0; --j) {
+                    const int s0 = j * kc, e0 = min(B, s0 + kc);
+                    float4* CK = ckpt_rec(S, Q, j, i);
+                    const float4 k0 = CK[0], k1 = CK[1];
+                    block_eval(A, K, Vh, Wh, i, pix, smp, s0, e0, mk(k0.x, k0.y, k0.z), mk(k1.x, k1.y, k1.z),
+                               k0.w != 0.0f);
+                    st12(CK + 2, L);
+                    block_fold(S, Q, i, e0 - s0, L, false);
+                }
+            }
+            for (int b = HYB ? -1 : B - 1; b >= 0; --b) {
                 float4* C = cache_rec(S, Q, b, i);
                 const float4 c0 = C[0], c1 = C[1], c2 = C[2];
                 float e[12];
@@ -716,6 +810,7 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
 // short and long paths share a wavefront without idling.  At vertex b the lane differentiates
 // E_b + W_b L[b+1] against its adjoint rows, then advances them, a <- a W_b.  Gradients go to
 // workgroup LDS accumulators, flushed at the end.
+template <bool HYB>
 __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
@@ -759,13 +854,30 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
         if (slot >= 0) {
             const DevView V = gval(A.views, (size_t)v);
             const DevWorld W = gval(A.worlds, (size_t)V.world);
-            const float4* C = cache_rec(S, Q, b - 1, slot);
-            const float4 c2 = C[2], c3 = C[3];
-            uint32_t hw = (uint32_t)__float_as_int(c2.w);
+            uint32_t hw;
+            float hu, hv;
+            const float4* C;  // the record whose E words hold the suffix beyond this vertex
+            if (HYB) {
+                const int v0 = b - 1;
+                if (v0 % A.ckpt == 0) {  // block start: recompute the block's suffix values
+                    const int e0 = min(B, v0 + A.ckpt);
+                    block_eval(A, K, V, W, slot, pix, smp, v0, e0, o, d, prev_delta);
+                    float Lb[12];
+                    ld12(ckpt_rec(S, Q, v0 / A.ckpt, slot) + 2, Lb);
+                    block_fold(S, Q, slot, e0 - v0, Lb, true);
+                }
+                const float4 hr = *hit_rec(S, Q, v0, slot);
+                hw = __float_as_uint(hr.x); hu = hr.y; hv = hr.z;
+                C = cache_rec(S, Q, v0 % A.ckpt, slot);
+            } else {
+                C = cache_rec(S, Q, b - 1, slot);
+                const float4 c2 = C[2], c3 = C[3];
+                hw = __float_as_uint(c2.w); hu = c3.x; hv = c3.y;
+            }
             Hit h;
             h.prim = (int)(hw & ((1u << 26) - 1));
             int rec_nee = (int)((hw >> 26) & 7);
-            h.u = c3.x; h.t = c3.x; h.v = c3.y;
+            h.u = hu; h.t = hu; h.v = hv;
             Vtx x;
             surface(W, h, o, d, x);
             v3 so, sd;
@@ -901,11 +1013,14 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         if (mode == 0) hipLaunchKernelGGL(k_compact<0>, dim3(gb), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL(k_compact<1>, dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_SHADE, s);
-        if (mode == 0) hipLaunchKernelGGL(k_shade<0>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL(k_shade<1>, dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, a);
+        const int sg = blocks_for(a.n_chunk, G.shade), xg = blocks_for(a.n_chunk, G.extend);
+        if (mode == 0) hipLaunchKernelGGL(k_shade<0>, dim3(sg), dim3(BLOCK), 0, s, a);
+        else if (a.ckpt > 0) hipLaunchKernelGGL(k_shade<2>, dim3(sg), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL(k_shade<1>, dim3(sg), dim3(BLOCK), 0, s, a);
         M(KF_SHADOW, s);
-        if (mode == 0) hipLaunchKernelGGL(k_shadow<0>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
-        else hipLaunchKernelGGL(k_shadow<1>, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
+        if (mode == 0) hipLaunchKernelGGL(k_shadow<0>, dim3(xg), dim3(BLOCK), lds, s, a);
+        else if (a.ckpt > 0) hipLaunchKernelGGL(k_shadow<2>, dim3(xg), dim3(BLOCK), lds, s, a);
+        else hipLaunchKernelGGL(k_shadow<1>, dim3(xg), dim3(BLOCK), lds, s, a);
     }
     if (mode == 0) {
         if (a.out) {
@@ -915,9 +1030,11 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     } else {
         size_t glds = (size_t)a.lds_nd * sizeof(double) + (size_t)a.lds_nf * sizeof(float);
         M(KF_FOLD, s);
-        hipLaunchKernelGGL(k_fold, dim3(gb), dim3(BLOCK), 0, s, a);
+        if (a.ckpt > 0) hipLaunchKernelGGL(k_fold<true>, dim3(gb), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL(k_fold<false>, dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_REPLAY, s);
-        hipLaunchKernelGGL(k_replay, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
+        if (a.ckpt > 0) hipLaunchKernelGGL(k_replay<true>, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
+        else hipLaunchKernelGGL(k_replay<false>, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
     }
     return hipGetLastError();
 }
@@ -929,7 +1046,7 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend, BLOCK, lds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1>, BLOCK, 0)) != hipSuccess) return r;
     size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay, BLOCK, glds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay<false>, BLOCK, glds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_gen, BLOCK, 0)) != hipSuccess) return r;
     G->extend = (e > 0 ? e : 1) * cu;
     G->shade = (sh > 0 ? sh : 1) * cu;

@@ -87,3 +87,17 @@ def test_c5_uneven_multiworld_crops():
     res = run(wl, d=d, oracle_mode=oracle.MODE_CACHED_PRB)
     _check(res)
     assert len(res["grad_rel"]) == len(wl.scene.slot_names)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_hybrid_replay_parity_c2_crop(k):
+    # hybrid cached replay (checkpoint interval k): same gradient as the oracle's cached replay
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+    res = run(wl, oracle_mode=oracle.MODE_CACHED_PRB, plan_kw={"checkpoint_interval": k})
+    _check(res, gate_groups=("albedo_tex", "roughness", "cond_n", "cond_k", "light_Le"))
+
+
+def test_hybrid_replay_parity_c1_config_loss():
+    wl = sg.config1()
+    _check(run(wl, d=loss_delta_c1(wl), oracle_mode=oracle.MODE_HYBRID, plan_kw={"checkpoint_interval": 2}))

@@ -411,3 +411,28 @@ def test_plain_c_caller_matches_binding(tmp_path):
     ref = np.concatenate([img] + [g.cpu().numpy() for g in grads])
     assert got.shape == ref.shape
     assert np.allclose(got, ref, rtol=1e-5, atol=1e-6)
+
+
+def test_hybrid_replay_matches_cached_and_saves_workspace():
+    # deep paths (85 polarizer sheets, depth 128): the hybrid replay gives the cached gradient
+    # with a fraction of the backward workspace; batches and chunking as for the cached replay
+    ppt = _ppt()
+    wl = sg.polarizer_stack(width=64, height=36, spp=2)
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = _params(wl.scene)
+    cached = ppt.Plan(scene, wl.views, 128)
+    d = torch.randn(cached.image_numel, device="cuda")
+    gc = cached.backward(params, 4, d)
+    for k in (1, 8, 16, 200 // 2):
+        hyb = ppt.Plan(scene, wl.views, 128, checkpoint_interval=k)
+        gh = hyb.backward(params, 4, d)
+        for a, b in zip(gc, gh):
+            assert rel(b.cpu().numpy(), a.cpu().numpy(), floor=1e-12) < 1e-5
+        if k in (8, 16):  # hit records + a suffix every k vertices + k records of block scratch
+            assert hyb.workspace_bytes(1) < 0.4 * cached.workspace_bytes(1)
+    hc = ppt.Plan(scene, wl.views, 128, chunk_paths=1000, checkpoint_interval=16)
+    for a, b in zip(gc, hc.backward(params, 4, d)):
+        assert rel(b.cpu().numpy(), a.cpu().numpy(), floor=1e-12) < 1e-5
+    for bad in (-1, 129):
+        with pytest.raises(ppt.PPTError, match="EINVAL"):
+            ppt.Plan(scene, wl.views, 128, checkpoint_interval=bad)
