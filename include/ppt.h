@@ -105,7 +105,9 @@ int ppt_scene_slots(const ppt_scene* scene, int32_t* n_slots, int64_t* numel_out
 /* Fix the views, the maximum path depth (1..128 surface interactions) and the flags of a
  * family of calls.  All paths of all views form one index space that is processed in chunks
  * of chunk_paths paths (one launch sequence covers the whole batch of views, also views of
- * different worlds, resolutions and sample counts).  views: host array of n_views records. */
+ * different worlds, resolutions and sample counts).  views: host array of n_views records.
+ * Errors: PPT_EINVAL for an invalid view or option, PPT_EUNSUPPORTED for a depth outside
+ * 1..128, 2^19 or more views, or a view with 2^31 or more paths (crop pixels x spp). */
 int ppt_plan_create(const ppt_scene* scene, const ppt_view* views, int32_t n_views, int32_t max_depth,
                     uint32_t flags, const ppt_plan_opts* opts, ppt_plan** out);
 void ppt_plan_destroy(ppt_plan* plan);

@@ -557,6 +557,10 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
                   V.sensor >= PPT_SENSOR_NONE && V.sensor <= PPT_SENSOR_ANALYZER4 && V.fov_y_deg > 0.0f &&
                   V.fov_y_deg < 180.0f;
         if (ok && V.sensor == PPT_SENSOR_POLARIZER) ok = slot_ok(sc, V.theta_slot, V.theta_off, 1);
+        if (ok && (int64_t)V.crop_w * V.crop_h * V.spp >= (1ll << 31)) {
+            delete P;
+            return fail(PPT_EUNSUPPORTED, "a view has 2^31 or more paths");
+        }
         double o[3] = {V.origin[0], V.origin[1], V.origin[2]}, t[3] = {V.target[0], V.target[1], V.target[2]};
         double up[3] = {V.up[0], V.up[1], V.up[2]};
         double f[3] = {t[0] - o[0], t[1] - o[1], t[2] - o[2]};

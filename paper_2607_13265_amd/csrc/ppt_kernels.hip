@@ -124,25 +124,32 @@ struct WaveFetch {
     DEV bool more() const { return !exhausted || c < cend; }  // wave-uniform
 };
 
-// view of a global path index (views are few; binary search over their path offsets)
+// view of a global path index (binary search over the views' first path indices)
 DEV int find_view(const DevView* views, int n_views, int64_t g) {
     int lo = 0, hi = n_views - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (views[mid].path_off <= g) lo = mid; else hi = mid - 1;
+        if (gval(views, (size_t)mid).path_off <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
+// Path keys of a global path index.  Lanes of a wavefront hold consecutive paths, so the view
+// of the wavefront's first lane is looked up once and a lane searches only when its path lies
+// beyond that view.  The index within a view fits 32 bits (checked when the plan is made).
 struct PathId { int v, px, py, lx, ly; uint32_t smp, pix; };
-DEV PathId path_id(const DevView* views, int n_views, int64_t g) {
+DEV PathId path_id(const DevView* views, int n_views, int64_t g, int64_t g_first) {
     PathId r;
-    r.v = find_view(views, n_views, g);
-    const DevView& V = views[r.v];
-    int64_t local = g - V.path_off;
-    int64_t pl = local / V.spp;
-    r.smp = (uint32_t)(local - pl * V.spp);
-    r.lx = (int)(pl % V.crop_w);
-    r.ly = (int)(pl / V.crop_w);
+    const int v0 = __builtin_amdgcn_readfirstlane(find_view(views, n_views, g_first));
+    r.v = v0;
+    const int64_t end0 = v0 + 1 < n_views ? gval(views, (size_t)(v0 + 1)).path_off : INT64_MAX;
+    if (g >= end0) r.v = find_view(views, n_views, g);
+    const DevView V = gval(views, (size_t)r.v);
+    const uint32_t local = (uint32_t)(g - V.path_off);
+    const uint32_t spp = (uint32_t)V.spp, cw = (uint32_t)V.crop_w;
+    const uint32_t pl = local / spp;
+    r.smp = local - pl * spp;
+    r.ly = (int)(pl / cw);
+    r.lx = (int)(pl - (uint32_t)r.ly * cw);
     r.px = V.crop_x0 + r.lx;
     r.py = V.crop_y0 + r.ly;
     r.pix = (uint32_t)(r.py * V.width + r.px);
@@ -200,13 +207,15 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
     Count cnt;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
         int64_t g = A.g0 + i;
-        PathId id = path_id(A.views, A.n_views, g);
-        const DevView& V = A.views[id.v];
+        const int64_t g_first = __builtin_amdgcn_readfirstlane((uint32_t)(i - lane_id())) + A.g0;
+        PathId id = path_id(A.views, A.n_views, g, g_first);
+        const DevView V = gval(A.views, (size_t)id.v);
         bool live = !(A.mask && !A.mask[g]);
         v3 o, d;
         camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
         float4* R = ray_rec(S, i);
         ray_set(R, o, d);
+        R[2] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // the whole record is written
         R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
                   __uint_as_float(id.smp), 0.0f);
         if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
