@@ -213,9 +213,14 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
         bool live = !(A.mask && !A.mask[g]);
         v3 o, d;
         camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
+        // rotation from the canonical frame of the light arriving along -d to the sensor frame,
+        // kept in the record's spare words for the pixel reduction
+        const v3 kc = -d;
+        float Cs, Ss;
+        rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
         float4* R = ray_rec(S, i);
         ray_set(R, o, d);
-        R[2] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // the whole record is written
+        R[2] = f4(0.0f, 0.0f, Cs, Ss);  // the whole record is written
         R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
                   __uint_as_float(id.smp), 0.0f);
         if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
@@ -533,20 +538,18 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
         int v = 0, lx = 0, ly = 0;
         if (valid) {
             // pixel of the path from its stored keys; the segment key is (view, pixel)
-            const float4 r3 = ray_rec(S, i)[3];
+            const float4* R = ray_rec(S, i);
+            const float4 r3 = R[3];
             const int info = __float_as_int(r3.x);
             v = info >> 12;
             const DevView V = gval(A.views, (size_t)v);
-            const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
+            const uint32_t pix = __float_as_uint(r3.y);
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
             lx = px - V.crop_x0; ly = py - V.crop_y0;
             key = ((int64_t)v << 32) | (int64_t)pix;
             if (!(info & INFO_DEAD)) {
-                v3 o, d;
-                camera_ray(V, px, py, smp, A.seed, o, d);
-                v3 kc = -d;
-                float Cs, Ss;
-                rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
+                const float4 r2 = R[2];
+                const float Cs = r2.z, Ss = r2.w;  // sensor rotation of the camera ray
                 float Lo[12];
                 ld12(acc_rec(S, i) + 5, Lo);
 #pragma unroll
