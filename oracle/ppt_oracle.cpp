@@ -146,6 +146,17 @@ static inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - 
 static inline double len(V3 a) { return std::sqrt(dot(a, a)); }
 static inline V3 normalize(V3 a) { return a * (1.0 / len(a)); }
 
+// Vectors whose entries may be tape variables (the shading normal of a normal-mapped surface).
+template <class T> struct VT { T x, y, z; };
+template <class T> static inline VT<T> lift(V3 a) { return {T(a.x), T(a.y), T(a.z)}; }
+template <class T> static inline T dot(const VT<T>& a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> static inline T dot(const VT<T>& a, const VT<T>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> static inline VT<T> cross(V3 a, const VT<T>& b) {
+    return {b.z * a.y - b.y * a.z, b.x * a.z - b.z * a.x, b.y * a.x - b.x * a.y};
+}
+template <class T> static inline VT<T> vscale(const VT<T>& a, T s) { return {a.x * s, a.y * s, a.z * s}; }
+template <class T> static inline VT<T> vneg(const VT<T>& a) { return {-a.x, -a.y, -a.z}; }
+
 template <class T> struct Cx { T re, im; };
 template <class T> static inline Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T> static inline Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
@@ -296,12 +307,12 @@ template <class T> static M4<T> jones_diag_mueller(Cx<T> as, Cx<T> ap) {
 // Fresnel reflection and (flux-form) transmission Mueller matrices, Born & Wolf amplitudes,
 // for incidence cosine ci and complex relative index m = n2/n1.  Bases: s perpendicular to
 // the plane of incidence, p = k x s for each wave.
-template <class T> static void fresnel(double ci, Cx<T> m, M4<T>* MR, M4<T>* MT) {
+template <class T> static void fresnel(T ci, Cx<T> m, M4<T>* MR, M4<T>* MT) {
     Cx<T> m2 = cmul(m, m);
     Cx<T> one{T(1.0), T(0.0)};
-    Cx<T> st2 = cdiv(Cx<T>{T(1.0 - ci * ci), T(0.0)}, m2);
+    Cx<T> st2 = cdiv(Cx<T>{T(1.0) - ci * ci, T(0.0)}, m2);
     Cx<T> ct = csqrt(csub(one, st2));
-    Cx<T> cI{T(ci), T(0.0)};
+    Cx<T> cI{ci, T(0.0)};
     Cx<T> mct = cmul(m, ct), mci = cmul(m, cI);
     Cx<T> rs = cdiv(csub(cI, mct), cadd(cI, mct));
     Cx<T> rp = cdiv(csub(mci, ct), cadd(mci, ct));
@@ -315,15 +326,15 @@ template <class T> static void fresnel(double ci, Cx<T> m, M4<T>* MR, M4<T>* MT)
 }
 
 // ============================================================================ GGX
-template <class T> static T ggx_D(double cos_h, T a) {
-    if (cos_h <= 0.0) return T(0.0);
+template <class T> static T ggx_D(T cos_h, T a) {
+    if (val(cos_h) <= 0.0) return T(0.0);
     T a2 = a * a;
     T d = (a2 - 1.0) * (cos_h * cos_h) + 1.0;
     return a2 / (d * d * M_PI);
 }
-template <class T> static T smith_G1(double cos_w, T a) {
-    if (cos_w <= 0.0) return T(0.0);
-    double tan2 = (1.0 - cos_w * cos_w) / (cos_w * cos_w);
+template <class T> static T smith_G1(T cos_w, T a) {
+    if (val(cos_w) <= 0.0) return T(0.0);
+    T tan2 = (T(1.0) - cos_w * cos_w) / (cos_w * cos_w);
     T lam = (sqrt(a * a * tan2 + 1.0) - 1.0) * 0.5;
     return T(1.0) / (lam + 1.0);
 }
@@ -331,7 +342,7 @@ template <class T> static T smith_G1(double cos_w, T a) {
 // ============================================================================ scene
 enum { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3, MAT_SHEET = 4,
        MAT_EMITTER = 5, MAT_BLEND = 6 };
-enum { SENSOR_NONE = 0, SENSOR_POLARIZER = 1, SENSOR_ANALYZER4 = 2 };
+enum { SENSOR_NONE = 0, SENSOR_POLARIZER = 1, SENSOR_ANALYZER4 = 2, SENSOR_LIGHTSTAGE4 = 3 };
 enum { FLAG_NO_NEE = 1, FLAG_GAUGE = 1 << 16 };
 enum { LOBE_NONE = 0, LOBE_REFLECT = 1, LOBE_TRANSMIT = 2, LOBE_DIFFUSE = 3, LOBE_GLOSSY = 4, LOBE_SHEET = 5,
        LOBE_INVALID = 6 };
@@ -343,10 +354,15 @@ struct Material {
     int32_t eta_slot; uint32_t eta_off;
     int32_t kap_slot; uint32_t kap_off;
     int32_t emit_slot; uint32_t emit_off;
-    float axis[3]; float blend; uint32_t reserved[3];
+    float axis[3]; float blend;
+    float emit_circ;                                        // emitted Stokes: Le (1, 0, 0, emit_circ)
+    int32_t spec_slot; uint32_t spec_off, spec_tw, spec_th;  // specular map: scale of the GGX lobe
+    int32_t nrm_slot; uint32_t nrm_off, nrm_tw, nrm_th;      // tangent-space normal map (3 channels)
+    uint32_t reserved[4];
 };
-static_assert(sizeof(Material) == 88, "material record");
-struct LightRec { float p0[3], eu[3], ev[3]; int32_t le_slot; uint32_t le_off, pad; };
+static_assert(sizeof(Material) == 128, "material record");
+// circ: the light emits Le (1, 0, 0, circ) (circular polarization is frame-independent)
+struct LightRec { float p0[3], eu[3], ev[3]; int32_t le_slot; uint32_t le_off; float circ; };
 static_assert(sizeof(LightRec) == 48, "light record");
 
 struct View {
@@ -566,6 +582,12 @@ template <class T> static T mat_alpha(const PAcc<T>& P, const Material& m, doubl
     if (val(a) > 1.0) return T(1.0);
     return a;
 }
+// Specular map: scale of the GGX lobe (1 when the material has none).
+template <class T> static T mat_spec(const PAcc<T>& P, const Material& m, double u, double v) {
+    if (m.spec_slot < 0) return T(1.0);
+    if (m.spec_tw == 0) return P.get(m.spec_slot, m.spec_off);
+    return tex_lookup(P, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, 1, 0, u, v);
+}
 template <class T> static Cx<T> mat_ior(const PAcc<T>& P, const Material& m) {
     T n = P.get(m.eta_slot, m.eta_off);
     T k = (m.kap_slot >= 0) ? P.get(m.kap_slot, m.kap_off) : T(0.0);
@@ -589,6 +611,8 @@ struct Vtx {
     V3 wl;                     // direction to the light sample
     double nee_geom;           // cos_light * area * n_lights / dist^2
     int light;
+    bool nmap;                 // the material has a normal map: ns comes from it
+    V3 tg, bt;                 // tangent frame (u direction, ng x tangent) of a normal-mapped triangle
 };
 
 static bool is_delta(uint32_t t) { return t == MAT_DIELECTRIC || t == MAT_SHEET; }
@@ -612,6 +636,41 @@ static Camera make_camera(const View& v) {
     return c;
 }
 
+
+// ============================================================================ shading normal
+// Tangent frame of triangle p at its outward geometric normal N: the tangent follows increasing
+// u (dP/du from the triangle's uv parameterisation, made perpendicular to N), the bitangent is
+// N x tangent.  A triangle with a degenerate uv map takes the canonical basis of N instead.
+static void tangent_frame(const World& w, int p, V3 N, V3& tg, V3& bt) {
+    V3 e1 = w.v1[p] - w.v0[p], e2 = w.v2[p] - w.v0[p];
+    const double* t = &w.uv[6 * (size_t)p];
+    double du1 = t[2] - t[0], dv1 = t[3] - t[1], du2 = t[4] - t[0], dv2 = t[5] - t[1];
+    double det = du1 * dv2 - du2 * dv1;
+    V3 dpdu = (e1 * dv2 - e2 * dv1) * (det < 0.0 ? -1.0 : 1.0);
+    V3 tp = dpdu - N * dot(dpdu, N);
+    double l = len(tp);
+    if (det == 0.0 || !(l > 1e-6 * (len(e1) + len(e2)))) {
+        V3 yy;
+        onb(N, tg, yy);
+    } else {
+        tg = tp * (1.0 / l);
+    }
+    bt = cross(N, tg);
+}
+// Shading normal toward the viewer side: the normal map's tangent-space components (t, b, n)
+// give the outward normal normalize(t T + b B + n N); on the back side it is negated.
+template <class T> static VT<T> shading_normal(const PAcc<T>& P, const Material& m, const Vtx& x) {
+    if (!x.nmap) return lift<T>(x.ns);
+    T c[3];
+    for (int k = 0; k < 3; ++k)
+        c[k] = (m.nrm_tw == 0) ? P.get(m.nrm_slot, m.nrm_off + k)
+                               : tex_lookup(P, m.nrm_slot, m.nrm_off, m.nrm_tw, m.nrm_th, 3, k, x.u, x.v);
+    VT<T> n{c[0] * x.tg.x + c[1] * x.bt.x + c[2] * x.ng.x, c[0] * x.tg.y + c[1] * x.bt.y + c[2] * x.ng.y,
+            c[0] * x.tg.z + c[1] * x.bt.z + c[2] * x.ng.z};
+    T il = T(1.0) / sqrt(dot(n, n));
+    if (!x.front) il = -il;
+    return vscale(n, il);
+}
 
 // ============================================================================ path tracing (detached part)
 static V3 onb_x(V3 n) { V3 x, y; onb(n, x, y); return x; }
@@ -695,9 +754,26 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
         x.wo = -d;
         x.front = dot(x.ng, x.wo) > 0.0;
         x.ns = x.front ? x.ng : -x.ng;
+        const V3 ngf = x.ns;  // geometric normal on the viewer side
+        x.nmap = m.nrm_slot >= 0 && h.prim < nt;
+        if (x.nmap) {
+            tangent_frame(w, h.prim, x.ng, x.tg, x.bt);
+            VT<double> n = shading_normal(P, m, x);
+            x.ns = V3{n.x, n.y, n.z};
+        }
         x.emit = m.emit_slot >= 0 && x.front && (b == 1 || prev_delta || (flags & FLAG_NO_NEE));
         x.lobe = LOBE_NONE;
         x.nee = 0;
+        // a normal-mapped vertex seen from behind its shading normal neither scatters nor samples
+        // a light (its emission still counts)
+        const bool dark = x.nmap && !(dot(x.ns, x.wo) > 0.0);
+        if (dark && !(m.type == MAT_EMITTER || b == max_depth)) {
+            x.nee = 3;
+            x.lobe = LOBE_INVALID;
+            sig.add((uint32_t)x.prim); sig.add((uint32_t)x.lobe); sig.add((uint32_t)x.nee);
+            g.v.push_back(x);
+            break;
+        }
         if (m.type == MAT_EMITTER || b == max_depth) {
             sig.add((uint32_t)x.prim); sig.add(0); sig.add(0);
             g.v.push_back(x);
@@ -721,7 +797,8 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
             x.wl = dv * (1.0 / dist);
             x.light = li;
             double cos_y = -dot(nl_, x.wl), cos_x = dot(x.ns, x.wl);
-            if (!(cos_y > 0.0) || !(cos_x > 0.0)) {
+            // with a normal map the light must also lie above the geometric surface
+            if (!(cos_y > 0.0) || !(cos_x > 0.0) || (x.nmap && !(dot(ngf, x.wl) > 0.0))) {
                 x.nee = 3;
             } else {
                 V3 so = spawn(x.p, x.ng, x.wl);
@@ -787,6 +864,12 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
             default:
                 x.lobe = LOBE_INVALID;
         }
+        // with a normal map, a reflected direction must leave above the geometric surface and a
+        // transmitted one below it
+        if (x.nmap && x.lobe != LOBE_INVALID && x.lobe != LOBE_SHEET) {
+            double side = dot(ngf, x.wi);
+            if (x.lobe == LOBE_TRANSMIT ? !(side < 0.0) : !(side > 0.0)) x.lobe = LOBE_INVALID;
+        }
         sig.add((uint32_t)x.prim); sig.add((uint32_t)x.lobe); sig.add((uint32_t)x.nee);
         g.v.push_back(x);
         if (x.lobe == LOBE_INVALID) break;
@@ -812,16 +895,35 @@ template <class T> static M4<T> specular_canon(const M4<T>& Ml, V3 k_in, V3 n_in
     V3 sx = (l > 1e-12) ? s * (1.0 / l) : onb_x(k_in);
     return to_canon(Ml, k_in, sx, k_out, sx);
 }
+// The same with a differentiated normal (a normal-mapped shading normal): the s axis, and with
+// it both rotators, move with the normal.
+template <class T> static M4<T> rotator_t(V3 k, const VT<T>& x_from, const VT<T>& x_to) {
+    T c = dot(x_from, x_to), s = dot(cross(k, x_from), x_to);
+    T c2 = c * c - s * s, s2 = c * s * 2.0;
+    M4<T> r = meye<T>();
+    r.m[1][1] = c2; r.m[1][2] = s2; r.m[2][1] = -s2; r.m[2][2] = c2;
+    return r;
+}
+template <class T> static M4<T> specular_canon(const M4<T>& Ml, V3 k_in, const VT<T>& n_inc, V3 k_out) {
+    VT<T> s = cross(k_in, n_inc);
+    T l = sqrt(dot(s, s));
+    VT<T> sx = (val(l) > 1e-12) ? vscale(s, T(1.0) / l) : lift<T>(onb_x(k_in));
+    M4<T> Rin = rotator_t(k_in, lift<T>(canon_x(k_in)), sx);
+    M4<T> Rout = rotator_t(k_out, sx, lift<T>(canon_x(k_out)));
+    return mmul(mmul(Rout, Ml), Rin);
+}
 
-// GGX microfacet pBRDF value f(wi -> wo) in canonical frames (without the cosine).
-template <class T> static M4<T> ggx_f(V3 ns, V3 wi, V3 wo, T alpha, Cx<T> m) {
+// GGX microfacet pBRDF value f(wi -> wo) in canonical frames (without the cosine), for the
+// (possibly differentiated) shading normal ns.
+template <class T> static M4<T> ggx_f(const VT<T>& ns, V3 wi, V3 wo, T alpha, Cx<T> m) {
     V3 h = normalize(wi + wo);
-    double ci = dot(ns, wi), co = dot(ns, wo), chh = dot(ns, h), ih = std::fabs(dot(wi, h));
+    T ci = dot(ns, wi), co = dot(ns, wo), chh = dot(ns, h);
+    double ih = std::fabs(dot(wi, h));
     T D = ggx_D(chh, alpha);
     T G = smith_G1(ci, alpha) * smith_G1(co, alpha);
     M4<T> MR;
-    fresnel(ih, m, &MR, (M4<T>*)nullptr);
-    M4<T> Ml = mscale(MR, D * G / (4.0 * ci * co));
+    fresnel(T(ih), m, &MR, (M4<T>*)nullptr);
+    M4<T> Ml = mscale(MR, D * G / (ci * co * 4.0));
     return specular_canon(Ml, -wi, h, wo);
 }
 template <class T> static M4<T> diffuse_f(T rho) {
@@ -832,15 +934,15 @@ template <class T> static M4<T> diffuse_f(T rho) {
 
 // BSDF value (per channel) for light arriving along -wi and leaving along x.wo, canonical frames.
 template <class T>
-static void bsdf_eval(const Material& m, const Vtx& x, V3 wi, const PAcc<T>& P, M4<T> f[3]) {
+static void bsdf_eval(const Material& m, const Vtx& x, const VT<T>& ns, V3 wi, const PAcc<T>& P, M4<T> f[3]) {
     if (m.type == MAT_LAMBERT) {
         for (int c = 0; c < 3; ++c) f[c] = to_canon(diffuse_f(mat_albedo(P, m, c, x.u, x.v)), -wi, canon_x(-wi), x.wo, canon_x(x.wo));
     } else if (m.type == MAT_GGX_DIELECTRIC || m.type == MAT_GGX_CONDUCTOR) {
-        M4<T> g = ggx_f(x.ns, wi, x.wo, mat_alpha(P, m, x.u, x.v), mat_ior(P, m));
+        M4<T> g = mscale(ggx_f(ns, wi, x.wo, mat_alpha(P, m, x.u, x.v), mat_ior(P, m)), mat_spec(P, m, x.u, x.v));
         for (int c = 0; c < 3; ++c) f[c] = g;
     } else if (m.type == MAT_BLEND) {
         Cx<T> eta{P.get(m.eta_slot, m.eta_off), T(0.0)};
-        M4<T> g = ggx_f(x.ns, wi, x.wo, mat_alpha(P, m, x.u, x.v), eta);
+        M4<T> g = mscale(ggx_f(ns, wi, x.wo, mat_alpha(P, m, x.u, x.v), eta), mat_spec(P, m, x.u, x.v));
         for (int c = 0; c < 3; ++c) {
             M4<T> dl = to_canon(diffuse_f(mat_albedo(P, m, c, x.u, x.v)), -wi, canon_x(-wi), x.wo, canon_x(x.wo));
             f[c] = madd(mscale(dl, T((double)m.blend)), mscale(g, T(1.0 - (double)m.blend)));
@@ -858,32 +960,40 @@ template <class T>
 static void eval_vertex(const World& w, const Vtx& x, const PAcc<T>& P, VEval<T>& out) {
     const Material& m = w.mats[x.mat];
     for (int c = 0; c < 3; ++c) { out.E[c] = szero<T>(); out.W[c] = mzero<T>(); }
+    // the shading normal is a differentiated quantity when it comes from a normal map
+    const VT<T> ns = shading_normal(P, m, x);
     if (x.emit)
-        for (int c = 0; c < 3; ++c) out.E[c].s[0] = P.get(m.emit_slot, m.emit_off + c);
+        for (int c = 0; c < 3; ++c) {
+            T le = P.get(m.emit_slot, m.emit_off + c);
+            out.E[c].s[0] = le;
+            out.E[c].s[3] = le * (double)m.emit_circ;
+        }
     if (x.nee == 1) {
+        // light Stokes Le (1, 0, 0, circ): columns 0 and 3 of the BSDF Mueller matrix
         const LightRec& L = w.lights[x.light];
         M4<T> f[3];
-        bsdf_eval(m, x, x.wl, P, f);
-        double cx = dot(x.ns, x.wl);
+        bsdf_eval(m, x, ns, x.wl, P, f);
+        T cx = dot(ns, x.wl);
         for (int c = 0; c < 3; ++c) {
             T s = P.get(L.le_slot, L.le_off + c) * (cx * x.nee_geom);
-            for (int i = 0; i < 4; ++i) out.E[c].s[i] = out.E[c].s[i] + f[c].m[i][0] * s;
+            for (int i = 0; i < 4; ++i)
+                out.E[c].s[i] = out.E[c].s[i] + f[c].m[i][0] * s + f[c].m[i][3] * (s * (double)L.circ);
         }
     }
     switch (x.lobe) {
         case LOBE_DIFFUSE:
         case LOBE_GLOSSY: {
             // the selected lobe's own value: weight and selection probability are equal (blend)
-            double ci = dot(x.ns, x.wi);
+            T ci = dot(ns, x.wi);
             for (int c = 0; c < 3; ++c) {
                 M4<T> f;
                 if (x.lobe == LOBE_DIFFUSE)
                     f = to_canon(diffuse_f(mat_albedo(P, m, c, x.u, x.v)), -x.wi, canon_x(-x.wi), x.wo, canon_x(x.wo));
                 else {
                     Cx<T> eta = (m.type == MAT_BLEND) ? Cx<T>{P.get(m.eta_slot, m.eta_off), T(0.0)} : mat_ior(P, m);
-                    f = ggx_f(x.ns, x.wi, x.wo, mat_alpha(P, m, x.u, x.v), eta);
+                    f = mscale(ggx_f(ns, x.wi, x.wo, mat_alpha(P, m, x.u, x.v), eta), mat_spec(P, m, x.u, x.v));
                 }
-                out.W[c] = mscale(f, T(ci / x.pdf));
+                out.W[c] = mscale(f, ci / x.pdf);
             }
             break;
         }
@@ -893,12 +1003,13 @@ static void eval_vertex(const World& w, const Vtx& x, const PAcc<T>& P, VEval<T>
             T ecam = x.front ? T(1.0) : eta, efar = x.front ? eta : T(1.0);
             M4<T> M;
             if (x.lobe == LOBE_REFLECT) {
-                fresnel(dot(x.ns, x.wo), Cx<T>{efar / ecam, T(0.0)}, &M, (M4<T>*)nullptr);
-                M = specular_canon(M, -x.wi, x.ns, x.wo);
+                fresnel(dot(ns, x.wo), Cx<T>{efar / ecam, T(0.0)}, &M, (M4<T>*)nullptr);
+                M = x.nmap ? specular_canon(M, -x.wi, ns, x.wo) : specular_canon(M, -x.wi, x.ns, x.wo);
             } else {
                 // light crosses from the far side: incidence cosine |wi.n|, relative index ecam/efar
-                fresnel(std::fabs(dot(x.wi, x.ns)), Cx<T>{ecam / efar, T(0.0)}, (M4<T>*)nullptr, &M);
-                M = specular_canon(M, -x.wi, -x.ns, x.wo);
+                T cw = dot(ns, x.wi);
+                fresnel(val(cw) < 0.0 ? -cw : cw, Cx<T>{ecam / efar, T(0.0)}, (M4<T>*)nullptr, &M);
+                M = x.nmap ? specular_canon(M, -x.wi, vneg(ns), x.wo) : specular_canon(M, -x.wi, -x.ns, x.wo);
             }
             M = mscale(M, T(1.0 / x.prob));
             for (int c = 0; c < 3; ++c) out.W[c] = M;
@@ -927,11 +1038,14 @@ static int sensor(const View& vw, V3 k_cam, V3 x_sensor, const PAcc<T>& P, M4<T>
         S[0] = mmul(polarizer<T>(P.get(vw.theta_slot, vw.theta_off)), R);
         return 1;
     }
-    if (vw.sensor == SENSOR_ANALYZER4) {
+    if (vw.sensor == SENSOR_ANALYZER4 || vw.sensor == SENSOR_LIGHTSTAGE4) {
         S[0] = mmul(polarizer<double>(0.0), RT);
         S[1] = mmul(polarizer<double>(M_PI / 4), RT);
         S[2] = mmul(polarizer<double>(M_PI / 2), RT);
-        S[3] = mmul(mmul(polarizer<double>(M_PI / 4), retarder(M_PI / 2)), RT);
+        // circular analyzers: a quarter-wave plate at 0 then a polarizer at +45 degrees (passes
+        // s3 > 0, right-circular here) or at -45 degrees (passes s3 < 0, left-circular)
+        double a3 = vw.sensor == SENSOR_ANALYZER4 ? M_PI / 4 : -M_PI / 4;
+        S[3] = mmul(mmul(polarizer<double>(a3), retarder(M_PI / 2)), RT);
         return 4;
     }
     S[0] = RT;
@@ -1155,7 +1269,9 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
     }
 }
 
-static int n_analyzers(const View& v) { return v.sensor == SENSOR_ANALYZER4 ? 4 : 1; }
+static int n_analyzers(const View& v) {
+    return (v.sensor == SENSOR_ANALYZER4 || v.sensor == SENSOR_LIGHTSTAGE4) ? 4 : 1;
+}
 
 }  // namespace ora
 
@@ -1176,7 +1292,7 @@ extern "C" {
 void* ppto_scene_load(const void* blob, size_t nbytes, char* err, int errlen) {
     Reader r{(const uint8_t*)blob, nbytes};
     uint32_t hdr[4];
-    if (!r.get(hdr, 16) || hdr[0] != 0x31545050u || hdr[1] != 1u) { set_err(err, errlen, "bad header"); return nullptr; }
+    if (!r.get(hdr, 16) || hdr[0] != 0x31545050u || hdr[1] != 2u) { set_err(err, errlen, "bad header"); return nullptr; }
     Scene* sc = new Scene();
     sc->slot_numel.resize(hdr[2]);
     if (hdr[2] && !r.get(sc->slot_numel.data(), 4ull * hdr[2])) { delete sc; set_err(err, errlen, "truncated slots"); return nullptr; }
@@ -1356,8 +1472,8 @@ void ppto_canon_x(const double* k, double* x) {
 // GGX pBRDF value f (16, canonical frames) and the scalars D and G for a conductor/dielectric.
 void ppto_ggx_eval(const double* ns, const double* wi, const double* wo, double alpha, double m_re, double m_im,
                    double* f16) {
-    M4<double> f = ggx_f<double>(V3{ns[0], ns[1], ns[2]}, V3{wi[0], wi[1], wi[2]}, V3{wo[0], wo[1], wo[2]}, alpha,
-                                 Cx<double>{m_re, m_im});
+    M4<double> f = ggx_f<double>(VT<double>{ns[0], ns[1], ns[2]}, V3{wi[0], wi[1], wi[2]}, V3{wo[0], wo[1], wo[2]},
+                                 alpha, Cx<double>{m_re, m_im});
     for (int i = 0; i < 16; ++i) f16[i] = f.m[i / 4][i % 4];
 }
 int ppto_trace(void* scene, int world, const double* o, const double* d, double tmax, int any_hit, int brute,

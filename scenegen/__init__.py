@@ -18,7 +18,7 @@ import numpy as np
 
 # ----------------------------------------------------------------------------- constants
 MAGIC = 0x31545050  # 'PPT1'
-VERSION = 1
+VERSION = 2
 
 MAT_LAMBERT = 0        # depolarizing diffuse reflector (Sec. 4.1: only M00 is non-zero)
 MAT_DIELECTRIC = 1     # smooth dielectric interface, polarized Fresnel R/T (delta lobes)
@@ -31,6 +31,7 @@ MAT_BLEND = 6          # stochastic 50/50-style blend of a Lambertian and a GGX 
 SENSOR_NONE = 0        # output the full Stokes vector in the sensor frame
 SENSOR_POLARIZER = 1   # ideal linear polarizer at angle theta (a parameter)
 SENSOR_ANALYZER4 = 2   # four analyzers: 0, 45, 90 degree polarizers and QWP(0) + 45 degree polarizer
+SENSOR_LIGHTSTAGE4 = 3 # four analyzers: 0, 45, 90 degree polarizers and QWP(0) + -45 degree polarizer
 
 FLAG_NO_NEE = 1
 
@@ -49,19 +50,23 @@ MAT_DTYPE = np.dtype([
     ("eta_slot", "<i4"), ("eta_off", "<u4"),
     ("kappa_slot", "<i4"), ("kappa_off", "<u4"),
     ("emit_slot", "<i4"), ("emit_off", "<u4"),
-    ("axis", "<f4", 3), ("blend", "<f4"), ("reserved", "<u4", 3),
+    ("axis", "<f4", 3), ("blend", "<f4"),
+    ("emit_circ", "<f4"),
+    ("spec_slot", "<i4"), ("spec_off", "<u4"), ("spec_tw", "<u4"), ("spec_th", "<u4"),
+    ("normal_slot", "<i4"), ("normal_off", "<u4"), ("normal_tw", "<u4"), ("normal_th", "<u4"),
+    ("reserved", "<u4", 4),
 ])
-assert MAT_DTYPE.itemsize == 88
+assert MAT_DTYPE.itemsize == 128
 
 LIGHT_DTYPE = np.dtype([
     ("p0", "<f4", 3), ("eu", "<f4", 3), ("ev", "<f4", 3),
-    ("le_slot", "<i4"), ("le_off", "<u4"), ("pad", "<u4"),
+    ("le_slot", "<i4"), ("le_off", "<u4"), ("circ", "<f4"),
 ])
 assert LIGHT_DTYPE.itemsize == 48
 
 
 def analyzer_count(sensor: int) -> int:
-    return 4 if sensor == SENSOR_ANALYZER4 else 1
+    return 4 if sensor in (SENSOR_ANALYZER4, SENSOR_LIGHTSTAGE4) else 1
 
 
 # ----------------------------------------------------------------------------- containers
@@ -76,7 +81,7 @@ class World:
 
     def add_material(self, **kw) -> int:
         rec = np.zeros((), MAT_DTYPE)
-        for k in ("albedo_slot", "alpha_slot", "eta_slot", "kappa_slot", "emit_slot"):
+        for k in ("albedo_slot", "alpha_slot", "eta_slot", "kappa_slot", "emit_slot", "spec_slot", "normal_slot"):
             rec[k] = -1
         rec["blend"] = 0.5
         for k, v in kw.items():
@@ -103,13 +108,14 @@ class World:
     def add_sphere(self, c, r, mat):
         self.spheres.append((float(c[0]), float(c[1]), float(c[2]), float(r), int(mat)))
 
-    def add_light(self, p0, eu, ev, le_slot, le_off=0):
-        """Rectangular one-sided area light; adds its emitter geometry and its NEE record."""
-        m = self.add_material(type=MAT_EMITTER, emit_slot=le_slot, emit_off=le_off)
+    def add_light(self, p0, eu, ev, le_slot, le_off=0, circ=0.0):
+        """Rectangular one-sided area light; adds its emitter geometry and its NEE record.
+        circ is the degree of circular polarization of the emission, Le (1, 0, 0, circ)."""
+        m = self.add_material(type=MAT_EMITTER, emit_slot=le_slot, emit_off=le_off, emit_circ=circ)
         self.add_quad(p0, eu, ev, m)
         rec = np.zeros((), LIGHT_DTYPE)
         rec["p0"], rec["eu"], rec["ev"] = p0, eu, ev
-        rec["le_slot"], rec["le_off"] = le_slot, le_off
+        rec["le_slot"], rec["le_off"], rec["circ"] = le_slot, le_off, circ
         self.lights.append(rec)
 
     def n_tris(self):
@@ -178,13 +184,13 @@ class Workload:
 
 
 def image_numel(views) -> int:
-    a = np.where(views["sensor"] == SENSOR_ANALYZER4, 4, 1)
+    a = np.where(np.isin(views["sensor"], (SENSOR_ANALYZER4, SENSOR_LIGHTSTAGE4)), 4, 1)
     return int(np.sum(a * views["crop_w"].astype(np.int64) * views["crop_h"] * 12))
 
 
 def view_offsets(views) -> np.ndarray:
     """Float offset of each view's block in the concatenated [V][A][h][w][3][4] output."""
-    a = np.where(views["sensor"] == SENSOR_ANALYZER4, 4, 1)
+    a = np.where(np.isin(views["sensor"], (SENSOR_ANALYZER4, SENSOR_LIGHTSTAGE4)), 4, 1)
     sizes = a * views["crop_w"].astype(np.int64) * views["crop_h"] * 12
     return np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
 
@@ -503,7 +509,7 @@ def config5(seeds=range(50, 58), crop=None):
             remap[sc.slot(name)] = merged.add_slot(f"w{wi}_{name}", val)
         w = sc.worlds[0]
         for rec in w.materials:
-            for k in ("albedo_slot", "alpha_slot", "eta_slot", "kappa_slot", "emit_slot"):
+            for k in ("albedo_slot", "alpha_slot", "eta_slot", "kappa_slot", "emit_slot", "spec_slot", "normal_slot"):
                 if rec[k] >= 0:
                     rec[k] = remap[int(rec[k])]
         for rec in w.lights:
@@ -549,17 +555,134 @@ def polarizer_stack(n_sheets: int = 85, width: int = 1280, height: int = 720, sp
                     grad_slots=("floor_albedo",))
 
 
+# ----------------------------------------------------------------------------- light stage
+def normal_map(rng, h, w, amp, coarse=8):
+    """Tangent-space normal map input (t, b, n) = (gx, gy, 1) with smooth seeded slopes in
+    [-amp, amp]; the renderer normalises it."""
+    g = smooth_noise(rng, h, w, 2, coarse=coarse, lo=-amp, hi=amp)
+    return np.concatenate([g, np.ones((h, w, 1), np.float32)], -1).astype(np.float32)
+
+
+def _facing_rect(center, size):
+    """(p0, eu, ev) of a size x size rectangle centred at `center` emitting toward the origin."""
+    c = np.asarray(center, np.float64)
+    n = -c / np.linalg.norm(c)
+    a = np.cross(np.array([0.0, 1.0, 0.0]), n)
+    a = a / np.linalg.norm(a)
+    b = np.cross(n, a)
+    eu, ev = a * size, b * size
+    if np.dot(np.cross(eu, ev), n) < 0:
+        eu, ev = ev, eu
+    return c - 0.5 * (eu + ev), eu, ev
+
+
+def scene_lightstage(seed: int = 6, tex: int = 64):
+    """Virtual light stage (the paper's multi-view capture with right-circular illumination,
+    synthetic): a normal-mapped central object on a normal-mapped ground, a smooth dielectric and
+    a conductor with normal maps, ringed by eight right-circularly polarized area lights."""
+    rng = np.random.default_rng(seed)
+    sc = Scene()
+    w = sc.add_world()
+    s_ior = sc.add_slot("ior", [1.5])
+    # ground: Lambertian/GGX blend with albedo, roughness, specular and normal maps
+    s_galb = sc.add_slot("ground_albedo", smooth_noise(rng, tex, tex, 3))
+    s_grgh = sc.add_slot("ground_roughness", smooth_noise(rng, tex, tex, 1, lo=0.1, hi=0.5))
+    s_gspc = sc.add_slot("ground_specular", smooth_noise(rng, tex, tex, 1, lo=0.5, hi=1.0))
+    s_gnrm = sc.add_slot("ground_normal", normal_map(rng, tex, tex, 0.3))
+    m_ground = w.add_material(type=MAT_BLEND, albedo_slot=s_galb, albedo_tw=tex, albedo_th=tex,
+                              alpha_slot=s_grgh, alpha_tw=tex, alpha_th=tex, eta_slot=s_ior, blend=0.5,
+                              spec_slot=s_gspc, spec_tw=tex, spec_th=tex,
+                              normal_slot=s_gnrm, normal_tw=tex, normal_th=tex)
+    _ground(w, -1.0, 5.0, m_ground)
+    # central object (a stand-in for the captured bust): icosphere with all four maps
+    s_oalb = sc.add_slot("object_albedo", smooth_noise(rng, tex, tex, 3, coarse=6))
+    s_orgh = sc.add_slot("object_roughness", smooth_noise(rng, tex, tex, 1, coarse=6, lo=0.1, hi=0.6))
+    s_ospc = sc.add_slot("object_specular", smooth_noise(rng, tex, tex, 1, coarse=6, lo=0.4, hi=1.0))
+    s_onrm = sc.add_slot("object_normal", normal_map(rng, tex, tex, 0.4, coarse=12))
+    m_obj = w.add_material(type=MAT_BLEND, albedo_slot=s_oalb, albedo_tw=tex, albedo_th=tex,
+                           alpha_slot=s_orgh, alpha_tw=tex, alpha_th=tex, eta_slot=s_ior, blend=0.4,
+                           spec_slot=s_ospc, spec_tw=tex, spec_th=tex,
+                           normal_slot=s_onrm, normal_tw=tex, normal_th=tex)
+    base = icosphere(4)
+    w.add_tris(base * 0.9 + np.array([0.0, -0.1, 0.0]), sphere_uv(base), m_obj)
+    # smooth dielectric with a normal map: its s/p frames move with the shading normal
+    small = icosphere(3)
+    s_gnm = sc.add_slot("glass_normal", normal_map(rng, 32, 32, 0.2))
+    m_glass = w.add_material(type=MAT_DIELECTRIC, eta_slot=s_ior, normal_slot=s_gnm, normal_tw=32, normal_th=32)
+    w.add_tris(small * 0.5 + np.array([1.7, -0.5, 0.6]), sphere_uv(small), m_glass)
+    # GGX conductor with a constant specular scale and a normal map
+    s_meta = sc.add_slot("metal_eta", [0.6])
+    s_mkap = sc.add_slot("metal_kappa", [3.0])
+    s_mrgh = sc.add_slot("metal_roughness", [0.25])
+    s_mspc = sc.add_slot("metal_specular", [0.8])
+    s_mnrm = sc.add_slot("metal_normal", normal_map(rng, 32, 32, 0.3))
+    m_metal = w.add_material(type=MAT_GGX_CONDUCTOR, alpha_slot=s_mrgh, eta_slot=s_meta, kappa_slot=s_mkap,
+                             spec_slot=s_mspc, normal_slot=s_mnrm, normal_tw=32, normal_th=32)
+    w.add_tris(small * 0.5 + np.array([-1.7, -0.5, 0.4]), sphere_uv(small), m_metal)
+    # eight right-circular lights on a ring above the object, facing its centre
+    s_le = sc.add_slot("light_Le", [3.0, 3.0, 3.0])
+    for k in range(8):
+        a = 2 * np.pi * (k + 0.5) / 8
+        p0, eu, ev = _facing_rect((4.0 * np.cos(a), 3.5, 4.0 * np.sin(a)), 1.6)
+        w.add_light(p0, eu, ev, s_le, 0, circ=1.0)
+    return sc
+
+
+def lightstage(seed: int = 6, res: int = 256, spp: int = 16, n_views: int = 8, max_depth: int = 6) -> Workload:
+    """Multi-view light-stage capture: n_views cameras on a ring, each with the four analyzer
+    states 0, 45, 90 degrees and left-circular; gradients of the normal, specular and roughness
+    maps (the parameters of the paper's light-stage gradient study)."""
+    sc = scene_lightstage(seed)
+    views = []
+    for k in range(n_views):
+        a = 2 * np.pi * k / n_views
+        views.append(make_view(0, res, res, spp, (5.5 * np.cos(a), 1.2, 5.5 * np.sin(a)), (0.0, -0.3, 0.0),
+                               (0, 1, 0), 40.0, SENSOR_LIGHTSTAGE4, -1, 0, k))
+    return Workload("lightstage", sc, np.asarray(views, VIEW_DTYPE), max_depth=max_depth, seed=seed,
+                    grad_slots=("ground_normal", "ground_specular", "ground_roughness", "object_normal",
+                                "object_specular", "object_roughness", "glass_normal", "metal_normal",
+                                "metal_specular"))
+
+
+def tilted_plane_scene(phi=0.0, theta_light=0.5, material=MAT_LAMBERT, spec=None, normal_map_on=True):
+    """A plane y = 0 (tangent +x along u) whose constant normal map tilts the shading normal by
+    phi toward +x, lit by a tiny light at angle theta_light from the geometric normal in the
+    xy-plane; the camera looks straight down at the origin through a very narrow field."""
+    sc = Scene()
+    s_alb = sc.add_slot("albedo", [0.6, 0.5, 0.4])
+    s_rgh = sc.add_slot("roughness", [0.3])
+    s_ior = sc.add_slot("ior", [1.5])
+    s_nrm = sc.add_slot("normal", [np.sin(phi), 0.0, np.cos(phi)])
+    s_spc = sc.add_slot("specular", [1.0 if spec is None else spec])
+    s_le = sc.add_slot("light_Le", [5.0, 5.0, 5.0])
+    w = sc.add_world()
+    kw = dict(type=material, albedo_slot=s_alb, alpha_slot=s_rgh, eta_slot=s_ior)
+    if normal_map_on:
+        kw.update(normal_slot=s_nrm)
+    if spec is not None:
+        kw.update(spec_slot=s_spc)
+    m = w.add_material(**kw)
+    # eu = +x (u), ev = -z: normal eu x ev = +y, tangent +x, bitangent +y x +x = -z
+    w.add_quad((-50.0, 0.0, 50.0), (100.0, 0.0, 0.0), (0.0, 0.0, -100.0), m)
+    d = 20.0
+    c = np.array([d * np.sin(theta_light), d * np.cos(theta_light), 0.0])
+    p0, eu, ev = _facing_rect(c, 1e-3)
+    w.add_light(p0, eu, ev, s_le)
+    return sc
+
+
 # ----------------------------------------------------------------------------- closed-form test scenes
-def emitter_wall_scene(le=10.0, sheets=(), z_light=-5.0, size=50.0):
-    """Camera at the origin looking down -z at a huge one-sided emitter; optional polarizer
-    sheets (axis angles in radians, measured from +x toward +y) stacked in between."""
+def emitter_wall_scene(le=10.0, sheets=(), z_light=-5.0, size=50.0, circ=0.0):
+    """Camera at the origin looking down -z at a huge one-sided emitter (Stokes Le (1, 0, 0,
+    circ)); optional polarizer sheets (axis angles in radians, measured from +x toward +y)
+    stacked in between."""
     sc = Scene()
     s_theta = sc.add_slot("theta", [0.0])
     s_le = sc.add_slot("light_Le", [le, le, le])
     w = sc.add_world()
     h = size / 2
     # emitter facing +z: eu x ev = +z -> eu = +x, ev = +y
-    w.add_light((-h, -h, z_light), (size, 0, 0), (0, size, 0), s_le)
+    w.add_light((-h, -h, z_light), (size, 0, 0), (0, size, 0), s_le, circ=circ)
     n = len(sheets)
     for i, a in enumerate(sheets):
         z = -1.0 - (i + 1) * (abs(z_light) - 2.0) / (n + 1)
