@@ -90,8 +90,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=48, help="full views in the oracle sample")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
-    ap.add_argument("--workload", choices=("batched128", "uneven8", "optimise", "depth_sweep"), default="batched128",
+    ap.add_argument("--workload", choices=("batched128", "uneven8", "lightstage", "optimise", "depth_sweep"),
+                    default="batched128",
                     help="batched128: 128 views of one scene (the headline); uneven8: eight worlds of uneven size; "
+                         "lightstage: 8 views with circular lights, four analyzers and normal/specular maps; "
                          "optimise: Adam recovery of textures and lights through the autograd wrapper; "
                          "depth_sweep: time and memory against the maximum depth behind an 85-sheet polarizer stack")
     ap.add_argument("--opt-steps", type=int, default=200)
@@ -276,6 +278,12 @@ def main():
         wl = sg.config3(res=args.res, spp=args.spp)
         desc = (f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), {args.res}x{args.res}, "
                 f"{args.spp} spp, depth {wl.max_depth}, 20.5k-triangle icosphere scene, render + PRB backward, "
+                "HIP-graph replay")
+    elif args.workload == "lightstage":
+        wl = sg.lightstage()
+        desc = (f"light stage: {len(wl.views)} views on a ring, {int(wl.views[0]['width'])}^2, "
+                f"{int(wl.views[0]['spp'])} spp, depth {wl.max_depth}, 8 right-circular lights, analyzers 0/45/90 "
+                "degrees and left-circular, normal/specular/roughness maps (7.7k triangles), render + PRB backward, "
                 "HIP-graph replay")
     else:
         wl = sg.config5()

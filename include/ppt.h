@@ -43,6 +43,8 @@ extern "C" {
 #define PPT_SENSOR_NONE 0      /* full Stokes vector in the sensor frame */
 #define PPT_SENSOR_POLARIZER 1 /* ideal linear polarizer at angle theta (a parameter, radians) */
 #define PPT_SENSOR_ANALYZER4 2 /* polarizers at 0, 45, 90 degrees and QWP(0) followed by 45 degrees */
+#define PPT_SENSOR_LIGHTSTAGE4 3 /* polarizers at 0, 45, 90 degrees and QWP(0) followed by -45 degrees
+                                    (a left-circular analyzer: it passes s3 < 0) */
 
 /* One camera view (88 bytes, host memory).  The image is width x height pixels; only the
  * window [crop_x0, crop_x0 + crop_w) x [crop_y0, crop_y0 + crop_h) is rendered.  The
@@ -74,20 +76,34 @@ typedef struct ppt_scene ppt_scene;
 typedef struct ppt_plan ppt_plan;
 
 /* Scene blob (little-endian, 32-bit words unless stated):
- *   header     magic 0x31545050 ('PPT1'), version 1, n_slots (<= 64), n_worlds
+ *   header     magic 0x31545050 ('PPT1'), version 2, n_slots (<= 64), n_worlds
  *   slots      n_slots element counts (the float32 parameter tensors of every call)
  *   per world  n_tris, n_spheres, n_materials, n_lights, then
  *              triangles: n_tris x 9 floats (v0, v1, v2), n_tris x 6 floats (uv0, uv1, uv2),
  *                         n_tris material indices;
  *              spheres:   n_spheres x 4 floats (centre, signed radius: < 0 = inward normal),
  *                         n_spheres material indices;
- *              materials: 88-byte records {type; albedo slot, offset, texture width, height;
+ *              materials: 128-byte records {type; albedo slot, offset, texture width, height;
  *                         roughness slot, offset, width, height; eta slot, offset; kappa slot,
- *                         offset; emission slot, offset; sheet axis[3]; blend; 3 reserved}
+ *                         offset; emission slot, offset; sheet axis[3]; blend; emission circ;
+ *                         specular-map slot, offset, width, height; normal-map slot, offset,
+ *                         width, height; 4 reserved}
  *                         (slot -1 = absent, width 0 = constant, texture layout [h][w][ch]);
- *              lights:    48-byte records {p0[3], eu[3], ev[3]; radiance slot, offset; pad},
+ *              lights:    48-byte records {p0[3], eu[3], ev[3]; radiance slot, offset; circ},
  *                         one-sided rectangles emitting along eu x ev (their geometry is also
  *                         present as two triangles with an emitter material).
+ *   Emission: an emitter radiates the Stokes vector Le (1, 0, 0, circ) per RGB channel, circ in
+ *   [-1, 1] the degree of circular polarization (right-circular = s3 > 0 in this library's
+ *   Stokes convention; circular polarization needs no transverse frame).  A light record and
+ *   the emitter material of its geometry should carry the same circ.
+ *   Specular map (GGX types and the blend): a 1-channel scale of the GGX lobe (absent = 1).
+ *   Normal map (every scattering type; triangles only, spheres keep their geometric normal):
+ *   3 channels (t, b, n) give the outward shading normal normalize(t T + b B + n N), with N the
+ *   geometric normal, T the unit tangent along increasing u (dP/du made perpendicular to N; the
+ *   canonical basis of N for a degenerate uv map) and B = N x T.  A vertex seen from behind its
+ *   shading normal is black (its emission still counts); a light sample or a sampled direction
+ *   on the wrong side of the geometric surface is discarded.  The shading normal is
+ *   differentiated, including the s/p frames of the smooth dielectric.
  *   Material types: 0 Lambertian, 1 smooth dielectric, 2 GGX dielectric (reflection),
  *   3 GGX conductor (complex IOR eta + i kappa), 4 linear polarizer sheet, 5 emitter,
  *   6 Lambertian/GGX-dielectric blend (lobe probability = blend).

@@ -194,6 +194,39 @@ DEV cf fresnel_T_vjp(float ci, cf m, float ga, float gb, float gc, float gd) {
     return cadd(g, cscale(cconj(du), gk / ci));
 }
 
+// d(loss)/d ci of the reflection entries (a moving shading normal changes the incidence cosine):
+// d ct/d ci = ci / (m^2 ct), drs/d ci = 2 (u - ci u') / (ci + u)^2 with u = m ct,
+// drp/d ci = 2 m (ct - ci ct') / (m ci + ct)^2.
+DEV float fresnel_R_dci(float ci, cf m, float ga, float gb, float gc, float gd) {
+    Fres F;
+    fresnel_amp(ci, m, F, false);
+    cf g_rs, g_rp;
+    jones_abcd_vjp(F.rs, F.rp, ga, gb, gc, gd, g_rs, g_rp);
+    cf dct = cdiv(cf{ci, 0.0f}, cmul(cmul(m, m), F.ct));
+    cf u = cmul(m, F.ct), du = cmul(m, dct);
+    cf cu = cadd(cf{ci, 0.0f}, u), cv = cadd(cscale(m, ci), F.ct);
+    cf drs = cdiv(cscale(csub(u, cscale(du, ci)), 2.0f), cmul(cu, cu));
+    cf drp = cdiv(cmul(cscale(m, 2.0f), csub(F.ct, cscale(dct, ci))), cmul(cv, cv));
+    return cmul(g_rs, cconj(drs)).re + cmul(g_rp, cconj(drp)).re;
+}
+// the same for the flux-form transmission entries kappa (a, b, c, d)(ts, tp), kappa = Re(m ct)/ci
+DEV float fresnel_T_dci(float ci, cf m, float ga, float gb, float gc, float gd) {
+    Fres F;
+    fresnel_amp(ci, m, F, true);
+    float a, b, c, d;
+    jones_abcd(F.ts, F.tp, a, b, c, d);
+    float gk = ga * a + gb * b + gc * c + gd * d;
+    cf g_ts, g_tp;
+    jones_abcd_vjp(F.ts, F.tp, F.kappa * ga, F.kappa * gb, F.kappa * gc, F.kappa * gd, g_ts, g_tp);
+    cf dct = cdiv(cf{ci, 0.0f}, cmul(cmul(m, m), F.ct));
+    cf u = cmul(m, F.ct), du = cmul(m, dct);
+    cf cu = cadd(cf{ci, 0.0f}, u), cv = cadd(cscale(m, ci), F.ct);
+    cf dts = cdiv(cscale(csub(u, cscale(du, ci)), 2.0f), cmul(cu, cu));
+    cf dtp = cdiv(cscale(csub(F.ct, cscale(dct, ci)), 2.0f), cmul(cv, cv));
+    float dkap = du.re / ci - u.re / (ci * ci);
+    return cmul(g_ts, cconj(dts)).re + cmul(g_tp, cconj(dtp)).re + gk * dkap;
+}
+
 // ============================================================================ GGX
 DEV float ggx_D(float ch, float a) {
     if (ch <= 0.0f) return 0.0f;
@@ -215,6 +248,17 @@ DEV float smith_dlnG1(float cw, float a) {
     float s = sqrtf(1.0f + a * a * t2);
     float lam = 0.5f * (s - 1.0f);
     return -(a * t2 / (2.0f * s)) / (1.0f + lam);
+}
+// d ln D / d cos_h and d ln G1 / d cos_w (derivatives along a moving shading normal)
+DEV float ggx_dlnD_dc(float ch, float a) {
+    float a2 = a * a, d = (a2 - 1.0f) * ch * ch + 1.0f;
+    return -4.0f * ch * (a2 - 1.0f) / d;
+}
+DEV float smith_dlnG1_dc(float cw, float a) {
+    float t2 = (1.0f - cw * cw) / (cw * cw);
+    float s = sqrtf(1.0f + a * a * t2);
+    float lam = 0.5f * (s - 1.0f);
+    return a * a / (2.0f * s * cw * cw * cw * (1.0f + lam));
 }
 
 // ============================================================================ scene access
@@ -280,10 +324,12 @@ struct Call {
 // Per-vertex gradient of the parameters a vertex reads, combined over its next-event and
 // continuation terms before it is scattered (one bilinear scatter per texture).
 struct GradVtx {
-    float rho[3], alpha, eta, kap, le[3], emit[3];
+    float rho[3], alpha, eta, kap, le[3], emit[3], ks;
+    v3 gns;  // d(loss)/d(shading normal) of a normal-mapped vertex
     DEV void zero() {
-        rho[0] = rho[1] = rho[2] = 0.0f; alpha = eta = kap = 0.0f;
+        rho[0] = rho[1] = rho[2] = 0.0f; alpha = eta = kap = ks = 0.0f;
         le[0] = le[1] = le[2] = 0.0f; emit[0] = emit[1] = emit[2] = 0.0f;
+        gns = mk(0.0f, 0.0f, 0.0f);
     }
 };
 
@@ -346,6 +392,34 @@ DEV void rough_scatter(const Call& K, const DevMaterial& m, float u, float v, fl
     bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
 #pragma unroll
     for (int k = 0; k < 4; ++k) K.g(m.alpha_slot, m.alpha_off + B.i[k], g * B.w[k]);
+}
+// channel c of a constant (tw = 0) or bilinear texture with ch channels, and its scatter
+DEV float tex_read(const Call& K, int slot, int off, int tw, int th, int ch, int c, float u, float v) {
+    if (tw == 0) return K.p(slot, off + c);
+    Bilin B;
+    bilin(u, v, tw, th, ch, B);
+    float r = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r += K.p(slot, off + B.i[k] + c) * B.w[k];
+    return r;
+}
+template <int CH>
+DEV void tex_scatter(const Call& K, int slot, int off, int tw, int th, float u, float v, const float* g) {
+    if (tw == 0) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) K.g(slot, off + c, g[c]);
+        return;
+    }
+    Bilin B;
+    bilin(u, v, tw, th, CH, B);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) K.g(slot, off + B.i[k] + c, g[c] * B.w[k]);
+}
+// specular map: scale of the GGX lobe (1 without a map)
+DEV float spec_scale(const Call& K, const DevMaterial& m, float u, float v) {
+    return m.spec_slot < 0 ? 1.0f : tex_read(K, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, 1, 0, u, v);
 }
 DEV cf ior(const Call& K, const DevMaterial& m) {
     return cf{K.p(m.eta_slot, m.eta_off), m.kap_slot >= 0 ? K.p(m.kap_slot, m.kap_off) : 0.0f};
@@ -503,7 +577,8 @@ DEV v3 spawn(v3 p, v3 ng, v3 dir) {
 struct Vtx {
     v3 p, ng, ns, wo, wi, wl;
     float u, v;
-    int mat, orig;
+    int mat, orig, prim;  // prim: primitive record index (BVH order)
+    bool tri, nmap;       // a triangle; its material has a normal map (ns comes from it)
     bool front, emit;
     int lobe, nee, light;
     float prob, pdf, nee_geom;
@@ -526,7 +601,9 @@ DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
     const float4* pr = W.prims + 3 * h.prim;
     float4 A = ldg4(pr, 0), B = ldg4(pr, 1);
     x.orig = __float_as_int(A.w);
-    if (__float_as_int(B.w) == 0) {
+    x.prim = h.prim;
+    x.tri = __float_as_int(B.w) == 0;
+    if (x.tri) {
         float4 C = ldg4(pr, 2);
         v3 e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
         x.p = mk(A.x, A.y, A.z) + e1 * h.u + e2 * h.v;
@@ -543,6 +620,42 @@ DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
         x.v = acosf(fminf(fmaxf(nout.y, -1.0f), 1.0f)) * (1.0f / PI_F);
     }
     x.mat = gval(W.prim_mat, (size_t)x.orig);
+}
+
+// Tangent frame of a triangle hit at its outward geometric normal ng: the tangent follows
+// increasing u (dP/du of the triangle's uv map, made perpendicular to ng; the canonical basis of
+// ng for a degenerate uv map), the bitangent is ng x tangent.
+DEV void tangent_frame(const DevWorld& W, const Vtx& x, v3& tg, v3& bt) {
+    const float4* pr = W.prims + 3 * x.prim;
+    float4 Bq = ldg4(pr, 1), Cq = ldg4(pr, 2);
+    v3 e1 = mk(Bq.x, Bq.y, Bq.z), e2 = mk(Cq.x, Cq.y, Cq.z);
+    const float* t = W.tri_uv + 6 * (size_t)x.orig;
+    float u0 = gval(t, 0), v0 = gval(t, 1);
+    float du1 = gval(t, 2) - u0, dv1 = gval(t, 3) - v0, du2 = gval(t, 4) - u0, dv2 = gval(t, 5) - v0;
+    float det = du1 * dv2 - du2 * dv1;
+    v3 dpdu = (e1 * dv2 - e2 * dv1) * (det < 0.0f ? -1.0f : 1.0f);
+    v3 tp = dpdu - x.ng * dot(dpdu, x.ng);
+    float l = sqrtf(dot(tp, tp));
+    if (det == 0.0f || !(l > 1e-6f * (sqrtf(dot(e1, e1)) + sqrtf(dot(e2, e2))))) {
+        v3 yy;
+        onb(x.ng, tg, yy);
+    } else {
+        tg = tp * (1.0f / l);
+    }
+    bt = cross(x.ng, tg);
+}
+// Normal-mapped shading normal toward the viewer side: the map's tangent-space components
+// (t, b, n) give the outward normal normalize(t T + b B + n N).  il = +-1 / |t T + b B + n N|.
+DEV v3 mapped_normal(const DevWorld& W, const Call& K, const DevMaterial& m, const Vtx& x, v3& tg, v3& bt, float& il) {
+    tangent_frame(W, x, tg, bt);
+    float c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = tex_read(K, m.nrm_slot, m.nrm_off, m.nrm_tw, m.nrm_th, 3, k, x.u, x.v);
+    v3 n = mk(c[0] * tg.x + c[1] * bt.x + c[2] * x.ng.x, c[0] * tg.y + c[1] * bt.y + c[2] * x.ng.y,
+              c[0] * tg.z + c[1] * bt.z + c[2] * x.ng.z);
+    il = 1.0f / sqrtf(dot(n, n));
+    if (!x.front) il = -il;
+    return n * il;
 }
 
 DEV int sample_glossy(v3 ns, v3 wo, float alpha, float u1, float u2, v3& wi, float& pdf) {
@@ -585,6 +698,9 @@ constexpr int NEE_NONE = 0, NEE_VISIBLE = 1, NEE_OCCLUDED = 2, NEE_ZERO = 3, NEE
 // emission rule, the next-event light sample, the lobe choice and continuation direction.
 // When the light sample needs a visibility test, x.nee = NEE_PENDING and (so, sd, stmax)
 // describe the shadow ray; the caller resolves it (a shadow-ray kernel, or a recorded flag).
+// EXT: the extended material features (normal maps, specular maps, circularly polarized
+// emitters) are compiled in; kernels of scenes without them skip that code.
+template <bool EXT>
 DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64_t seed, uint32_t pix, uint32_t smp,
                       int b, int max_depth, uint32_t flags, bool prev_delta, v3 d, Vtx& x, v3& so, v3& sd,
                       float& stmax) {
@@ -592,11 +708,24 @@ DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64
     x.wo = -d;
     x.front = dot(x.ng, x.wo) > 0.0f;
     x.ns = x.front ? x.ng : -x.ng;
+    const v3 ngf = x.ns;  // geometric normal on the viewer side
+    x.nmap = EXT && m.nrm_slot >= 0 && x.tri;
+    if (x.nmap) {
+        v3 tg, bt;
+        float il;
+        x.ns = mapped_normal(W, K, m, x, tg, bt, il);
+    }
     x.emit = m.emit_slot >= 0 && x.front && (b == 1 || prev_delta || (flags & FLAG_NO_NEE));
     x.lobe = LOBE_NONE;
     x.nee = NEE_NONE;
     x.prob = 1.0f; x.pdf = 1.0f; x.nee_geom = 0.0f; x.light = 0;
     if (m.type == MAT_EMITTER || b == max_depth) return;
+    // a normal-mapped vertex seen from behind its shading normal neither scatters nor samples a light
+    if (x.nmap && !(dot(x.ns, x.wo) > 0.0f)) {
+        x.nee = NEE_ZERO;
+        x.lobe = LOBE_INVALID;
+        return;
+    }
     float ua[4], ub[4];
     uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 0, ua);
     uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 1, ub);
@@ -610,7 +739,8 @@ DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64
         x.wl = dv * (1.0f / dist);
         x.light = li;
         float cos_y = -dot(ld3(L.n), x.wl), cos_x = dot(x.ns, x.wl);
-        if (!(cos_y > 0.0f) || !(cos_x > 0.0f)) {
+        // with a normal map the light must also lie above the geometric surface
+        if (!(cos_y > 0.0f) || !(cos_x > 0.0f) || (x.nmap && !(dot(ngf, x.wl) > 0.0f))) {
             x.nee = NEE_ZERO;
         } else {
             so = spawn(x.p, x.ng, x.wl);
@@ -669,6 +799,12 @@ DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64
             break;
         default:
             x.lobe = LOBE_INVALID;
+    }
+    // with a normal map, a reflected direction must leave above the geometric surface and a
+    // transmitted one below it
+    if (x.nmap && x.lobe != LOBE_INVALID && x.lobe != LOBE_SHEET) {
+        float side = dot(ngf, x.wi);
+        if (x.lobe == LOBE_TRANSMIT ? !(side < 0.0f) : !(side > 0.0f)) x.lobe = LOBE_INVALID;
     }
 }
 
@@ -745,29 +881,80 @@ DEV void ggx_eval(const Call& K, const DevMaterial& m, const Vtx& x, v3 wi, cf e
     g.w.rgb[0] = g.w.rgb[1] = g.w.rgb[2] = 1.0f;
     g.w.kind = 2;
 }
-// gradient of a GGX lobe scaled by s: entries of s*kappa*F0 have local adjoint (gA..gD)
-DEV void ggx_backprop(const Vtx& x, cf eta, const GGXv& g, float s, float gA, float gB, float gC, float gD,
-                      GradVtx& gv) {
-    float sk = s * g.kappa;
-    float gk = s * (g.a * gA + g.b * gB + g.c * gC + g.d * gD);  // d/d kappa
+// Gradient of a GGX lobe with entries s ks kappa (a, b, c, d) whose local adjoints are gA..gD
+// (ks the specular-map scale).  Returns d(loss)/d ln kappa for the shading-normal chain.
+DEV float ggx_backprop(const Vtx& x, cf eta, const GGXv& g, float s, float ks, float gA, float gB, float gC, float gD,
+                       GradVtx& gv) {
+    float q = s * (g.a * gA + g.b * gB + g.c * gC + g.d * gD);  // d/d(ks kappa)
+    float jk = q * ks * g.kappa;
+    gv.ks += q * g.kappa;
     if (g.in && g.kappa != 0.0f) {
         float dln = ggx_dlnD(g.ch, g.alpha) + smith_dlnG1(g.ci, g.alpha) + smith_dlnG1(g.co, g.alpha);
-        gv.alpha += gk * g.kappa * dln;
+        gv.alpha += jk * dln;
     }
+    float sk = s * ks * g.kappa;
     cf gm = fresnel_R_vjp(g.ih, eta, sk * gA, sk * gB, sk * gC, sk * gD);
     gv.eta += gm.re;
     gv.kap += gm.im;
+    return jk;
+}
+// d ln(kappa cos_i) / d ns of a GGX lobe for light arriving along -wi (the 1/cos_i inside kappa
+// cancels the cosine factor of the weight): D through cos_h, G1 through cos_i and cos_o, 1/cos_o
+DEV v3 ggx_dln_dns(const GGXv& g, v3 wi, v3 wo) {
+    v3 h = normalize(wi + wo);
+    return h * ggx_dlnD_dc(g.ch, g.alpha) + wi * smith_dlnG1_dc(g.ci, g.alpha) +
+           wo * (smith_dlnG1_dc(g.co, g.alpha) - 1.0f / g.co);
+}
+// d(loss)/d of the rotator entries (ci, si, co, so) of a Fresnel-form weight: sum_c a_c^T W_c L_c
+DEV void w_frame_grad(const WC& w, const float* a, const float* L, float& gci, float& gsi, float& gco, float& gso) {
+    gci = gsi = gco = gso = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float* ac = a + 4 * c;
+        const float* Lc = L + 4 * c;
+        float s = w.rgb[c];
+        float v1 = w.ci * Lc[1] + w.si * Lc[2], v2 = -w.si * Lc[1] + w.ci * Lc[2];
+        float f1 = w.B * Lc[0] + w.A * v1, f2 = w.C * v2 + w.D * Lc[3];
+        float r1 = w.co * ac[1] - w.so * ac[2], r2 = w.so * ac[1] + w.co * ac[2];
+        gco += s * (ac[1] * f1 + ac[2] * f2);
+        gso += s * (ac[1] * f2 - ac[2] * f1);
+        float d1 = s * (ac[0] * w.B + r1 * w.A), d2 = s * (r2 * w.C - ac[3] * w.D);
+        gci += d1 * Lc[1] + d2 * Lc[2];
+        gsi += d1 * Lc[2] - d2 * Lc[1];
+    }
+}
+// d(loss)/d n_inc through the two rotators of a specular event (spec_frames), given the adjoints
+// of their entries: c = x_from . s, sn = (k x x_from) . s, (C, S) = (c^2 - sn^2, 2 c sn), and
+// s = normalize(k_in x n_inc)
+DEV v3 spec_frames_grad(v3 k_in, v3 n_inc, v3 k_out, float gci, float gsi, float gco, float gso) {
+    v3 sr = cross(k_in, n_inc);
+    float l2 = dot(sr, sr);
+    if (l2 < 1e-16f) return mk(0.0f, 0.0f, 0.0f);  // normal incidence: the axis is fixed
+    float il = 1.0f / sqrtf(l2);
+    v3 s = sr * il;
+    v3 xi = canon_x(k_in), yi = cross(k_in, xi);
+    float c1 = dot(xi, s), s1 = dot(yi, s);
+    v3 gs = xi * (2.0f * (c1 * gci + s1 * gsi)) + yi * (2.0f * (c1 * gsi - s1 * gci));
+    v3 xo = canon_x(k_out), yo = cross(xo, k_out);
+    float c2 = dot(s, xo), s2 = dot(s, yo);
+    gs = gs + xo * (2.0f * (c2 * gco + s2 * gso)) + yo * (2.0f * (c2 * gso - s2 * gco));
+    v3 gsr = (gs - s * dot(s, gs)) * il;
+    return cross(gsr, k_in);
 }
 
 // W_b and E_b of a vertex (values), and with GRAD their vector-Jacobian products against the
 // adjoint rows a (3 x 4, canonical frame of wo) and the cached suffix Ln (3 x 4, frame of -wi):
 // d(sum_c a_c . (E_c + W_c Ln_c)) / d params, accumulated through Call.
 // Eemit receives the emission of the vertex and Enee the next-event part (computed when the
-// light sample is visible or still pending).
-template <bool GRAD>
+// light sample is visible or still pending).  Emitters radiate Le (1, 0, 0, circ).  With a
+// normal map the shading normal x.ns is differentiated too: every cosine, the GGX D and G
+// terms, the dielectric's Fresnel incidence cosine and its s/p frames.  EXT: the extended
+// material features are compiled in (without them: no circular emission, no maps).
+template <bool GRAD, bool EXT>
 DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, float* Eemit, float* Enee, const float* a,
                      const float* Ln) {
     const DevMaterial m = gval(W.mats, (size_t)x.mat);
+    const bool nm = EXT && x.nmap;
 #pragma unroll
     for (int i = 0; i < 12; ++i) { Eemit[i] = 0.0f; Enee[i] = 0.0f; }
     GradVtx gv;
@@ -776,11 +963,13 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
     if (x.emit) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Eemit[4 * c] = K.p(m.emit_slot, m.emit_off + c);
-            if (GRAD) gv.emit[c] += a[4 * c];
+            float le = K.p(m.emit_slot, m.emit_off + c);
+            Eemit[4 * c] = le;
+            if (EXT) Eemit[4 * c + 3] = le * m.emit_circ;
+            if (GRAD) gv.emit[c] += EXT ? a[4 * c] + m.emit_circ * a[4 * c + 3] : a[4 * c];
         }
     }
-    // next-event estimation: E_c += f_c e0 * cos_x * geom * Le_c
+    // next-event estimation: E_c += f_c (e0 + circ e3) * cos_x * geom * Le_c
     if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
         const DevLight L = gval(W.lights, (size_t)x.light);
         float cx = dot(x.ns, x.wl);
@@ -793,6 +982,7 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
         else if (m.type == MAT_BLEND) { wd = m.blend; wg = 1.0f - m.blend; }
         else if (m.type == MAT_GGX_DIELECTRIC || m.type == MAT_GGX_CONDUCTOR) wg = 1.0f;
         if (wd != 0.0f) {
+            float jl = 0.0f;  // this term's share of the loss (linear in cos_x)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float rho = albedo(K, m, c, x.u, x.v);
@@ -800,22 +990,32 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
                 if (GRAD) {
                     gv.rho[c] += a[4 * c] * wd * gs * le[c] * (1.0f / PI_F);
                     gv.le[c] += a[4 * c] * wd * rho * gs * (1.0f / PI_F);
+                    jl += a[4 * c] * wd * rho * gs * le[c] * (1.0f / PI_F);
                 }
             }
+            if (GRAD && nm) gv.gns = gv.gns + x.wl * (jl / cx);
         }
         if (wg != 0.0f) {
             bool real_ior = m.type != MAT_GGX_CONDUCTOR;
             cf eta = real_ior ? cf{K.p(m.eta_slot, m.eta_off), 0.0f} : ior(K, m);
             GGXv g;
             ggx_eval(K, m, x, x.wl, eta, g);
-            // f e0 = Rout kappa (a, b, 0, 0) = kappa (a, Cout b, -Sout b, 0)
-            float e0 = g.kappa * g.a, e1 = g.kappa * g.w.co * g.b, e2 = -g.kappa * g.w.so * g.b;
+            const float ks = EXT ? spec_scale(K, m, x.u, x.v) : 1.0f, kk = g.kappa * ks;
+            const float circ = EXT ? L.circ : 0.0f;
+            // columns 0 and 3 of Rout F Rin: kappa (a, Cout b, -Sout b, 0) and kappa (0, Sout d, Cout d, c)
+            float col[4] = {kk * g.a, kk * g.w.co * g.b, -kk * g.w.so * g.b, 0.0f};
+            if (EXT) {
+                col[1] += kk * circ * g.w.so * g.d;
+                col[2] += kk * circ * g.w.co * g.d;
+                col[3] = kk * circ * g.c;
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float s = wg * gs * le[c];
-                Enee[4 * c] += s * e0; Enee[4 * c + 1] += s * e1; Enee[4 * c + 2] += s * e2;
+                Enee[4 * c] += s * col[0]; Enee[4 * c + 1] += s * col[1]; Enee[4 * c + 2] += s * col[2];
+                if (EXT) Enee[4 * c + 3] += s * col[3];
             }
-            if (GRAD) {
+            if (GRAD && !EXT) {
                 float qa = 0.0f, qb = 0.0f;  // sum_c s_c (a_c0) and sum_c s_c (a_c1 Cout - a_c2 Sout)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -824,8 +1024,21 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
                     qa += s * q; qb += s * r;
                     gv.le[c] += wg * gs * g.kappa * (q * g.a + r * g.b);
                 }
-                // local adjoint of kappa*F0 entries: e0 = kappa a, e1/e2 = kappa b rotated
-                ggx_backprop(x, eta, g, 1.0f, qa, qb, 0.0f, 0.0f, gv);
+                ggx_backprop(x, eta, g, 1.0f, 1.0f, qa, qb, 0.0f, 0.0f, gv);
+            }
+            if (GRAD && EXT) {
+                float Lv[12];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float s = wg * gs * le[c];
+                    Lv[4 * c] = s; Lv[4 * c + 1] = 0.0f; Lv[4 * c + 2] = 0.0f; Lv[4 * c + 3] = circ * s;
+                    gv.le[c] += wg * gs * (a[4 * c] * col[0] + a[4 * c + 1] * col[1] + a[4 * c + 2] * col[2] +
+                                           a[4 * c + 3] * col[3]);
+                }
+                float gA, gB, gC, gD;
+                w_local_grad(g.w, a, Lv, gA, gB, gC, gD);
+                float jk = ggx_backprop(x, eta, g, 1.0f, ks, gA, gB, gC, gD, gv);
+                if (nm && jk != 0.0f) gv.gns = gv.gns + ggx_dln_dns(g, x.wl, x.wo) * jk;
             }
         }
     }
@@ -833,11 +1046,17 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
     switch (x.lobe) {
         case LOBE_DIFFUSE: {
             w.kind = 1;
+            float jw = 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 w.rgb[c] = albedo(K, m, c, x.u, x.v);
-                if (GRAD) gv.rho[c] += a[4 * c] * Ln[4 * c];
+                if (GRAD) {
+                    gv.rho[c] += a[4 * c] * Ln[4 * c];
+                    jw += a[4 * c] * w.rgb[c] * Ln[4 * c];
+                }
             }
+            // the weight is rho cos_i / (pi pdf) with the pdf detached: linear in cos_i
+            if (GRAD && nm) gv.gns = gv.gns + x.wi * (jw / dot(x.ns, x.wi));
             w.A = w.B = w.C = w.D = 0.0f; w.ci = w.co = 1.0f; w.si = w.so = 0.0f;
             break;
         }
@@ -846,14 +1065,16 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
             cf eta = real_ior ? cf{K.p(m.eta_slot, m.eta_off), 0.0f} : ior(K, m);
             GGXv g;
             ggx_eval(K, m, x, x.wi, eta, g);
+            const float ks = EXT ? spec_scale(K, m, x.u, x.v) : 1.0f;
             float s = g.ci / x.pdf;  // f cos / pdf; the selected lobe's weight equals its probability
-            float k = g.kappa * s;
+            float k = g.kappa * s * ks;
             w = g.w;
             w.A = k * g.a; w.B = k * g.b; w.C = k * g.c; w.D = k * g.d;
             if (GRAD) {
                 float gA, gB, gC, gD;
                 w_local_grad(w, a, Ln, gA, gB, gC, gD);
-                ggx_backprop(x, eta, g, s, gA, gB, gC, gD, gv);
+                float jk = ggx_backprop(x, eta, g, s, ks, gA, gB, gC, gD, gv);
+                if (nm && jk != 0.0f) gv.gns = gv.gns + ggx_dln_dns(g, x.wi, x.wo) * jk;
             }
             break;
         }
@@ -863,17 +1084,18 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
             float ecam = x.front ? 1.0f : eta, efar = x.front ? eta : 1.0f;
             float a0, b0, c0, d0, ci;
             cf mm;
-            if (x.lobe == LOBE_REFLECT) {
+            const bool refl = x.lobe == LOBE_REFLECT;
+            const v3 n_inc = refl ? x.ns : -x.ns;
+            if (refl) {
                 ci = dot(x.ns, x.wo);
                 mm = cf{efar / ecam, 0.0f};
                 fresnel_R(ci, mm, a0, b0, c0, d0);
-                spec_frames(-x.wi, x.ns, x.wo, w);
             } else {
                 ci = fabsf(dot(x.wi, x.ns));
                 mm = cf{ecam / efar, 0.0f};
                 fresnel_T(ci, mm, a0, b0, c0, d0);
-                spec_frames(-x.wi, -x.ns, x.wo, w);
             }
+            spec_frames(-x.wi, n_inc, x.wo, w);
             float ip = 1.0f / x.prob;
             w.kind = 2;
             w.rgb[0] = w.rgb[1] = w.rgb[2] = 1.0f;
@@ -881,11 +1103,21 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
             if (GRAD) {
                 float gA, gB, gC, gD;
                 w_local_grad(w, a, Ln, gA, gB, gC, gD);
-                cf gm = (x.lobe == LOBE_REFLECT) ? fresnel_R_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip)
-                                                 : fresnel_T_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip);
+                cf gm = refl ? fresnel_R_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip)
+                             : fresnel_T_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip);
                 // m = eta (camera outside, reflection) or 1/eta, and the reverse for transmission
-                bool m_is_eta = (x.lobe == LOBE_REFLECT) == x.front;
+                bool m_is_eta = refl == x.front;
                 gv.eta += m_is_eta ? gm.re : -gm.re / (eta * eta);
+                if (nm) {
+                    // incidence cosine: wo . ns (reflection) or |wi . ns| (transmission)
+                    float gci = refl ? fresnel_R_dci(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip)
+                                     : fresnel_T_dci(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip);
+                    v3 dci = refl ? x.wo : (dot(x.wi, x.ns) < 0.0f ? -x.wi : x.wi);
+                    float g1, g2, g3, g4;
+                    w_frame_grad(w, a, Ln, g1, g2, g3, g4);
+                    v3 gn = spec_frames_grad(-x.wi, n_inc, x.wo, g1, g2, g3, g4);
+                    gv.gns = gv.gns + dci * gci + (refl ? gn : -gn);
+                }
             }
             break;
         }
@@ -909,12 +1141,24 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
         if (m.alpha_slot >= 0) rough_scatter(K, m, x.u, x.v, gv.alpha);
         if (m.eta_slot >= 0) K.g(m.eta_slot, m.eta_off, gv.eta);
         if (m.kap_slot >= 0) K.g(m.kap_slot, m.kap_off, gv.kap);
+        if (EXT && m.spec_slot >= 0 && gv.ks != 0.0f)
+            tex_scatter<1>(K, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, x.u, x.v, &gv.ks);
         if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
             const DevLight L = gval(W.lights, (size_t)x.light);
             for (int c = 0; c < 3; ++c) K.g(L.le_slot, L.le_off + c, gv.le[c]);
         }
         if (m.emit_slot >= 0)
             for (int c = 0; c < 3; ++c) K.g(m.emit_slot, m.emit_off + c, gv.emit[c]);
+        if (nm) {
+            // ns = il (t T + b B + n N): d/d(t, b, n) = (T, B, N) . il (I - ns ns^T) g
+            v3 tg, bt;
+            float il;
+            mapped_normal(W, K, m, x, tg, bt, il);
+            v3 gr = (gv.gns - x.ns * dot(x.ns, gv.gns)) * il;
+            float gt[3] = {dot(tg, gr), dot(bt, gr), dot(x.ng, gr)};
+            if (gt[0] != 0.0f || gt[1] != 0.0f || gt[2] != 0.0f)
+                tex_scatter<3>(K, m.nrm_slot, m.nrm_off, m.nrm_tw, m.nrm_th, x.u, x.v, gt);
+        }
     }
 }
 
@@ -929,7 +1173,8 @@ DEV void analyzer_apply(int sensor, float theta, int a, const float* v, float* o
     } else if (a == 0) { C = 1.0f; S = 0.0f; q = 0.5f * (v[0] + v[1]); }
     else if (a == 1) { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[2]); }
     else if (a == 2) { C = -1.0f; S = 0.0f; q = 0.5f * (v[0] - v[1]); }
-    else { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[3]); }  // QWP(0) then polarizer at 45 deg
+    else if (sensor == SENSOR_ANALYZER4) { C = 0.0f; S = 1.0f; q = 0.5f * (v[0] + v[3]); }  // QWP(0), polarizer at 45 deg
+    else { C = 0.0f; S = -1.0f; q = 0.5f * (v[0] - v[3]); }  // QWP(0), polarizer at -45 deg: left-circular
     o[0] = q; o[1] = C * q; o[2] = S * q; o[3] = 0.0f;
 }
 // row delta^T A_a
@@ -941,10 +1186,10 @@ DEV void analyzer_row(int sensor, float theta, int a, const float* dl, float* r)
     else if (a == 0) { C = 1.0f; S = 0.0f; }
     else if (a == 1) { C = 0.0f; S = 1.0f; }
     else if (a == 2) { C = -1.0f; S = 0.0f; }
-    else { C = 0.0f; S = 1.0f; kind = 1; }
+    else { C = 0.0f; S = sensor == SENSOR_ANALYZER4 ? 1.0f : -1.0f; kind = 1; }
     float q = 0.5f * (dl[0] + C * dl[1] + S * dl[2]);  // output = w q(v), w = (1, C, S, 0)
     if (kind == 0) { r[0] = q; r[1] = C * q; r[2] = S * q; r[3] = 0.0f; }
-    else { r[0] = q; r[1] = 0.0f; r[2] = 0.0f; r[3] = q; }
+    else { r[0] = q; r[1] = 0.0f; r[2] = 0.0f; r[3] = S * q; }  // circular analyzers: q(v) = (v0 + S v3) / 2
 }
 // delta^T (dP(theta)/dtheta) v
 DEV float polarizer_dtheta(float theta, const float* dl, const float* v) {

@@ -59,10 +59,14 @@ struct BlobMaterial {
     int32_t eta_slot; uint32_t eta_off;
     int32_t kap_slot; uint32_t kap_off;
     int32_t emit_slot; uint32_t emit_off;
-    float axis[3]; float blend; uint32_t reserved[3];
+    float axis[3]; float blend;
+    float emit_circ;
+    int32_t spec_slot; uint32_t spec_off, spec_tw, spec_th;
+    int32_t nrm_slot; uint32_t nrm_off, nrm_tw, nrm_th;
+    uint32_t reserved[4];
 };
-static_assert(sizeof(BlobMaterial) == 88, "material record");
-struct BlobLight { float p0[3], eu[3], ev[3]; int32_t le_slot; uint32_t le_off, pad; };
+static_assert(sizeof(BlobMaterial) == 128, "material record");
+struct BlobLight { float p0[3], eu[3], ev[3]; int32_t le_slot; uint32_t le_off; float circ; };
 static_assert(sizeof(BlobLight) == 48, "light record");
 static_assert(sizeof(ppt_view) == 88, "view record");
 
@@ -177,6 +181,7 @@ struct ppt_scene {
     DevBuf dev_worlds;
     int cu_count = 256;
     int stack_cap = 2;     // traversal stack entries: deepest BVH + 2
+    bool has_ext = false;  // normal maps, specular maps or circularly polarized emitters
     ~ppt_scene() { for (auto* w : worlds) delete w; }
 };
 
@@ -257,6 +262,9 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
         m.emit_slot = b.emit_slot; m.emit_off = (int32_t)b.emit_off;
         for (int k = 0; k < 3; ++k) m.axis[k] = b.axis[k];
         m.blend = b.blend;
+        m.emit_circ = b.emit_circ;
+        m.spec_slot = b.spec_slot; m.spec_off = (int32_t)b.spec_off; m.spec_tw = (int32_t)b.spec_tw; m.spec_th = (int32_t)b.spec_th;
+        m.nrm_slot = b.nrm_slot; m.nrm_off = (int32_t)b.nrm_off; m.nrm_tw = (int32_t)b.nrm_tw; m.nrm_th = (int32_t)b.nrm_th;
         char msg[160];
         std::snprintf(msg, sizeof msg, "world %d material %llu: invalid parameter reference", wi, (unsigned long long)i);
         bool ok = b.type <= MAT_BLEND;
@@ -282,10 +290,24 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
                 ok = alb_ok() && alpha_ok() && slot_ok(sc, b.eta_slot, b.eta_off, 1) && b.blend >= 0.0f && b.blend <= 1.0f;
                 break;
         }
-        if (ok && b.emit_slot >= 0) ok = slot_ok(sc, b.emit_slot, b.emit_off, 3);
+        if (ok && b.emit_slot >= 0) ok = slot_ok(sc, b.emit_slot, b.emit_off, 3) && std::fabs(b.emit_circ) <= 1.0f;
+        // optional maps: specular scale (1 channel) and tangent-space normal (3 channels)
+        auto map_ok = [&](int32_t slot, uint32_t off, uint32_t tw, uint32_t th, int ch) {
+            if (slot < 0) return true;
+            if (tw > 0 && (th == 0 || (uint64_t)tw * th > (1ull << 30))) return false;
+            return slot_ok(sc, slot, off, tw > 0 ? (int64_t)tw * th * ch : ch);
+        };
+        if (ok) ok = map_ok(b.spec_slot, b.spec_off, b.spec_tw, b.spec_th, 1) &&
+                     map_ok(b.nrm_slot, b.nrm_off, b.nrm_tw, b.nrm_th, 3);
+        if (ok && b.spec_slot >= 0 && !(b.type == MAT_GGX_DIELECTRIC || b.type == MAT_GGX_CONDUCTOR || b.type == MAT_BLEND))
+            ok = false;
+        if (ok && b.nrm_slot >= 0 && !(b.type == MAT_LAMBERT || b.type == MAT_DIELECTRIC || b.type == MAT_GGX_DIELECTRIC ||
+                                       b.type == MAT_GGX_CONDUCTOR || b.type == MAT_BLEND))
+            ok = false;
         if (ok && b.type == MAT_EMITTER && b.emit_slot < 0) ok = false;
         if (!ok) return fail(PPT_EINVAL, msg);
         if (b.type != MAT_GGX_CONDUCTOR) m.kap_slot = -1;
+        if (b.nrm_slot >= 0 || b.spec_slot >= 0 || b.emit_circ != 0.0f) sc->has_ext = true;
     }
     // lights
     std::vector<DevLight> lights(nl);
@@ -293,6 +315,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
         BlobLight b;
         std::memcpy(&b, bl + i, sizeof(b));
         if (!slot_ok(sc, b.le_slot, b.le_off, 3)) return fail(PPT_EINVAL, "light radiance reference out of range");
+        if (!(std::fabs(b.circ) <= 1.0f)) return fail(PPT_EINVAL, "light circular polarization outside [-1, 1]");
         DevLight& L = lights[i];
         double eu[3] = {b.eu[0], b.eu[1], b.eu[2]}, ev[3] = {b.ev[0], b.ev[1], b.ev[2]};
         double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2], eu[0] * ev[1] - eu[1] * ev[0]};
@@ -303,6 +326,8 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
         }
         L.area = (float)a;
         L.le_slot = b.le_slot; L.le_off = (int32_t)b.le_off;
+        L.circ = b.circ;
+        if (b.circ != 0.0f) sc->has_ext = true;
     }
     // primitives
     uint64_t np = nt + ns;
@@ -487,7 +512,7 @@ int ppt_scene_create(const void* blob, size_t nbytes, ppt_scene** out) {
     if (nbytes < 16) return fail(PPT_EINVAL, "blob truncated (header)");
     uint32_t hdr[4];
     std::memcpy(hdr, p, 16); p += 16;
-    if (hdr[0] != 0x31545050u || hdr[1] != 1u) return fail(PPT_EINVAL, "bad blob magic or version");
+    if (hdr[0] != 0x31545050u || hdr[1] != 2u) return fail(PPT_EINVAL, "bad blob magic or version");
     if (hdr[2] > (uint32_t)MAX_SLOTS) return fail(PPT_EUNSUPPORTED, "too many parameter slots");
     if (hdr[3] == 0 || hdr[3] > 4096) return fail(PPT_EINVAL, "bad world count");
     if ((size_t)(end - p) < 4ull * hdr[2]) return fail(PPT_EINVAL, "blob truncated (slots)");
@@ -554,7 +579,7 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
                   V.spp >= 1 && V.crop_x0 >= 0 && V.crop_y0 >= 0 && V.crop_w >= 0 && V.crop_h >= 0 &&
                   (int64_t)V.crop_x0 + V.crop_w <= V.width && (int64_t)V.crop_y0 + V.crop_h <= V.height &&
                   (int64_t)V.width * V.height <= (1ll << 31) && V.view_id < (1u << 24) &&
-                  V.sensor >= PPT_SENSOR_NONE && V.sensor <= PPT_SENSOR_ANALYZER4 && V.fov_y_deg > 0.0f &&
+                  V.sensor >= PPT_SENSOR_NONE && V.sensor <= PPT_SENSOR_LIGHTSTAGE4 && V.fov_y_deg > 0.0f &&
                   V.fov_y_deg < 180.0f;
         if (ok && V.sensor == PPT_SENSOR_POLARIZER) ok = slot_ok(sc, V.theta_slot, V.theta_off, 1);
         if (ok && (int64_t)V.crop_w * V.crop_h * V.spp >= (1ll << 31)) {
@@ -588,7 +613,7 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
         D.tan_h = (float)std::tan(0.5 * (double)V.fov_y_deg * M_PI / 180.0);
         D.aspect = (float)((double)V.width / (double)V.height);
         D.sensor = V.sensor; D.theta_slot = V.theta_slot; D.theta_off = V.theta_off;
-        D.n_analyzers = V.sensor == PPT_SENSOR_ANALYZER4 ? 4 : 1;
+        D.n_analyzers = (V.sensor == PPT_SENSOR_ANALYZER4 || V.sensor == PPT_SENSOR_LIGHTSTAGE4) ? 4 : 1;
         D.view_id = V.view_id;
         D.out_off = out_off;
         D.path_off = path_off;
@@ -688,6 +713,7 @@ static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayou
     a.S = path_state(ws, L);
     a.Q = p->Q;
     a.mask = p->mask;
+    a.ext = p->scene->has_ext ? 1 : 0;  // kernels with normal/specular maps and circular emitters
     return a;
 }
 

@@ -35,7 +35,7 @@ constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8, CKPT_F4 = 5;
 
 enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
                          MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };
-enum SensorType : int32_t { SENSOR_NONE = 0, SENSOR_POLARIZER = 1, SENSOR_ANALYZER4 = 2 };
+enum SensorType : int32_t { SENSOR_NONE = 0, SENSOR_POLARIZER = 1, SENSOR_ANALYZER4 = 2, SENSOR_LIGHTSTAGE4 = 3 };
 enum Lobe : int32_t { LOBE_NONE = 0, LOBE_REFLECT = 1, LOBE_TRANSMIT = 2, LOBE_DIFFUSE = 3, LOBE_GLOSSY = 4,
                       LOBE_SHEET = 5, LOBE_INVALID = 6 };
 
@@ -48,12 +48,16 @@ struct DevMaterial {
     int32_t emit_slot, emit_off;
     float axis[3];
     float blend;
+    float emit_circ;                                // emitted Stokes Le (1, 0, 0, emit_circ)
+    int32_t spec_slot, spec_off, spec_tw, spec_th;  // specular map (scale of the GGX lobe); slot -1 = none
+    int32_t nrm_slot, nrm_off, nrm_tw, nrm_th;      // tangent-space normal map (3 channels); slot -1 = none
 };
 
 struct DevLight {
     float p0[3], eu[3], ev[3], n[3];
     float area;
     int32_t le_slot, le_off;
+    float circ;  // emitted Stokes Le (1, 0, 0, circ)
 };
 
 // BVH2 node: both children's boxes in one 64-byte record (Aila & Laine 2009 layout).
@@ -147,6 +151,7 @@ struct WArgs {
     int32_t first;          // first bounce: the queue is the identity over the chunk's slots
     int32_t lds_nd, lds_nf;  // used entries of the workgroup gradient accumulators
     int32_t ckpt;           // hybrid replay checkpoint interval k, 0 = cached suffix replay
+    int32_t ext;            // the scene uses normal maps, specular maps or circular emitters
     float* out;             // render output
     const float* dout;      // backward: dL/dStokes
     double* gacc;           // backward: FP64 gradient accumulators

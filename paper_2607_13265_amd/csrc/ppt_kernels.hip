@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
 }
 
 // ============================================================================ shading
-template <int MODE>
+template <int MODE, bool EXT>
 __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                 surface(W, h, o, d, x);
                 v3 so, sd;
                 float stmax = 0.0f;
-                vertex_setup(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+                vertex_setup<EXT>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
                 if (A.sig) {
                     uint64_t sg = A.sig[g];
                     sig_add(sg, (uint32_t)x.orig);
@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                 WC w;
                 w.kind = 0;
                 float Ee[12], En[12];
-                if (MODE != 2) eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
+                if (MODE != 2) eval_vertex<false, EXT>(W, K, x, w, Ee, En, nullptr, nullptr);
                 cont = x.lobe != LOBE_NONE && x.lobe != LOBE_INVALID;
                 shadow = x.nee == NEE_PENDING;
                 float4* H = shd_rec(S, slot);
@@ -617,6 +617,7 @@ DEV void w_apply_select(const WC& w, int c, const float* in, float* out) {
 // (W_b and E_b); block_fold then folds them back from the suffix L beyond the block's last vertex,
 // leaving in L the suffix at its first vertex (with store_suffix, each record's E words receive
 // the suffix beyond its vertex, which the replay reads).
+template <bool EXT>
 DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWorld& W, int slot, uint32_t pix,
                     uint32_t smp, int s, int e, v3 o, v3 d, bool prev_delta) {
     const PathState& S = A.S;
@@ -631,11 +632,11 @@ DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWo
         surface(W, h, o, d, x);
         v3 so, sd;
         float stmax;
-        vertex_setup(W, K, V, A.seed, pix, smp, v + 1, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+        vertex_setup<EXT>(W, K, V, A.seed, pix, smp, v + 1, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
         if (x.nee == NEE_PENDING) x.nee = (int)((hw >> 26) & 7);
         WC w;
         float Ee[12], En[12];
-        eval_vertex<false>(W, K, x, w, Ee, En, nullptr, nullptr);
+        eval_vertex<false, EXT>(W, K, x, w, Ee, En, nullptr, nullptr);
         float4* C = cache_rec(S, Q, v - s, slot);
         C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
         C[1] = f4(w.B, w.C, w.D, w.ci);
@@ -679,7 +680,7 @@ DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool s
 // (into ro/rd) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
 // contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
 // register until the view changes.
-template <bool HYB>
+template <bool HYB, bool EXT>
 __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
@@ -718,7 +719,7 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
                     const int s0 = j * kc, e0 = min(B, s0 + kc);
                     float4* CK = ckpt_rec(S, Q, j, i);
                     const float4 k0 = CK[0], k1 = CK[1];
-                    block_eval(A, K, Vh, Wh, i, pix, smp, s0, e0, mk(k0.x, k0.y, k0.z), mk(k1.x, k1.y, k1.z),
+                    block_eval<EXT>(A, K, Vh, Wh, i, pix, smp, s0, e0, mk(k0.x, k0.y, k0.z), mk(k1.x, k1.y, k1.z),
                                k0.w != 0.0f);
                     st12(CK + 2, L);
                     block_fold(S, Q, i, e0 - s0, L, false);
@@ -822,7 +823,7 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
 // short and long paths share a wavefront without idling.  At vertex b the lane differentiates
 // E_b + W_b L[b+1] against its adjoint rows, then advances them, a <- a W_b.  Gradients go to
 // workgroup LDS accumulators, flushed at the end.
-template <bool HYB>
+template <bool HYB, bool EXT>
 __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
@@ -873,7 +874,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
                 const int v0 = b - 1;
                 if (v0 % A.ckpt == 0) {  // block start: recompute the block's suffix values
                     const int e0 = min(B, v0 + A.ckpt);
-                    block_eval(A, K, V, W, slot, pix, smp, v0, e0, o, d, prev_delta);
+                    block_eval<EXT>(A, K, V, W, slot, pix, smp, v0, e0, o, d, prev_delta);
                     float Lb[12];
                     ld12(ckpt_rec(S, Q, v0 / A.ckpt, slot) + 2, Lb);
                     block_fold(S, Q, slot, e0 - v0, Lb, true);
@@ -894,7 +895,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             surface(W, h, o, d, x);
             v3 so, sd;
             float stmax;
-            vertex_setup(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+            vertex_setup<EXT>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
             if (x.nee == NEE_PENDING) x.nee = rec_nee;
             float Ln[12];  // L[b+1], stored in this vertex's record by the fold (zero after the last)
             if (b < B) {
@@ -905,7 +906,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             }
             WC w;
             float Ee[12], En[12];
-            eval_vertex<true>(W, K, x, w, Ee, En, av, Ln);
+            eval_vertex<true, EXT>(W, K, x, w, Ee, En, av, Ln);
             if (b >= B || x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) {
                 slot = -1;
             } else {
@@ -1026,9 +1027,15 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         else hipLaunchKernelGGL(k_compact<1>, dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_SHADE, s);
         const int sg = blocks_for(a.n_chunk, G.shade), xg = blocks_for(a.n_chunk, G.extend);
-        if (mode == 0) hipLaunchKernelGGL(k_shade<0>, dim3(sg), dim3(BLOCK), 0, s, a);
-        else if (a.ckpt > 0) hipLaunchKernelGGL(k_shade<2>, dim3(sg), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL(k_shade<1>, dim3(sg), dim3(BLOCK), 0, s, a);
+        if (a.ext) {
+            if (mode == 0) hipLaunchKernelGGL((k_shade<0, true>), dim3(sg), dim3(BLOCK), 0, s, a);
+            else if (a.ckpt > 0) hipLaunchKernelGGL((k_shade<2, true>), dim3(sg), dim3(BLOCK), 0, s, a);
+            else hipLaunchKernelGGL((k_shade<1, true>), dim3(sg), dim3(BLOCK), 0, s, a);
+        } else {
+            if (mode == 0) hipLaunchKernelGGL((k_shade<0, false>), dim3(sg), dim3(BLOCK), 0, s, a);
+            else if (a.ckpt > 0) hipLaunchKernelGGL((k_shade<2, false>), dim3(sg), dim3(BLOCK), 0, s, a);
+            else hipLaunchKernelGGL((k_shade<1, false>), dim3(sg), dim3(BLOCK), 0, s, a);
+        }
         M(KF_SHADOW, s);
         if (mode == 0) hipLaunchKernelGGL(k_shadow<0>, dim3(xg), dim3(BLOCK), lds, s, a);
         else if (a.ckpt > 0) hipLaunchKernelGGL(k_shadow<2>, dim3(xg), dim3(BLOCK), lds, s, a);
@@ -1042,11 +1049,18 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     } else {
         size_t glds = (size_t)a.lds_nd * sizeof(double) + (size_t)a.lds_nf * sizeof(float);
         M(KF_FOLD, s);
-        if (a.ckpt > 0) hipLaunchKernelGGL(k_fold<true>, dim3(gb), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL(k_fold<false>, dim3(gb), dim3(BLOCK), 0, s, a);
+        if (a.ckpt > 0 && a.ext) hipLaunchKernelGGL((k_fold<true, true>), dim3(gb), dim3(BLOCK), 0, s, a);
+        else if (a.ckpt > 0) hipLaunchKernelGGL((k_fold<true, false>), dim3(gb), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_fold<false, false>), dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_REPLAY, s);
-        if (a.ckpt > 0) hipLaunchKernelGGL(k_replay<true>, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
-        else hipLaunchKernelGGL(k_replay<false>, dim3(blocks_for(a.n_chunk, G.adjoint)), dim3(BLOCK), glds, s, a);
+        const int rg = blocks_for(a.n_chunk, G.adjoint);
+        if (a.ext) {
+            if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+            else hipLaunchKernelGGL((k_replay<false, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+        } else {
+            if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, false>), dim3(rg), dim3(BLOCK), glds, s, a);
+            else hipLaunchKernelGGL((k_replay<false, false>), dim3(rg), dim3(BLOCK), glds, s, a);
+        }
     }
     return hipGetLastError();
 }
@@ -1056,9 +1070,9 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     size_t lds = (size_t)stack_cap * BLOCK * sizeof(int);
     hipError_t r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend, BLOCK, lds)) != hipSuccess) return r;
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1>, BLOCK, 0)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1, false>, BLOCK, 0)) != hipSuccess) return r;
     size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay<false>, BLOCK, glds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay<false, false>, BLOCK, glds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_gen, BLOCK, 0)) != hipSuccess) return r;
     G->extend = (e > 0 ? e : 1) * cu;
     G->shade = (sh > 0 ? sh : 1) * cu;

@@ -101,3 +101,42 @@ def test_hybrid_replay_parity_c2_crop(k):
 def test_hybrid_replay_parity_c1_config_loss():
     wl = sg.config1()
     _check(run(wl, d=loss_delta_c1(wl), oracle_mode=oracle.MODE_HYBRID, plan_kw={"checkpoint_interval": 2}))
+
+
+# the light stage: right-circular lights, analyzers at 0, 45, 90 degrees and left-circular,
+# normal maps (blend, smooth dielectric, conductor), specular and roughness maps, depth 6
+LIGHTSTAGE_TEX = ("ground_albedo", "ground_roughness", "ground_specular", "ground_normal", "object_albedo",
+                  "object_roughness", "object_specular", "object_normal", "glass_normal", "metal_normal")
+
+
+def _lightstage_crops():
+    wl = sg.lightstage(res=128, spp=8)
+    wl.views = sg.crop_views(wl.views[[0, 3, 5]], 44, 52, 13, 11)
+    return wl
+
+
+def test_lightstage_crop_parity():
+    wl = _lightstage_crops()
+    res = run(wl, oracle_mode=oracle.MODE_CACHED_PRB, pixel_grad_slots=("ior", "metal_specular", "light_Le"),
+              max_pixels=48)
+    _check(res, gate_groups=LIGHTSTAGE_TEX)
+
+
+def test_lightstage_hybrid_replay_parity():
+    wl = _lightstage_crops()
+    res = run(wl, oracle_mode=oracle.MODE_HYBRID, plan_kw={"checkpoint_interval": 2})
+    _check(res, gate_groups=LIGHTSTAGE_TEX)
+
+
+def test_circular_emitter_analyzers_closed_form():
+    # GPU images of a right/left/partially circular emitter against the closed forms:
+    # left-circular analyzer (s0 - s3)/2, right-circular (s0 + s3)/2, linear ones s0/2
+    import paper_2607_13265_amd as ppt
+    for circ in (1.0, -1.0, 0.5):
+        sc, _ = sg.emitter_wall_scene(le=10.0, circ=circ)
+        for sensor, expect3 in ((sg.SENSOR_LIGHTSTAGE4, 5.0 * (1 - circ)), (sg.SENSOR_ANALYZER4, 5.0 * (1 + circ))):
+            v = np.asarray([sg.make_view(0, 16, 8, 2, (0, 0, 0), (0, 0, -1), (0, 1, 0), 30.0, sensor)], sg.VIEW_DTYPE)
+            plan = ppt.Plan(ppt.Scene(sc.to_blob()), v, 3)
+            img = plan.render([torch.from_numpy(p).cuda() for p in sc.params()], 7).cpu().numpy().reshape(4, -1, 3, 4)
+            assert np.allclose(img[:3, ..., 0], 5.0, rtol=1e-6)
+            assert np.allclose(img[3, ..., 0], expect3, rtol=1e-6, atol=1e-5)
