@@ -333,9 +333,9 @@ __global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
 }
 
 // ============================================================================ hit compaction
-// Splits the rays of this bounce: misses end their path here (signature, and the render's empty
-// radiance for a camera ray that escapes), hits go to the hit queue that the shading kernel reads,
-// so its lanes all hold a vertex.
+// Splits the rays of this bounce: misses end their path here (signature; a camera ray that escapes
+// keeps a vertex count of 0, which the pixel reduction reads as no radiance), hits go to the hit
+// queue that the shading kernel reads, so its lanes all hold a vertex.
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
     PathState& S = A.S;
@@ -354,13 +354,7 @@ __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
             const int info = __float_as_int(R[3].x);
             if (!(info & INFO_DEAD)) {
                 hit = __float_as_int(R[2].y) >= 0;
-                if (!hit) {
-                    if (A.sig) sig_add(A.sig[A.g0 + slot], 0xffffffffu);
-                    if (MODE == 0 && (info & 255) == 0) {
-                        float4* AC = acc_rec(S, slot);
-                        AC[5] = AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
-                    }
-                }
+                if (!hit && A.sig) sig_add(A.sig[A.g0 + slot], 0xffffffffu);
             }
         }
         bq_push(qh, hit, slot);
@@ -547,7 +541,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
             lx = px - V.crop_x0; ly = py - V.crop_y0;
             key = ((int64_t)v << 32) | (int64_t)pix;
-            if (!(info & INFO_DEAD)) {
+            if (!(info & INFO_DEAD) && (info & 255) != 0) {  // a camera ray that escaped has no radiance
                 const float4 r2 = R[2];
                 const float Cs = r2.z, Ss = r2.w;  // sensor rotation of the camera ray
                 float Lo[12];
