@@ -159,7 +159,7 @@ struct WArgs {
     const uint8_t* mask;    // optional per-path mask (global path index)
 };
 
-struct LaunchGrid { int extend, shade, adjoint, other; };  // workgroups per kernel family
+struct LaunchGrid { int extend, shade, adjoint, other, cu; };  // workgroups per kernel family; compute units
 
 constexpr uint32_t FLAG_NO_NEE = 1u;
 

@@ -1002,6 +1002,14 @@ hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t
     return hipGetLastError();
 }
 
+// Workgroups of a grid-filling launch of kernel fn: as many per compute unit as its registers and
+// its LDS (static + lds bytes) allow, and no more than the items need.
+static int resident_grid(const void* fn, size_t lds, int64_t n, const LaunchGrid& G) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    return blocks_for(n, per_cu * G.cu);
+}
+
 // One chunk of paths through every bounce.  mode 0: render, 1: backward.  M is told the family
 // of every kernel before its launch (event timing).
 hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M) {
@@ -1020,6 +1028,7 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         if (mode == 0) hipLaunchKernelGGL(k_compact<0>, dim3(gb), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL(k_compact<1>, dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_SHADE, s);
+        // (a grid sized to each variant's own occupancy measured slower for the render variant)
         const int sg = blocks_for(a.n_chunk, G.shade), xg = blocks_for(a.n_chunk, G.extend);
         if (a.ext) {
             if (mode == 0) hipLaunchKernelGGL((k_shade<0, true>), dim3(sg), dim3(BLOCK), 0, s, a);
@@ -1043,11 +1052,20 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     } else {
         size_t glds = (size_t)a.lds_nd * sizeof(double) + (size_t)a.lds_nf * sizeof(float);
         M(KF_FOLD, s);
-        if (a.ckpt > 0 && a.ext) hipLaunchKernelGGL((k_fold<true, true>), dim3(gb), dim3(BLOCK), 0, s, a);
-        else if (a.ckpt > 0) hipLaunchKernelGGL((k_fold<true, false>), dim3(gb), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_fold<false, false>), dim3(gb), dim3(BLOCK), 0, s, a);
+        // each fold workgroup takes one contiguous slice of the chunk, so the grid is the resident
+        // one (a second, partial round of workgroups would leave most of the GPU idle)
+        const void* fold_fn = a.ckpt > 0 ? (a.ext ? (const void*)k_fold<true, true> : (const void*)k_fold<true, false>)
+                                         : (const void*)k_fold<false, false>;
+        const int fg = resident_grid(fold_fn, 0, a.n_chunk, G);
+        if (a.ckpt > 0 && a.ext) hipLaunchKernelGGL((k_fold<true, true>), dim3(fg), dim3(BLOCK), 0, s, a);
+        else if (a.ckpt > 0) hipLaunchKernelGGL((k_fold<true, false>), dim3(fg), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_fold<false, false>), dim3(fg), dim3(BLOCK), 0, s, a);
         M(KF_REPLAY, s);
-        const int rg = blocks_for(a.n_chunk, G.adjoint);
+        // the persistent replay grid: as many workgroups per compute unit as this call's
+        // accumulator size and the variant's registers allow
+        const void* fn = a.ext ? (a.ckpt > 0 ? (const void*)k_replay<true, true> : (const void*)k_replay<false, true>)
+                               : (a.ckpt > 0 ? (const void*)k_replay<true, false> : (const void*)k_replay<false, false>);
+        const int rg = resident_grid(fn, glds, a.n_chunk, G);
         if (a.ext) {
             if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
             else hipLaunchKernelGGL((k_replay<false, true>), dim3(rg), dim3(BLOCK), glds, s, a);
@@ -1071,6 +1089,7 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     G->extend = (e > 0 ? e : 1) * cu;
     G->shade = (sh > 0 ? sh : 1) * cu;
     G->adjoint = (ad > 0 ? ad : 1) * cu;
+    G->cu = cu;
     G->other = (ot > 0 ? ot : 1) * cu;
     return hipSuccess;
 }
