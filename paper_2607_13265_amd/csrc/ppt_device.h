@@ -505,8 +505,8 @@ DEV void trav_begin(Trav& T, const DevWorld& W, v3 o, v3 d, float tmax) {
 }
 // One round of while-while traversal with speculative leaf postponement (Aila & Laine 2009):
 // the lanes of the wavefront in this call descend, a lane that reaches a leaf parks it and keeps
-// descending until every such lane holds a leaf (or, with refill, until fewer than half of the
-// wavefront's lanes still descend), then the parked leaves are tested.  Returns true
+// descending until every such lane holds a leaf (or, with refill, until fewer than a quarter of
+// the wavefront's lanes still descend), then the parked leaves are tested.  Returns true
 // when the ray is finished: closest hit in T.h (ANY = false), or the first hit (ANY = true).
 template <bool ANY>
 DEV bool trav_round(Trav& T, uint32_t& n_nodes, uint32_t& n_prims, int* stack, bool refill) {
@@ -543,9 +543,10 @@ DEV bool trav_round(Trav& T, uint32_t& n_nodes, uint32_t& n_prims, int* stack, b
             T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
         }
         if (!__any(T.leaf == 0)) break;  // every lane in this loop holds a leaf
-        // while queued rays remain (refill, wave-uniform) and more than half of the wavefront has
-        // left the descent, end the round so that the finished lanes take new rays
-        if (refill && __popcll(__ballot(true)) < WAVE / 2) break;
+        // while queued rays remain (refill, wave-uniform) and fewer than a quarter of the
+        // wavefront's lanes still descend, end the round so that the finished lanes take new rays
+        // (thresholds of 1/8, 1/2 and 3/4, and no early end, measured slower)
+        if (refill && __popcll(__ballot(true)) < WAVE / 4) break;
     }
     while (T.leaf < 0) {
         int enc = ~T.leaf;
