@@ -67,6 +67,12 @@ def _scene_with(mat_kw):
     dict(type=99),                                                       # unknown material type
     dict(type=sg.MAT_SHEET, axis=(0.0, 0.0, 0.0)),                      # degenerate polarizer axis
     dict(type=sg.MAT_EMITTER),                                           # emitter without radiance
+    dict(type=sg.MAT_EMITTER, emit_slot=0, emit_circ=1.5),              # |circular degree| > 1
+    dict(type=sg.MAT_LAMBERT, albedo_slot=0, spec_slot=0),              # specular map on a Lambertian
+    dict(type=sg.MAT_GGX_DIELECTRIC, alpha_slot=0, eta_slot=0, spec_slot=0, spec_tw=2, spec_th=2),  # map past the slot
+    dict(type=sg.MAT_LAMBERT, albedo_slot=0, normal_slot=0, normal_off=1),  # 3 normal components past the end
+    dict(type=sg.MAT_LAMBERT, albedo_slot=0, normal_slot=0, normal_tw=1, normal_th=0),  # texture without height
+    dict(type=sg.MAT_SHEET, axis=(1.0, 0.0, 0.0), normal_slot=0),       # normal map on a polarizer sheet
 ])
 def test_bad_material_references(blob, kw):
     rc, msg = _create(_scene_with(kw))
@@ -91,3 +97,19 @@ def test_non_finite_geometry(blob):
     w.add_tris(np.array([[[0, 0, 0], [1, 0, 0], [0, np.nan, 0]]]), None, m)
     rc, msg = _create(sc.to_blob())
     assert rc == -1 and "finite" in msg
+
+
+def test_light_circular_degree_out_of_range(blob):
+    sc = sg.Scene()
+    s_le = sc.add_slot("le", [1.0, 1.0, 1.0])
+    w = sc.add_world()
+    w.add_light((0, 0, 0), (1, 0, 0), (0, 1, 0), s_le, circ=-1.25)
+    w.materials[-1]["emit_circ"] = 0.0  # only the light record is out of range
+    rc, msg = _create(sc.to_blob())
+    assert rc == -1 and "circular" in msg
+
+
+def test_valid_light_stage_blob_passes_host_validation(blob):
+    # circular lights, the light-stage analyzers' scene with normal and specular maps
+    rc, msg = _create(sg.lightstage(res=16, spp=1).scene.to_blob())
+    assert rc == 0 or (rc == -3 and "device" in msg)
