@@ -13,7 +13,9 @@ constexpr int MAX_DEPTH = 128;
 constexpr int STACK = 64;       // BVH traversal stack entries per lane
 
 // Per-path records in the workspace (one record per slot, 16-byte vectors; a path touches only
-// its own cache lines even when the ray queues have scattered the live slots).
+// its own cache lines even when the ray queues have scattered the live slots).  The shading
+// kernel writes cache and shadow records whole, unused words included: records written in part
+// measured slower even where whole ones move more bytes.
 //   ray record, RAY_F4 = 4 vectors (64 B):
 //     [0] ro.x ro.y ro.z rd.x   [1] rd.y rd.z t u   [2] v prim - -   [3] info pix smp -
 //   shadow record, SHD_F4 = 8 vectors (128 B):

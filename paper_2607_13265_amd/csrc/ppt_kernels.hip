@@ -491,11 +491,13 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
                     C[2] = f4(w.si, w.co, w.so, __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29)));
                     C[3] = f4(sphere ? h.t : h.u, h.v, 0.0f, 0.0f);
                     st12(C + 4, Ee);
+                    C[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // a whole 128-byte record is written
                     if (shadow) st12(H + 2, En);
                 }
-                if (shadow) {
+                if (shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
                     H[1] = f4(sd.x, sd.y, sd.z, 0.0f);
+                    H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 float4* Rw = ray_rec(S, slot);
                 if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi);
