@@ -14,7 +14,8 @@ import torch
 from .core import Plan
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
-CANDIDATES = (1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
+CANDIDATES = (1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25, 1 << 26, 1 << 27)
+MEM_FRACTION = 0.6  # a candidate's render + backward workspaces must fit in this share of free memory
 
 
 def workload_key(blob: bytes, views, max_depth: int, flags: int, device_name: str) -> str:
@@ -60,10 +61,14 @@ def tune(scene, blob: bytes, views, max_depth: int, params, want=None, flags: in
     total = int(np.sum(np.asarray(views["crop_w"], np.int64) * views["crop_h"] * views["spp"]))
     timings = {}
     for q in candidates:
-        if q > 2 * total and timings:
-            break
+        if timings and max(timings) >= total:
+            break  # a previous candidate already held every path in one chunk
         plan = Plan(scene, views, max_depth, flags, chunk_paths=q)
         plan.set_stats(False)
+        free, _ = torch.cuda.mem_get_info(params[0].device)
+        if timings and plan.workspace_bytes(0) + plan.workspace_bytes(1) > MEM_FRACTION * free:
+            del plan
+            break  # larger chunks need more memory still
         d = torch.randn(plan.image_numel, device=params[0].device)
         t0 = time.perf_counter()
         timings[int(q)] = _time_step(plan, params, d, want, reps)
