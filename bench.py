@@ -426,8 +426,9 @@ def main():
     # algorithmic work per step of every family, from the in-kernel counters
     st = {k: st_r[k] + st_b[k] for k in st_r}
     work = {
-        "extend": ("alu", FLOP_NODE * st["nodes"] + FLOP_PRIM * st["prim_tests"]),
-        "shadow": ("alu", FLOP_NODE * st["shadow_nodes"] + FLOP_PRIM * st["shadow_prim_tests"]),
+        # one traversal family: closest-hit rays and, in the same launches, the shadow rays
+        "extend": ("alu", FLOP_NODE * (st["nodes"] + st["shadow_nodes"])
+                   + FLOP_PRIM * (st["prim_tests"] + st["shadow_prim_tests"])),
         "shade": ("alu", FLOP_SHADE * st["vertices"]),
         "replay": ("alu", FLOP_REPLAY * st_b["vertices"]),
         "fold": ("hbm", BYTES_FOLD_VERTEX * st_b["vertices"] + BYTES_FOLD_PATH * st_b["paths"]),

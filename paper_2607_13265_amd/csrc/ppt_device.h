@@ -507,9 +507,8 @@ DEV void trav_begin(Trav& T, const DevWorld& W, v3 o, v3 d, float tmax) {
 // the lanes of the wavefront in this call descend, a lane that reaches a leaf parks it and keeps
 // descending until every such lane holds a leaf (or, with refill, until fewer than a quarter of
 // the wavefront's lanes still descend), then the parked leaves are tested.  Returns true
-// when the ray is finished: closest hit in T.h (ANY = false), or the first hit (ANY = true).
-template <bool ANY>
-DEV bool trav_round(Trav& T, uint32_t& n_nodes, uint32_t& n_prims, int* stack, bool refill) {
+// when the ray is finished: closest hit in T.h (any = false), or the first hit (any = true).
+DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int* stack, bool refill) {
     while (T.ref != TRAV_DONE && T.ref >= 0) {
         ++n_nodes;
         const float4* nd = T.nodes + 4 * T.ref;
@@ -553,7 +552,7 @@ DEV bool trav_round(Trav& T, uint32_t& n_nodes, uint32_t& n_prims, int* stack, b
         int first = enc >> 3, cnt = (enc & 7) + 1;
         for (int k = 0; k < cnt; ++k) {
             ++n_prims;
-            if (hit_prim(T.prims, first + k, T.o, T.d, T.tb, T.h) && ANY) {
+            if (hit_prim(T.prims, first + k, T.o, T.d, T.tb, T.h) && any) {
                 T.leaf = 0;
                 T.ref = TRAV_DONE;
                 return true;

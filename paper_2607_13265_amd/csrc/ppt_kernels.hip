@@ -3,9 +3,11 @@
 // Paths are processed in chunks of a flat index space that spans every view of a plan (the
 // batch): path g = (view, crop pixel, sample), samples fastest.  Per chunk and bounce:
 //   k_extend   closest-hit traversal of the queued rays (lean kernel, LDS traversal stack),
+//              from the second bounce on together with the any-hit traversal of the previous
+//              bounce's next-event rays,
+//   k_compact  misses end their path, hits go to the shading queue,
 //   k_shade    vertex sampling and Mueller weights; appends continuing paths to the next ray
-//              queue and next-event rays to the shadow queue (wave-aggregated atomics),
-//   k_shadow   any-hit traversal of the next-event rays.
+//              queue and next-event rays to the shadow queue (wave-aggregated atomics).
 // Render (Sec. 3.1, Eq. 2): the state carries the prefix Mueller product beta and the radiance
 // sum; k_accum reduces the samples of each pixel.  Backward (Sec. 3.2, 4.3, Fig. 2): the primal
 // pass caches, per vertex, the weight W_b, the emission + next-event Stokes E_b and a hit record;
@@ -229,104 +231,93 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
     flush_stats(A.stats, cnt);
 }
 
-// ============================================================================ traversal kernels
-// Persistent traversal: each lane traces one ray at a time and takes the next queued ray as soon
-// as its own is finished, so rays of very different cost share a wavefront without idling.
-// counts[5] / counts[6] are the fetch counters of k_extend / k_shadow; each kernel clears the
-// other's for its next launch (the chunk start clears both).
+// Closest hits of the rays of one bounce: a persistent kernel in which a lane takes the next queued
+// ray as soon as its own is finished.  SMODE >= 0: the same launch resolves the shadow rays of the
+// previous bounce (positions [0, n_s) of one work list, any hit; SMODE is that bounce's mode: 0
+// render, 1 backward, 2 hybrid replay), so the two kinds of rays share one launch and its tail.
+template <int SMODE>
 __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
     extern __shared__ int lds_stack[];
     int* stack = lds_stack + threadIdx.x;
     PathState& S = A.S;
+    const int Q = A.Q;
     if (blockIdx.x == 0 && threadIdx.x == 0) {  // the queues the following kernels append to
         S.counts[1 - A.qin] = 0;
-        S.counts[2] = 0;
-        S.counts[6] = 0;
         S.counts[7] = 0;
+        if (SMODE < 0) S.counts[2] = 0;  // (a launch with shadow rays reads it: compaction clears it)
     }
     const int* q = A.qin ? S.queue1 : S.queue0;
-    const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    const int ne = A.first ? A.n_chunk : S.counts[A.qin];
+    const int ns = SMODE >= 0 ? S.counts[2] : 0;
+    const int n = ns + ne;
     if (!fetch_active(n)) return;
     Count cnt;
     WaveFetch F(n);
     Trav T;
-    bool alive = false;
-    int slot = -1;
+    bool alive = false, any = false;
+    int slot = -1, info = 0;
     while (true) {
         const int idx = F.take(!alive, n, &S.counts[5]);
         if (idx >= 0) {
-            slot = A.first ? idx : q[idx];
-            const float4* R = ray_rec(S, slot);
-            const int info = __float_as_int(R[3].x);
-            if (!(info & INFO_DEAD)) {
-                v3 o, d;
-                ray_od(R, o, d);
-                trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world), o, d, 3.0e38f);
+            any = idx < ns;
+            if (SMODE >= 0 && any) {
+                slot = S.squeue[idx];
+                info = __float_as_int(ray_rec(S, slot)[3].x);
+                const float4* H = shd_rec(S, slot);
+                const float4 s0 = H[0], s1 = H[1];
+                trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world),
+                           mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
                 alive = true;
-                ++cnt.c[ST_RAYS];
+                ++cnt.c[ST_SHADOW_RAYS];
+            } else {
+                slot = A.first ? idx : q[idx - ns];
+                const float4* R = ray_rec(S, slot);
+                info = __float_as_int(R[3].x);
+                if (!(info & INFO_DEAD)) {
+                    v3 o, d;
+                    ray_od(R, o, d);
+                    trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world), o, d, 3.0e38f);
+                    alive = true;
+                    ++cnt.c[ST_RAYS];
+                }
             }
         }
         if (!__any(alive) && !F.more()) break;
         const bool refill = F.more();
-        if (alive && trav_round<false>(T, cnt.c[ST_NODES], cnt.c[ST_PRIMS], stack, refill)) {
-            float4* R = ray_rec(S, slot);
-            ((float2*)(R + 1))[1] = make_float2(T.h.t, T.h.u);
-            ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
-            alive = false;
+        uint32_t nn = 0, np = 0;
+        const bool done = alive && trav_round(T, SMODE >= 0 && any, nn, np, stack, refill);
+        if (SMODE >= 0 && any) {
+            cnt.c[ST_SHADOW_NODES] += nn; cnt.c[ST_SHADOW_PRIMS] += np;
+        } else {
+            cnt.c[ST_NODES] += nn; cnt.c[ST_PRIMS] += np;
         }
-    }
-    flush_stats(A.stats, cnt);
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(BLOCK) k_shadow(WArgs A) {
-    extern __shared__ int lds_stack[];
-    int* stack = lds_stack + threadIdx.x;
-    PathState& S = A.S;
-    const int Q = A.Q;
-    if (blockIdx.x == 0 && threadIdx.x == 0) S.counts[5] = 0;
-    const int n = S.counts[2];
-    if (!fetch_active(n)) return;
-    Count cnt;
-    WaveFetch F(n);
-    Trav T;
-    bool alive = false;
-    int slot = -1, info = 0;
-    while (true) {
-        const int idx = F.take(!alive, n, &S.counts[6]);
-        if (idx >= 0) {
-            slot = S.squeue[idx];
-            info = __float_as_int(ray_rec(S, slot)[3].x);
-            const float4* H = shd_rec(S, slot);
-            const float4 s0 = H[0], s1 = H[1];
-            trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world), mk(s0.x, s0.y, s0.z),
-                       mk(s1.x, s1.y, s1.z), s0.w);
-            alive = true;
-            ++cnt.c[ST_SHADOW_RAYS];
-        }
-        if (!__any(alive) && !F.more()) break;
-        const bool refill = F.more();
-        if (alive && trav_round<true>(T, cnt.c[ST_SHADOW_NODES], cnt.c[ST_SHADOW_PRIMS], stack, refill)) {
+        if (done) {
             alive = false;
-            const bool occ = T.h.prim >= 0;
-            const float4* H = shd_rec(S, slot);
-            if (MODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
-                float4* dst = MODE == 0 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
-                if (!occ)
+            if (SMODE >= 0 && any) {
+                const bool occ = T.h.prim >= 0;
+                const float4* H = shd_rec(S, slot);
+                if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
+                    float4* dst = SMODE == 0 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+                    if (!occ)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        float4 a = dst[k], p = H[2 + k];
-                        dst[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
-                    }
+                        for (int k = 0; k < 3; ++k) {
+                            float4 a = dst[k], p = H[2 + k];
+                            dst[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
+                        }
+                }
+                if (SMODE != 0) {  // record the visibility in the hit word of the vertex whose light sample this is
+                    float* hwp = SMODE == 1 ? &cache_rec(S, Q, (info & 255) - 1, slot)[2].w
+                                            : &hit_rec(S, Q, (info & 255) - 1, slot)->x;
+                    uint32_t hw = (uint32_t)__float_as_int(*hwp);
+                    hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
+                    *hwp = __int_as_float((int)hw);
+                }
+                if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
+            } else {
+                float4* R = ray_rec(S, slot);
+                ((float2*)(R + 1))[1] = make_float2(T.h.t, T.h.u);
+                ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
             }
-            if (MODE != 0) {  // record the visibility in the hit word of the vertex whose light sample this is
-                float* hwp = MODE == 1 ? &cache_rec(S, Q, (info & 255) - 1, slot)[2].w
-                                       : &hit_rec(S, Q, (info & 255) - 1, slot)->x;
-                uint32_t hw = (uint32_t)__float_as_int(*hwp);
-                hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
-                *hwp = __int_as_float((int)hw);
-            }
-            if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
         }
     }
     flush_stats(A.stats, cnt);
@@ -341,6 +332,10 @@ __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
     PathState& S = A.S;
     const int* qin = A.qin ? S.queue1 : S.queue0;
     const int n = A.first ? A.n_chunk : S.counts[A.qin];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.counts[2] = 0;  // the shadow queue the shading kernel appends to (the traversal read it)
+        S.counts[5] = 0;  // the work counter of the next traversal launch
+    }
     __shared__ BlockQueue qh;
     if (threadIdx.x == 0) qh.n = 0;
     __syncthreads();
@@ -1021,17 +1016,20 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     int gb = blocks_for(a.n_chunk, G.other);
     M(KF_GEN, s);
     hipLaunchKernelGGL(k_gen, dim3(gb), dim3(BLOCK), 0, s, a);
+    const int xg = blocks_for(a.n_chunk, G.extend);
+    a.qin = 0;
+    a.first = 1;
+    M(KF_EXTEND, s);
+    hipLaunchKernelGGL(k_extend<-1>, dim3(xg), dim3(BLOCK), lds, s, a);
     for (int b = 1; b <= a.max_depth; ++b) {
         a.qin = (b - 1) & 1;
         a.first = b == 1;
-        M(KF_EXTEND, s);
-        hipLaunchKernelGGL(k_extend, dim3(blocks_for(a.n_chunk, G.extend)), dim3(BLOCK), lds, s, a);
         M(KF_COMPACT, s);
         if (mode == 0) hipLaunchKernelGGL(k_compact<0>, dim3(gb), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL(k_compact<1>, dim3(gb), dim3(BLOCK), 0, s, a);
         M(KF_SHADE, s);
         // (a grid sized to each variant's own occupancy measured slower for the render variant)
-        const int sg = blocks_for(a.n_chunk, G.shade), xg = blocks_for(a.n_chunk, G.extend);
+        const int sg = blocks_for(a.n_chunk, G.shade);
         if (a.ext) {
             if (mode == 0) hipLaunchKernelGGL((k_shade<0, true>), dim3(sg), dim3(BLOCK), 0, s, a);
             else if (a.ckpt > 0) hipLaunchKernelGGL((k_shade<2, true>), dim3(sg), dim3(BLOCK), 0, s, a);
@@ -1041,10 +1039,16 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
             else if (a.ckpt > 0) hipLaunchKernelGGL((k_shade<2, false>), dim3(sg), dim3(BLOCK), 0, s, a);
             else hipLaunchKernelGGL((k_shade<1, false>), dim3(sg), dim3(BLOCK), 0, s, a);
         }
-        M(KF_SHADOW, s);
-        if (mode == 0) hipLaunchKernelGGL(k_shadow<0>, dim3(xg), dim3(BLOCK), lds, s, a);
-        else if (a.ckpt > 0) hipLaunchKernelGGL(k_shadow<2>, dim3(xg), dim3(BLOCK), lds, s, a);
-        else hipLaunchKernelGGL(k_shadow<1>, dim3(xg), dim3(BLOCK), lds, s, a);
+        // the rays of bounce b + 1 and the shadow rays of bounce b in one traversal launch (a
+        // vertex at the maximum depth starts neither, so nothing follows the last bounce)
+        if (b < a.max_depth) {
+            a.qin = b & 1;
+            a.first = 0;
+            M(KF_EXTEND, s);
+            if (mode == 0) hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, a);
+            else if (a.ckpt > 0) hipLaunchKernelGGL(k_extend<2>, dim3(xg), dim3(BLOCK), lds, s, a);
+            else hipLaunchKernelGGL(k_extend<1>, dim3(xg), dim3(BLOCK), lds, s, a);
+        }
     }
     if (mode == 0) {
         if (a.out) {
@@ -1083,7 +1087,7 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     int e = 0, sh = 0, ad = 0, ot = 0;
     size_t lds = (size_t)stack_cap * BLOCK * sizeof(int);
     hipError_t r;
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend, BLOCK, lds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend<1>, BLOCK, lds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1, false>, BLOCK, 0)) != hipSuccess) return r;
     size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay<false, false>, BLOCK, glds)) != hipSuccess) return r;
