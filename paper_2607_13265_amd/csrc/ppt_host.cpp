@@ -457,7 +457,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
 struct WsLayout {
     size_t table, stats, counts, gacc, total;
     int lds_nd = 0, lds_nf = 0;
-    size_t ray, shd, acc, cache, hits, ckpt, q0, q1, sq, hq;
+    size_t ray, shd, acc, cache, hits, ckpt, q0, q1, sq, hq, hf;
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -477,7 +477,7 @@ static WsLayout ws_layout(const ppt_plan* p, int op) {
     L.cache = take(op == 1 ? records * CACHE_F4 * 16 * Q : 0);
     L.hits = take(hybrid ? (size_t)p->max_depth * 16 * Q : 0);
     L.ckpt = take(hybrid ? (size_t)((p->max_depth + p->ckpt - 1) / p->ckpt) * CKPT_F4 * 16 * Q : 0);
-    L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q); L.hq = take(4 * Q);
+    L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q); L.hq = take(4 * Q); L.hf = take(Q);
     L.gacc_n = 0;
     if (op == 1)
         for (int64_t n : p->scene->slot_numel) L.gacc_n += n;
@@ -495,6 +495,7 @@ static PathState path_state(void* ws, const WsLayout& L) {
     S.hits = (float4*)(w + L.hits);
     S.ckpt = (float4*)(w + L.ckpt);
     S.queue0 = (int*)(w + L.q0); S.queue1 = (int*)(w + L.q1); S.squeue = (int*)(w + L.sq); S.hqueue = (int*)(w + L.hq);
+    S.hflag = (uint8_t*)(w + L.hf);
     S.counts = (int*)(w + L.counts);
     return S;
 }

@@ -131,6 +131,7 @@ struct PathState {
     int* queue1;
     int* squeue;    // shadow-ray queue
     int* hqueue;    // queue of the rays of this bounce that hit a surface (input of the shading kernel)
+    uint8_t* hflag; // [Q] outcome of the slot's last closest-hit ray: 0 miss, 1 hit, 2 no ray (masked path)
     int* counts;    // 8 ints: sizes of queue0, queue1, the shadow queue, the replay queue; fetch counters of
                     // the replay, closest-hit and shadow kernels; size of the hit queue
 };

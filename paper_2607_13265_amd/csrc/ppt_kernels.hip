@@ -223,6 +223,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
         float4* R = ray_rec(S, i);
         ray_set(R, o, d);
         R[2] = f4(0.0f, 0.0f, Cs, Ss);  // the whole record is written
+        S.hflag[i] = live ? 0 : 2;
         R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
                   __uint_as_float(id.smp), 0.0f);
         if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
@@ -317,6 +318,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                 float4* R = ray_rec(S, slot);
                 ((float2*)(R + 1))[1] = make_float2(T.h.t, T.h.u);
                 ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
+                S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
             }
         }
     }
@@ -345,12 +347,9 @@ __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
         int slot = 0;
         if (i < n) {
             slot = A.first ? i : qin[i];
-            const float4* R = ray_rec(S, slot);
-            const int info = __float_as_int(R[3].x);
-            if (!(info & INFO_DEAD)) {
-                hit = __float_as_int(R[2].y) >= 0;
-                if (!hit && A.sig) sig_add(A.sig[A.g0 + slot], 0xffffffffu);
-            }
+            const int f = S.hflag[slot];  // (a byte per ray instead of the hit words of its record)
+            hit = f == 1;
+            if (f == 0 && A.sig) sig_add(A.sig[A.g0 + slot], 0xffffffffu);
         }
         bq_push(qh, hit, slot);
         bq_flush(qh, &S.counts[7], S.hqueue, false);
