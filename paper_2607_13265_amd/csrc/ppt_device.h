@@ -511,8 +511,14 @@ DEV void trav_begin(Trav& T, const DevWorld& W, v3 o, v3 d, float tmax) {
 DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int* stack, bool refill) {
     while (T.ref != TRAV_DONE && T.ref >= 0) {
         ++n_nodes;
+        // the two top stack entries, read while the node is in flight (below the bottom of the
+        // stack entry 0 is read and not used)
+        const int sp = T.sp;
+        const int top1 = stack[max(sp - 1, 0) * BLOCK], top2 = stack[max(sp - 2, 0) * BLOCK];
+        __builtin_amdgcn_sched_barrier(0);
         const float4* nd = T.nodes + 4 * T.ref;
         float4 q0 = ldg4(nd, 0), q1 = ldg4(nd, 1), q2 = ldg4(nd, 2), q3 = ldg4(nd, 3);
+        __builtin_amdgcn_sched_barrier(0);  // (keeps the stack reads ahead of the wait for the node)
         const v3 id = T.id, ood = T.ood;
         float a0 = fmaf(q0.x, id.x, -ood.x), a1 = fmaf(q0.y, id.x, -ood.x);
         float b0 = fmaf(q0.z, id.y, -ood.y), b1 = fmaf(q0.w, id.y, -ood.y);
@@ -524,23 +530,26 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         float g0 = fmaf(q2.z, id.z, -ood.z), g1 = fmaf(q2.w, id.z, -ood.z);
         float tnR = fmaxf(fmaxf(fminf(e0, e1), fminf(f0, f1)), fmaxf(fminf(g0, g1), 0.0f));
         float txR = fminf(fminf(fmaxf(e0, e1), fmaxf(f0, f1)), fminf(fmaxf(g0, g1), T.tb));
-        bool hL = tnL <= txL, hR = tnR <= txR;
-        int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
-        if (hL && hR) {
-            if (tnR < tnL) { int t = rL; rL = rR; rR = t; }
-            stack[(T.sp++) * BLOCK] = rR;
-            T.ref = rL;
-        } else if (hL) {
-            T.ref = rL;
-        } else if (hR) {
-            T.ref = rR;
-        } else {
-            T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
-        }
-        if (T.ref < 0 && T.leaf == 0) {  // park the leaf, keep descending
-            T.leaf = T.ref;
-            T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
-        }
+        const bool hL = tnL <= txL, hR = tnR <= txR;
+        const int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
+        // next reference, by selects: the nearer hit child (the farther one is pushed), else the
+        // top of the stack; a leaf is parked (when none is) and the descent goes on past it.  The
+        // two pops this can need were read above (pushing and at once popping the farther child
+        // of a parked nearer leaf is skipped).
+        const bool goR = hR && (!hL || tnR < tnL);
+        const int near = goR ? rR : rL, far = goR ? rL : rR;
+        const bool both = hL && hR, none = !hL && !hR, free_slot = T.leaf == 0;
+        const int pop1 = sp > 0 ? top1 : TRAV_DONE, pop2 = sp > 1 ? top2 : TRAV_DONE;
+        const bool park_near = !none && near < 0 && free_slot;
+        const bool park_pop = none && pop1 < 0 && free_slot;
+        const bool push = both && !park_near;
+        if (push) stack[sp * BLOCK] = far;
+        int ref = park_near ? (both ? far : pop1) : near;
+        ref = none ? (park_pop ? pop2 : pop1) : ref;
+        T.ref = ref;
+        T.leaf = park_near ? near : (park_pop ? pop1 : T.leaf);
+        const int npop = none ? (park_pop ? 2 : 1) : (park_near && !both ? 1 : 0);
+        T.sp = push ? sp + 1 : max(sp - npop, 0);
         if (!__any(T.leaf == 0)) break;  // every lane in this loop holds a leaf
         // while queued rays remain (refill, wave-uniform) and fewer than a quarter of the
         // wavefront's lanes still descend, end the round so that the finished lanes take new rays
