@@ -436,6 +436,11 @@ DEV float4 ldg4(const float4* p, int i) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The two halves of a word of a BVH node, widened to float.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+DEV float half_lo(float w) { return (float)__builtin_bit_cast(f16x2, w).x; }
+DEV float half_hi(float w) { return (float)__builtin_bit_cast(f16x2, w).y; }
+
 DEV v3 safe_inv(v3 d) {
     const float e = 1e-20f;
     return mk(1.0f / (fabsf(d.x) > e ? d.x : copysignf(e, d.x)), 1.0f / (fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
@@ -516,22 +521,22 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         const int sp = T.sp;
         const int top1 = stack[max(sp - 1, 0) * BLOCK], top2 = stack[max(sp - 2, 0) * BLOCK];
         __builtin_amdgcn_sched_barrier(0);
-        const float4* nd = T.nodes + 4 * T.ref;
-        float4 q0 = ldg4(nd, 0), q1 = ldg4(nd, 1), q2 = ldg4(nd, 2), q3 = ldg4(nd, 3);
+        const float4* nd = T.nodes + 2 * T.ref;
+        const float4 q0 = ldg4(nd, 0), q1 = ldg4(nd, 1);
         __builtin_amdgcn_sched_barrier(0);  // (keeps the stack reads ahead of the wait for the node)
         const v3 id = T.id, ood = T.ood;
-        float a0 = fmaf(q0.x, id.x, -ood.x), a1 = fmaf(q0.y, id.x, -ood.x);
-        float b0 = fmaf(q0.z, id.y, -ood.y), b1 = fmaf(q0.w, id.y, -ood.y);
-        float c0 = fmaf(q2.x, id.z, -ood.z), c1 = fmaf(q2.y, id.z, -ood.z);
+        float a0 = fmaf(half_lo(q0.x), id.x, -ood.x), a1 = fmaf(half_hi(q0.x), id.x, -ood.x);
+        float b0 = fmaf(half_lo(q0.y), id.y, -ood.y), b1 = fmaf(half_hi(q0.y), id.y, -ood.y);
+        float c0 = fmaf(half_lo(q1.x), id.z, -ood.z), c1 = fmaf(half_hi(q1.x), id.z, -ood.z);
         float tnL = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
         float txL = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), T.tb));
-        float e0 = fmaf(q1.x, id.x, -ood.x), e1 = fmaf(q1.y, id.x, -ood.x);
-        float f0 = fmaf(q1.z, id.y, -ood.y), f1 = fmaf(q1.w, id.y, -ood.y);
-        float g0 = fmaf(q2.z, id.z, -ood.z), g1 = fmaf(q2.w, id.z, -ood.z);
+        float e0 = fmaf(half_lo(q0.z), id.x, -ood.x), e1 = fmaf(half_hi(q0.z), id.x, -ood.x);
+        float f0 = fmaf(half_lo(q0.w), id.y, -ood.y), f1 = fmaf(half_hi(q0.w), id.y, -ood.y);
+        float g0 = fmaf(half_lo(q1.y), id.z, -ood.z), g1 = fmaf(half_hi(q1.y), id.z, -ood.z);
         float tnR = fmaxf(fmaxf(fminf(e0, e1), fminf(f0, f1)), fmaxf(fminf(g0, g1), 0.0f));
         float txR = fminf(fminf(fmaxf(e0, e1), fmaxf(f0, f1)), fminf(fmaxf(g0, g1), T.tb));
         const bool hL = tnL <= txL, hR = tnR <= txR;
-        const int rL = __float_as_int(q3.x), rR = __float_as_int(q3.y);
+        const int rL = __float_as_int(q1.z), rR = __float_as_int(q1.w);
         // next reference, by selects: the nearer hit child (the farther one is pushed), else the
         // top of the stack; a leaf is parked (when none is) and the descent goes on past it.  The
         // two pops this can need were read above (pushing and at once popping the farther child

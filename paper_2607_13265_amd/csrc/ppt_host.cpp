@@ -71,6 +71,28 @@ static_assert(sizeof(BlobLight) == 48, "light record");
 static_assert(sizeof(ppt_view) == 88, "view record");
 
 // ============================================================================ BVH (binned SAH)
+// Box bounds as IEEE half floats rounded outward: half_down(x) <= x <= half_up(x).  Beyond the
+// half range the bound becomes infinite (a box unbounded along that axis, still conservative).
+static uint16_t half_bits(_Float16 h) { uint16_t b; std::memcpy(&b, &h, 2); return b; }
+static float half_value(uint16_t b) { _Float16 h; std::memcpy(&h, &b, 2); return (float)h; }
+static uint16_t half_down(float x) {
+    const uint16_t b = half_bits((_Float16)x);  // nearest
+    if (half_value(b) <= x) return b;
+    if (b == 0x0000u) return 0x8001u;           // +0 above a tiny negative x
+    return (b & 0x8000u) ? (uint16_t)(b + 1) : (uint16_t)(b - 1);
+}
+static uint16_t half_up(float x) {
+    const uint16_t b = half_bits((_Float16)x);
+    if (half_value(b) >= x) return b;
+    if (b == 0x8000u) return 0x0001u;           // -0 below a tiny positive x
+    return (b & 0x8000u) ? (uint16_t)(b - 1) : (uint16_t)(b + 1);
+}
+static float half_pair(float lo, float hi) {   // (rounded-down lo, rounded-up hi) in one word
+    const uint32_t w = (uint32_t)half_down(lo) | ((uint32_t)half_up(hi) << 16);
+    float f;
+    std::memcpy(&f, &w, 4);
+    return f;
+}
 struct BPrim { float lo[3], hi[3], c[3]; };
 struct BNode { float lo[3], hi[3]; int left, right, first, count; };
 
@@ -388,21 +410,20 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
         for (const BNode& n : B.nodes)
             if (n.left < 0 && (n.count < 1 || n.count > 8)) ok_leaves = false;
         if (!ok_leaves) return fail(PPT_EDEVICE, "internal error: leaf size");
-        nodes.resize((size_t)std::max(n_inner, 1) * 4);
+        nodes.resize((size_t)std::max(n_inner, 1) * 2);
         std::memset(nodes.data(), 0, nodes.size() * sizeof(float4));
         for (size_t i = 0; i < B.nodes.size(); ++i) {
             const BNode& n = B.nodes[i];
             if (n.left < 0) continue;
             const BNode& L = B.nodes[n.left];
             const BNode& R = B.nodes[n.right];
-            float4* q = &nodes[4 * (size_t)inner_id[i]];
-            q[0] = make_float4(L.lo[0], L.hi[0], L.lo[1], L.hi[1]);
-            q[1] = make_float4(R.lo[0], R.hi[0], R.lo[1], R.hi[1]);
-            q[2] = make_float4(L.lo[2], L.hi[2], R.lo[2], R.hi[2]);
+            float4* q = &nodes[2 * (size_t)inner_id[i]];
             int rl = ref_of(n.left), rr = ref_of(n.right);
             float fl, fr;
             std::memcpy(&fl, &rl, 4); std::memcpy(&fr, &rr, 4);
-            q[3] = make_float4(fl, fr, 0.0f, 0.0f);
+            q[0] = make_float4(half_pair(L.lo[0], L.hi[0]), half_pair(L.lo[1], L.hi[1]),
+                               half_pair(R.lo[0], R.hi[0]), half_pair(R.lo[1], R.hi[1]));
+            q[1] = make_float4(half_pair(L.lo[2], L.hi[2]), half_pair(R.lo[2], R.hi[2]), fl, fr);
         }
         root_ref = ref_of(0);
         prims.resize(np * 3);

@@ -62,9 +62,11 @@ struct DevLight {
     float circ;  // emitted Stokes Le (1, 0, 0, circ)
 };
 
-// BVH2 node: both children's boxes in one 64-byte record (Aila & Laine 2009 layout).
-//   q0 = (L.lo.x, L.hi.x, L.lo.y, L.hi.y), q1 = (R.lo.x, R.hi.x, R.lo.y, R.hi.y),
-//   q2 = (L.lo.z, L.hi.z, R.lo.z, R.hi.z), q3 = (ref L, ref R, -, -) as int bits.
+// BVH2 node: both children's boxes in one 32-byte record (the two-box layout of Aila & Laine 2009
+// with the box bounds as IEEE half floats, lo rounded down and hi rounded up, so that each stored
+// box contains the exact one).  Words, each a pair of halves (first, second) or an int:
+//   q0 = ((L.lo.x, L.hi.x), (L.lo.y, L.hi.y), (R.lo.x, R.hi.x), (R.lo.y, R.hi.y)),
+//   q1 = ((L.lo.z, L.hi.z), (R.lo.z, R.hi.z), ref L, ref R).
 // A reference >= 0 is an inner node; < 0 is a leaf: ~ref = first << 3 | (count - 1).
 // Primitive records (3 x float4, BVH order): triangle (v0, orig), (e1, 0), (e2, 0);
 // sphere (c, orig), (r, 1, 0, 0), unused.
