@@ -451,9 +451,9 @@ DEV v3 safe_inv(v3 d) {
 // then shrinks to t.
 DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
     const float4* pr = prims + 3 * i;
-    float4 A = ldg4(pr, 0), B = ldg4(pr, 1);
-    if (__float_as_int(B.w) == 0) {
-        float4 C = ldg4(pr, 2);
+    // the kind is read from the third word, so all three are loaded at once (one round trip)
+    const float4 A = ldg4(pr, 0), B = ldg4(pr, 1), C = ldg4(pr, 2);
+    if (__float_as_int(C.w) == 0) {
         v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
         v3 p = cross(d, e2);
         float det = dot(e1, p);

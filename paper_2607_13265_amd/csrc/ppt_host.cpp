@@ -449,7 +449,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
                 std::memcpy(&fone, &one, 4);
                 prims[3 * k] = make_float4(s[0], s[1], s[2], forig);
                 prims[3 * k + 1] = make_float4(s[3], 0.0f, 0.0f, fone);
-                prims[3 * k + 2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                prims[3 * k + 2] = make_float4(0.0f, 0.0f, 0.0f, fone);
             }
         }
     }

@@ -69,7 +69,7 @@ struct DevLight {
 //   q1 = ((L.lo.z, L.hi.z), (R.lo.z, R.hi.z), ref L, ref R).
 // A reference >= 0 is an inner node; < 0 is a leaf: ~ref = first << 3 | (count - 1).
 // Primitive records (3 x float4, BVH order): triangle (v0, orig), (e1, 0), (e2, 0);
-// sphere (c, orig), (r, 1, 0, 0), unused.
+// sphere (c, orig), (r, 0, 0, 1), (0, 0, 0, 1); the last words as int bits (1: a sphere).
 struct DevWorld {
     const float4* nodes;
     const float4* prims;
