@@ -736,6 +736,10 @@ static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayou
     a.Q = p->Q;
     a.mask = p->mask;
     a.ext = p->scene->has_ext ? 1 : 0;  // kernels with normal/specular maps and circular emitters
+    if (p->scene->worlds.size() == 1) {
+        a.one_world = 1;
+        a.world0 = p->scene->worlds[0]->dev;
+    }
     return a;
 }
 

@@ -162,6 +162,8 @@ struct WArgs {
     double* gacc;           // backward: FP64 gradient accumulators
     uint64_t* sig;          // optional per-path signatures (global path index)
     const uint8_t* mask;    // optional per-path mask (global path index)
+    int32_t one_world;      // the scene has one world, world0 (read from the arguments, not per lane)
+    DevWorld world0;
 };
 
 struct LaunchGrid { int extend, shade, adjoint, other, cu; };  // workgroups per kernel family; compute units

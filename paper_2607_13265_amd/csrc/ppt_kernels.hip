@@ -198,6 +198,14 @@ DEV void ray_set(float4* R, v3 o, v3 d) {
 constexpr int INFO_DEAD = 1 << 9;
 DEV int info_make(int nverts, bool prev_delta, int view) { return nverts | (prev_delta ? 256 : 0) | (view << 12); }
 
+// World of a view: in a scene of one world it comes from the launch arguments (wave-uniform
+// scalar loads), otherwise from the world table through the view.
+DEV DevWorld world_of(const WArgs& A, int view) {
+    if (A.one_world) return A.world0;
+    return gval(A.worlds, (size_t)gval(A.views, (size_t)view).world);
+}
+DEV DevWorld world_of(const WArgs& A, const DevView& V) { return A.one_world ? A.world0 : gval(A.worlds, (size_t)V.world); }
+
 // ============================================================================ chunk start
 __global__ void k_reset_counts(int* counts) {
     if (threadIdx.x < 8) counts[threadIdx.x] = 0;
@@ -266,7 +274,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                 info = __float_as_int(ray_rec(S, slot)[3].x);
                 const float4* H = shd_rec(S, slot);
                 const float4 s0 = H[0], s1 = H[1];
-                trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world),
+                trav_begin(T, world_of(A, info >> 12),
                            mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
                 alive = true;
                 ++cnt.c[ST_SHADOW_RAYS];
@@ -277,7 +285,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                 if (!(info & INFO_DEAD)) {
                     v3 o, d;
                     ray_od(R, o, d);
-                    trav_begin(T, gval(A.worlds, (size_t)gval(A.views, (size_t)(info >> 12)).world), o, d, 3.0e38f);
+                    trav_begin(T, world_of(A, info >> 12), o, d, 3.0e38f);
                     alive = true;
                     ++cnt.c[ST_RAYS];
                 }
@@ -386,7 +394,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
             int64_t g = A.g0 + slot;
             const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
             const DevView V = gval(A.views, (size_t)v);
-            const DevWorld W = gval(A.worlds, (size_t)V.world);
+            const DevWorld W = world_of(A, V);
             const float4 r0 = R[0], r1 = R[1], r2 = R[2];
             Hit h;
             h.prim = __float_as_int(r2.y);
@@ -703,7 +711,7 @@ __global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
                 // blocks from the last to the first: re-evaluate from the block's checkpoint ray,
                 // store the suffix beyond the block, fold back to the block's first vertex
                 const DevView Vh = gval(A.views, (size_t)v);
-                const DevWorld Wh = gval(A.worlds, (size_t)Vh.world);
+                const DevWorld Wh = world_of(A, Vh);
                 const int kc = A.ckpt;
                 for (int j = (B + kc - 1) / kc - 1; j >= 0; --j) {
                     const int s0 = j * kc, e0 = min(B, s0 + kc);
@@ -856,7 +864,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
         if (!__any(slot >= 0)) break;
         if (slot >= 0) {
             const DevView V = gval(A.views, (size_t)v);
-            const DevWorld W = gval(A.worlds, (size_t)V.world);
+            const DevWorld W = world_of(A, V);
             uint32_t hw;
             float hu, hv;
             const float4* C;  // the record whose E words hold the suffix beyond this vertex
