@@ -281,14 +281,14 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
             } else {
                 slot = A.first ? idx : q[idx - ns];
                 const float4* R = ray_rec(S, slot);
+                // the ray and its info word in one round trip (a dead ray's record is set up
+                // and not traversed)
+                v3 o, d;
+                ray_od(R, o, d);
                 info = __float_as_int(R[3].x);
-                if (!(info & INFO_DEAD)) {
-                    v3 o, d;
-                    ray_od(R, o, d);
-                    trav_begin(T, world_of(A, info >> 12), o, d, 3.0e38f);
-                    alive = true;
-                    ++cnt.c[ST_RAYS];
-                }
+                trav_begin(T, world_of(A, info >> 12), o, d, 3.0e38f);
+                alive = !(info & INFO_DEAD);
+                if (alive) ++cnt.c[ST_RAYS];
             }
         }
         if (!__any(alive) && !F.more()) break;
