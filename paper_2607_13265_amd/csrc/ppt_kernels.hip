@@ -367,7 +367,8 @@ __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
 
 // ============================================================================ shading
 template <int MODE, bool EXT>
-__global__ void __launch_bounds__(BLOCK) k_shade(WArgs A) {
+// (four waves per SIMD where the registers then fit without spills)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE == 1 && EXT ? 1 : 4, 8))) k_shade(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
     Call K{A.table, nullptr};
@@ -679,7 +680,8 @@ DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool s
 // contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
 // register until the view changes.
 template <bool HYB, bool EXT>
-__global__ void __launch_bounds__(BLOCK) k_fold(WArgs A) {
+// (six waves per SIMD for the cached fold: its registers then fit without spills, measured faster)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 6, 8))) k_fold(WArgs A) {
     PathState& S = A.S;
     const int Q = A.Q;
     Call K{A.table, A.gacc};
