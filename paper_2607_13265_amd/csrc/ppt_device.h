@@ -555,11 +555,12 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         T.leaf = park_near ? near : (park_pop ? pop1 : T.leaf);
         const int npop = none ? (park_pop ? 2 : 1) : (park_near && !both ? 1 : 0);
         T.sp = push ? sp + 1 : max(sp - npop, 0);
-        if (!__any(T.leaf == 0)) break;  // every lane in this loop holds a leaf
-        // while queued rays remain (refill, wave-uniform) and fewer than a quarter of the
-        // wavefront's lanes still descend, end the round so that the finished lanes take new rays
-        // (thresholds of 1/8, 1/2 and 3/4, and no early end, measured slower)
-        if (refill && __popcll(__ballot(true)) < WAVE / 4) break;
+        // the round ends when every lane in this loop holds a leaf, or, while queued rays remain
+        // (refill, wave-uniform), when fewer than a quarter of the wavefront's lanes still descend,
+        // so that the finished lanes take new rays (thresholds of 1/8, 1/2 and 3/4, and no early
+        // end, measured slower); one wave-uniform test
+        const unsigned long long looping = __ballot(true), unparked = __ballot(T.leaf == 0);
+        if (unparked == 0ull || (refill && (int)__builtin_popcountll(looping) < WAVE / 4)) break;
     }
     while (T.leaf < 0) {
         int enc = ~T.leaf;
