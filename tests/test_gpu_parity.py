@@ -140,3 +140,38 @@ def test_circular_emitter_analyzers_closed_form():
             img = plan.render([torch.from_numpy(p).cuda() for p in sc.params()], 7).cpu().numpy().reshape(4, -1, 3, 4)
             assert np.allclose(img[:3, ..., 0], 5.0, rtol=1e-6)
             assert np.allclose(img[3, ..., 0], expect3, rtol=1e-6, atol=1e-5)
+
+
+def _far_scene(offset, scale):
+    """A Lambertian icosphere (1280 triangles), a dielectric sphere, a ground quad and a light, moved
+    to offset + scale * p.  The BVH's half-float box bounds are rounded outward: far from the
+    origin they widen (by ~2 units at 3e3) or, beyond the half range (6.55e4), become infinite;
+    either way no hit may be lost."""
+    off = np.asarray(offset, np.float64)
+    sc = sg.Scene()
+    s_alb = sc.add_slot("albedo", [0.6, 0.5, 0.4])
+    s_ior = sc.add_slot("ior", [1.5])
+    s_le = sc.add_slot("light_Le", [10.0, 10.0, 10.0])
+    w = sc.add_world()
+    m_lam = w.add_material(type=sg.MAT_LAMBERT, albedo_slot=s_alb)
+    m_die = w.add_material(type=sg.MAT_DIELECTRIC, eta_slot=s_ior)
+    P = lambda p: off + scale * np.asarray(p, np.float64)
+    w.add_quad(P((-10, -1.5, -10)), scale * np.array([0, 0, 20.0]), scale * np.array([20.0, 0, 0]), m_lam)
+    w.add_tris(P(0.8 * sg.icosphere(3) + np.array([-0.6, -0.4, 0.0])), None, m_lam)
+    w.add_sphere(P((0.9, -0.8, 0.5)), 0.5 * scale, m_die)
+    w.add_light(P((-1, 3, -1)), scale * np.array([2.0, 0, 0]), scale * np.array([0, 0, 2.0]), s_le)
+    views = np.asarray([sg.make_view(0, 32, 32, 4, P((0, 1, 6)), P((0, -0.5, 0)), (0, 1, 0), 40.0,
+                                     sg.SENSOR_NONE)], sg.VIEW_DTYPE)
+    return sg.Workload("far", sc, views, max_depth=3, seed=5)
+
+
+@pytest.mark.parametrize("offset,scale", [((0, 0, 0), 1.0), ((3000, 0, 0), 30.0),
+                                          ((1.2e5, -5.0e4, 8.0e4), 1000.0)])
+def test_far_geometry_no_lost_hits(offset, scale):
+    # same paths as the oracle (float64 boxes, its traversal pinned to brute force) wherever the
+    # scene sits; the scale keeps the float32 precision of the geometry relative to its size as at
+    # the origin
+    res = run(_far_scene(offset, scale), with_grads=False)
+    print(describe(res))
+    assert res["divergent"] <= 0.01 * res["n_paths"]
+    assert res["img_rel"] <= IMG_TOL
