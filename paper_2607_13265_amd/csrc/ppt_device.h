@@ -614,12 +614,13 @@ DEV bool is_delta(int t) { return t == MAT_DIELECTRIC || t == MAT_SHEET; }
 // Surface data of a hit (identical whether the hit comes from traversal or from a record).
 DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
     const float4* pr = W.prims + 3 * h.prim;
-    float4 A = ldg4(pr, 0), B = ldg4(pr, 1);
+    // the kind is in the third word and the material in the second: one round trip for the record
+    const float4 A = ldg4(pr, 0), B = ldg4(pr, 1), C = ldg4(pr, 2);
     x.orig = __float_as_int(A.w);
     x.prim = h.prim;
-    x.tri = __float_as_int(B.w) == 0;
+    x.mat = __float_as_int(B.w);
+    x.tri = __float_as_int(C.w) == 0;
     if (x.tri) {
-        float4 C = ldg4(pr, 2);
         v3 e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
         x.p = mk(A.x, A.y, A.z) + e1 * h.u + e2 * h.v;
         x.ng = normalize(cross(e1, e2));
@@ -634,7 +635,6 @@ DEV void surface(const DevWorld& W, const Hit& h, v3 o, v3 d, Vtx& x) {
         x.u = 0.5f + atan2f(nout.z, nout.x) * (0.5f / PI_F);
         x.v = acosf(fminf(fmaxf(nout.y, -1.0f), 1.0f)) * (1.0f / PI_F);
     }
-    x.mat = gval(W.prim_mat, (size_t)x.orig);
 }
 
 // Tangent frame of a triangle hit at its outward geometric normal ng: the tangent follows
@@ -716,7 +716,7 @@ constexpr int NEE_NONE = 0, NEE_VISIBLE = 1, NEE_OCCLUDED = 2, NEE_ZERO = 3, NEE
 // EXT: the extended material features (normal maps, specular maps, circularly polarized
 // emitters) are compiled in; kernels of scenes without them skip that code.
 template <bool EXT>
-DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64_t seed, uint32_t pix, uint32_t smp,
+DEV void vertex_setup(const DevWorld& W, const Call& K, uint32_t view_id, uint64_t seed, uint32_t pix, uint32_t smp,
                       int b, int max_depth, uint32_t flags, bool prev_delta, v3 d, Vtx& x, v3& so, v3& sd,
                       float& stmax) {
     const DevMaterial m = gval(W.mats, (size_t)x.mat);
@@ -742,8 +742,8 @@ DEV void vertex_setup(const DevWorld& W, const Call& K, const DevView& V, uint64
         return;
     }
     float ua[4], ub[4];
-    uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 0, ua);
-    uniforms(seed, pix, smp, V.view_id, (uint32_t)b, 1, ub);
+    uniforms(seed, pix, smp, view_id, (uint32_t)b, 0, ua);
+    uniforms(seed, pix, smp, view_id, (uint32_t)b, 1, ub);
     if (!is_delta(m.type) && !(flags & FLAG_NO_NEE) && W.n_lights > 0) {
         int nl = W.n_lights;
         int li = min((int)(ua[3] * (float)nl), nl - 1);

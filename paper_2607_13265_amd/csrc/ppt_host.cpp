@@ -191,7 +191,7 @@ struct Builder {
 
 // ============================================================================ scene / plan objects
 struct WorldHost {
-    DevBuf nodes, prims, prim_mat, tri_uv, mats, lights;
+    DevBuf nodes, prims, tri_uv, mats, lights;
     DevWorld dev;
     int bvh_depth = 0;
 };
@@ -429,9 +429,10 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
         prims.resize(np * 3);
         for (uint64_t k = 0; k < np; ++k) {
             int i = B.idx[k];
-            float forig;
+            float forig, fmat;
             int32_t orig = i;
             std::memcpy(&forig, &orig, 4);
+            std::memcpy(&fmat, &pmat[i], 4);
             if ((uint64_t)i < nt) {
                 const float* v = tv + 9 * (size_t)i;
                 float e1[3], e2[3];
@@ -440,7 +441,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
                     e2[a] = (float)((double)v[6 + a] - (double)v[a]);
                 }
                 prims[3 * k] = make_float4(v[0], v[1], v[2], forig);
-                prims[3 * k + 1] = make_float4(e1[0], e1[1], e1[2], 0.0f);
+                prims[3 * k + 1] = make_float4(e1[0], e1[1], e1[2], fmat);
                 prims[3 * k + 2] = make_float4(e2[0], e2[1], e2[2], 0.0f);
             } else {
                 const float* s = sp + 4 * ((size_t)i - nt);
@@ -448,7 +449,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
                 float fone;
                 std::memcpy(&fone, &one, 4);
                 prims[3 * k] = make_float4(s[0], s[1], s[2], forig);
-                prims[3 * k + 1] = make_float4(s[3], 0.0f, 0.0f, fone);
+                prims[3 * k + 1] = make_float4(s[3], 0.0f, 0.0f, fmat);
                 prims[3 * k + 2] = make_float4(0.0f, 0.0f, 0.0f, fone);
             }
         }
@@ -456,13 +457,11 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
     int rc;
     if ((rc = wh.nodes.upload(nodes.data(), nodes.size() * sizeof(float4), "bvh nodes"))) return rc;
     if ((rc = wh.prims.upload(prims.data(), prims.size() * sizeof(float4), "primitives"))) return rc;
-    if ((rc = wh.prim_mat.upload(pmat.data(), pmat.size() * 4, "primitive materials"))) return rc;
     if ((rc = wh.tri_uv.upload(tuv, nt * 24, "uv"))) return rc;
     if ((rc = wh.mats.upload(mats.data(), mats.size() * sizeof(DevMaterial), "materials"))) return rc;
     if ((rc = wh.lights.upload(lights.data(), lights.size() * sizeof(DevLight), "lights"))) return rc;
     wh.dev.nodes = (const float4*)wh.nodes.p;
     wh.dev.prims = (const float4*)wh.prims.p;
-    wh.dev.prim_mat = (const int32_t*)wh.prim_mat.p;
     wh.dev.tri_uv = (const float*)wh.tri_uv.p;
     wh.dev.mats = (const DevMaterial*)wh.mats.p;
     wh.dev.lights = (const DevLight*)wh.lights.p;

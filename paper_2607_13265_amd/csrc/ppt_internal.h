@@ -17,7 +17,8 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 // kernel writes cache and shadow records whole, unused words included: records written in part
 // measured slower even where whole ones move more bytes.
 //   ray record, RAY_F4 = 4 vectors (64 B):
-//     [0] ro.x ro.y ro.z rd.x   [1] rd.y rd.z t u   [2] v prim - -   [3] info pix smp -
+//     [0] ro.x ro.y ro.z rd.x   [1] rd.y rd.z t u   [2] v prim Cs Ss   [3] info pix smp view-id
+//     (Cs, Ss: sensor rotation of the camera ray; view-id: the view's sampling identity)
 //   shadow record, SHD_F4 = 8 vectors (128 B):
 //     [0] so.x so.y so.z tmax   [1] sd.x sd.y sd.z -   [2..4] 12 Stokes words: the pending next-event
 //     contribution (forward passes), then the adjoint rows of the replay (backward)
@@ -68,12 +69,12 @@ struct DevLight {
 //   q0 = ((L.lo.x, L.hi.x), (L.lo.y, L.hi.y), (R.lo.x, R.hi.x), (R.lo.y, R.hi.y)),
 //   q1 = ((L.lo.z, L.hi.z), (R.lo.z, R.hi.z), ref L, ref R).
 // A reference >= 0 is an inner node; < 0 is a leaf: ~ref = first << 3 | (count - 1).
-// Primitive records (3 x float4, BVH order): triangle (v0, orig), (e1, 0), (e2, 0);
-// sphere (c, orig), (r, 0, 0, 1), (0, 0, 0, 1); the last words as int bits (1: a sphere).
+// Primitive records (3 x float4, BVH order): triangle (v0, orig), (e1, mat), (e2, 0);
+// sphere (c, orig), (r, 0, 0, mat), (0, 0, 0, 1); orig (original primitive id), mat (material) and
+// the last word (0: a triangle, 1: a sphere) as int bits.
 struct DevWorld {
     const float4* nodes;
     const float4* prims;
-    const int32_t* prim_mat;     // by original primitive id
     const float* tri_uv;         // 6 per original triangle
     const DevMaterial* mats;
     const DevLight* lights;

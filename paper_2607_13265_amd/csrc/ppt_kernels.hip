@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
         R[2] = f4(0.0f, 0.0f, Cs, Ss);  // the whole record is written
         S.hflag[i] = live ? 0 : 2;
         R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
-                  __uint_as_float(id.smp), 0.0f);
+                  __uint_as_float(id.smp), __uint_as_float(V.view_id));  // (the view's sampling identity)
         if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
         if (live) ++cnt.c[ST_PATHS];
     }
@@ -387,16 +387,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
         int slot = 0;
         if (i < n) slot = S.hqueue[i];
         const float4* R = ray_rec(S, slot);
-        const float4 r3 = i < n ? R[3] : f4(__int_as_float(INFO_DEAD), 0.0f, 0.0f, 0.0f);
-        const int info = __float_as_int(r3.x);
-        if (!(info & INFO_DEAD)) {
+        if (i < n) {  // a queued ray is a live path's hit (a dead slot's outcome is never a hit)
+            const float4 r3 = R[3], r0 = R[0], r1 = R[1], r2 = R[2];  // one round trip
+            const int info = __float_as_int(r3.x);
             int nb = info & 255, v = info >> 12;
             bool prev_delta = (info >> 8) & 1;
             int64_t g = A.g0 + slot;
             const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
-            const DevView V = gval(A.views, (size_t)v);
-            const DevWorld W = world_of(A, V);
-            const float4 r0 = R[0], r1 = R[1], r2 = R[2];
+            const DevWorld W = world_of(A, v);
             Hit h;
             h.prim = __float_as_int(r2.y);
             h.t = r1.z; h.u = r1.w; h.v = r2.x;
@@ -408,7 +406,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 surface(W, h, o, d, x);
                 v3 so, sd;
                 float stmax = 0.0f;
-                vertex_setup<EXT>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+                vertex_setup<EXT>(W, K, __float_as_uint(r3.w), A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x,
+                                  so, sd, stmax);
                 if (A.sig) {
                     uint64_t sg = A.sig[g];
                     sig_add(sg, (uint32_t)x.orig);
@@ -425,7 +424,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 float4* H = shd_rec(S, slot);
                 if (MODE == 2) {
                     // hybrid replay: the hit record, and at a block start the ray into this vertex
-                    bool sphere = __float_as_int(ldg4(W.prims, 3 * h.prim + 1).w) != 0;
+                    const bool sphere = !x.tri;
                     *hit_rec(S, A.Q, b - 1, slot) = f4(__int_as_float(h.prim | (x.nee << 26)), sphere ? h.t : h.u, h.v, 0.0f);
                     if ((b - 1) % A.ckpt == 0) {
                         float4* CK = ckpt_rec(S, A.Q, (b - 1) / A.ckpt, slot);
@@ -488,7 +487,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     }
                 } else {  // MODE 1
                     float4* C = cache_rec(S, A.Q, b - 1, slot);
-                    bool sphere = __float_as_int(ldg4(W.prims, 3 * h.prim + 1).w) != 0;
+                    const bool sphere = !x.tri;
                     C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
                     C[1] = f4(w.B, w.C, w.D, w.ci);
                     C[2] = f4(w.si, w.co, w.so, __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29)));
@@ -631,7 +630,7 @@ DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWo
         surface(W, h, o, d, x);
         v3 so, sd;
         float stmax;
-        vertex_setup<EXT>(W, K, V, A.seed, pix, smp, v + 1, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+        vertex_setup<EXT>(W, K, V.view_id, A.seed, pix, smp, v + 1, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
         if (x.nee == NEE_PENDING) x.nee = (int)((hw >> 26) & 7);
         WC w;
         float Ee[12], En[12];
@@ -895,7 +894,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             surface(W, h, o, d, x);
             v3 so, sd;
             float stmax;
-            vertex_setup<EXT>(W, K, V, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+            vertex_setup<EXT>(W, K, V.view_id, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
             if (x.nee == NEE_PENDING) x.nee = rec_nee;
             float Ln[12];  // L[b+1], stored in this vertex's record by the fold (zero after the last)
             if (b < B) {
