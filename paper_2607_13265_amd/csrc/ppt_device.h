@@ -455,18 +455,18 @@ DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
     const float4 A = ldg4(pr, 0), B = ldg4(pr, 1), C = ldg4(pr, 2);
     if (__float_as_int(C.w) == 0) {
         v3 v0 = mk(A.x, A.y, A.z), e1 = mk(B.x, B.y, B.z), e2 = mk(C.x, C.y, C.z);
+        // every quantity is computed and one predicate decides (the same tests as early
+        // rejections, without their branches)
         v3 p = cross(d, e2);
         float det = dot(e1, p);
-        if (det == 0.0f) return false;
         float inv = 1.0f / det;
         v3 s = o - v0;
         float uu = dot(s, p) * inv;
-        if (uu < 0.0f || uu > 1.0f) return false;
         v3 q = cross(s, e1);
         float vv = dot(d, q) * inv;
-        if (vv < 0.0f || uu + vv > 1.0f) return false;
         float t = dot(e2, q) * inv;
-        if (!(t > 0.0f && t < tb)) return false;
+        const bool ok = det != 0.0f && !(uu < 0.0f || uu > 1.0f) && !(vv < 0.0f || uu + vv > 1.0f) && t > 0.0f && t < tb;
+        if (!ok) return false;
         tb = t; h.prim = i; h.t = t; h.u = uu; h.v = vv;
         return true;
     }

@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                 if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
             } else {
                 float4* R = ray_rec(S, slot);
-                ((float2*)(R + 1))[1] = make_float2(T.h.t, T.h.u);
+                ((float2*)(R + 1))[1] = make_float2(T.tb, T.h.u);  // (a hit's distance is the final tb)
                 ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
                 S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
             }
