@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_device.h",
                   "paper_2607_13265_amd/csrc/ppt_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_{}.md")
-KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "shadow": "ppt::k_shadow", "compact": "ppt::k_compact",
+KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "compact": "ppt::k_compact",
                  "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}
 
 

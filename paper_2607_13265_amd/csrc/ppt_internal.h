@@ -135,8 +135,9 @@ struct PathState {
     int* squeue;    // shadow-ray queue
     int* hqueue;    // queue of the rays of this bounce that hit a surface (input of the shading kernel)
     uint8_t* hflag; // [Q] outcome of the slot's last closest-hit ray: 0 miss, 1 hit, 2 no ray (masked path)
-    int* counts;    // 8 ints: sizes of queue0, queue1, the shadow queue, the replay queue; fetch counters of
-                    // the replay, closest-hit and shadow kernels; size of the hit queue
+    int* counts;    // 8 ints: [0], [1] sizes of queue0, queue1; [2] size of the shadow queue; [3] size of
+                    // the replay queue; [4], [5] work counters of the replay and traversal kernels; [6]
+                    // unused; [7] size of the hit queue
 };
 
 struct WArgs {
