@@ -38,7 +38,9 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 64 lanes
 PEAK_HBM_GBS = 8000.0
 # files whose content decides whether stored hardware counters still describe the kernels
 KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_device.h",
-                  "paper_2607_13265_amd/csrc/ppt_internal.h", "paper_2607_13265_amd/build.py")  # (build flags too)
+                  "paper_2607_13265_amd/csrc/ppt_internal.h", "paper_2607_13265_amd/csrc/ppt_host.cpp",
+                  "paper_2607_13265_amd/csrc/ppt_half.h",  # (the host builds the BVH the kernels traverse)
+                  "paper_2607_13265_amd/build.py")  # (and the compiler flags)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_{}.md")
 KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "compact": "ppt::k_compact",
                  "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}

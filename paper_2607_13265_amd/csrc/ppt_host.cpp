@@ -2,6 +2,7 @@
 // construction (flattened to the two-box node layout the traversal kernel reads), plan
 // creation (views and chunking of the path index space), workspace layout and the launch sequence.
 #include "ppt_internal.h"
+#include "ppt_half.h"
 #include "../../include/ppt.h"
 
 #include <hip/hip_runtime.h>
@@ -71,22 +72,7 @@ static_assert(sizeof(BlobLight) == 48, "light record");
 static_assert(sizeof(ppt_view) == 88, "view record");
 
 // ============================================================================ BVH (binned SAH)
-// Box bounds as IEEE half floats rounded outward: half_down(x) <= x <= half_up(x).  Beyond the
-// half range the bound becomes infinite (a box unbounded along that axis, still conservative).
-static uint16_t half_bits(_Float16 h) { uint16_t b; std::memcpy(&b, &h, 2); return b; }
-static float half_value(uint16_t b) { _Float16 h; std::memcpy(&h, &b, 2); return (float)h; }
-static uint16_t half_down(float x) {
-    const uint16_t b = half_bits((_Float16)x);  // nearest
-    if (half_value(b) <= x) return b;
-    if (b == 0x0000u) return 0x8001u;           // +0 above a tiny negative x
-    return (b & 0x8000u) ? (uint16_t)(b + 1) : (uint16_t)(b - 1);
-}
-static uint16_t half_up(float x) {
-    const uint16_t b = half_bits((_Float16)x);
-    if (half_value(b) >= x) return b;
-    if (b == 0x8000u) return 0x0001u;           // -0 below a tiny positive x
-    return (b & 0x8000u) ? (uint16_t)(b - 1) : (uint16_t)(b + 1);
-}
+// Box bounds as IEEE half floats rounded outward (ppt_half.h).
 static float half_pair(float lo, float hi) {   // (rounded-down lo, rounded-up hi) in one word
     const uint32_t w = (uint32_t)half_down(lo) | ((uint32_t)half_up(hi) << 16);
     float f;
