@@ -5,9 +5,11 @@
 //   k_extend   closest-hit traversal of the queued rays (lean kernel, LDS traversal stack),
 //              from the second bounce on together with the any-hit traversal of the previous
 //              bounce's next-event rays,
-//   k_compact  misses end their path, hits go to the shading queue,
+//   k_compact  from the one-byte outcome that traversal leaves per slot: misses end their path,
+//              hits go to the shading queue,
 //   k_shade    vertex sampling and Mueller weights; appends continuing paths to the next ray
-//              queue and next-event rays to the shadow queue (wave-aggregated atomics).
+//              queue and next-event rays to the shadow queue (workgroup-staged queues, one
+//              global atomic per flush).
 // Render (Sec. 3.1, Eq. 2): the state carries the prefix Mueller product beta and the radiance
 // sum; k_accum reduces the samples of each pixel.  Backward (Sec. 3.2, 4.3, Fig. 2): the primal
 // pass caches, per vertex, the weight W_b, the emission + next-event Stokes E_b and a hit record;
@@ -334,9 +336,10 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
 }
 
 // ============================================================================ hit compaction
-// Splits the rays of this bounce: misses end their path here (signature; a camera ray that escapes
-// keeps a vertex count of 0, which the pixel reduction reads as no radiance), hits go to the hit
-// queue that the shading kernel reads, so its lanes all hold a vertex.
+// Splits the rays of this bounce by the outcome byte traversal wrote for each slot: misses end their
+// path here (signature; a camera ray that escapes keeps a vertex count of 0, which the pixel
+// reduction reads as no radiance), hits go, in queue order, to the hit queue that the shading kernel
+// reads, so its lanes all hold a vertex.
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_compact(WArgs A) {
     PathState& S = A.S;
