@@ -161,6 +161,23 @@ int ppt_render(const ppt_plan* plan, const float* const* params, int32_t n_param
 int ppt_backward(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
                  const float* d_stokes, float* const* grads, void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of ppt_backward, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  It returns the
+ * same gradients as ppt_backward (same arguments, minus the workspace) and allocates nothing
+ * (no hipMalloc, hipFree or allocating library call): the per-path records of one chunk and the
+ * FP64 gradient accumulators live in a fixed device array of PPT_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held until the process ends; the first call on a device looks up that
+ * device's array.  Paths run in chunks of at most the plan's chunk size, cut down to what the array
+ * holds (results do not depend on the chunking; a deep path needs 128 bytes per vertex of max_depth).
+ * Every call on one GPU uses the same array, which keeps the previous call's contents (each call
+ * clears what it needs): calls that overlap on one GPU, from other streams or threads, race and must
+ * be serialized by the caller.  Work counters are not collected and per-kernel timing is not
+ * recorded.  Errors: as ppt_backward; PPT_EUNSUPPORTED when the gradient accumulators (8 bytes per
+ * parameter element) and the records of one 64-path chunk do not fit in the array. */
+#define PPT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ppt_backward_noalloc(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
+                         const float* d_stokes, float* const* grads, void* stream);
+
 /* Per-path 64-bit signatures (FNV-1a over primitive id, light-sample state and lobe of every
  * vertex) used to detect paths whose discrete decisions differ from another implementation.
  * sig_out: device, num_paths uint64.  ws as for ppt_render. */

@@ -30,6 +30,7 @@ SIGNATURES = {
     "ppt_plan_kernel_times": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "ppt_render": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),
     "ppt_backward": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _vp, _sz, _vp]),
+    "ppt_backward_noalloc": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _vp]),
     "ppt_signatures": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),
     "ppt_read_stats": (_i32, [_vp, _vp, _vp]),
     "ppt_debug_rng": (_i32, [_u64, _vp, _vp, _i64, _vp]),

@@ -173,6 +173,20 @@ class Plan:
                                  ctypes.c_void_p(d_stokes.data_ptr()), gt, wp, wn, _stream(stream)))
         return grads
 
+    def backward_noalloc(self, params, seed: int, d_stokes, grads, stream=None):
+        """ppt_backward_noalloc: the gradients of backward() computed in the library's fixed device
+        scratch (no workspace); ``grads`` are caller-provided tensors (None entries skipped)."""
+        params = self._params(params)
+        if d_stokes.dtype != torch.float32 or d_stokes.numel() != self.image_numel or not d_stokes.is_contiguous():
+            raise PPTError("d_stokes must be contiguous float32 with image_numel entries")
+        if len(grads) != len(params) or any(g is not None and (g.dtype != torch.float32 or not g.is_cuda or
+                                                                g.numel() != p.numel() or not g.is_contiguous())
+                                            for g, p in zip(grads, params)):
+            raise PPTError("grads must match the parameter tensors (float32, contiguous, same sizes)")
+        check(lib().ppt_backward_noalloc(self._h, ptr_table(params), len(params), int(seed) & (2**64 - 1),
+                                         ctypes.c_void_p(d_stokes.data_ptr()), ptr_table(grads), _stream(stream)))
+        return grads
+
     def signatures(self, params, seed: int, ws=None, stream=None):
         params = self._params(params)
         sig = torch.empty(self.num_paths, dtype=torch.int64, device=params[0].device)

@@ -22,6 +22,7 @@ hipError_t launch_finalize(const CallTable* tab, const double* gacc, int n_slots
 hipError_t launch_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M);
 hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G);
+hipError_t noalloc_scratch(void** ptr);
 }  // namespace ppt
 
 using namespace ppt;
@@ -467,9 +468,10 @@ struct WsLayout {
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-static WsLayout ws_layout(const ppt_plan* p, int op) {
+// Q: path-state slots of one chunk (the plan's chunk size, or less for the fixed scratch)
+static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     WsLayout L{};
-    const size_t Q = (size_t)p->Q;
+    const size_t Q = (size_t)Qslots;
     size_t at = 0;
     auto take = [&](size_t bytes) { size_t r = at; at = align256(at + bytes); return r; };
     L.table = take(sizeof(CallTable));
@@ -657,7 +659,7 @@ int64_t ppt_plan_image_numel(const ppt_plan* p) { return p ? p->image_numel : -1
 int64_t ppt_plan_num_paths(const ppt_plan* p) { return p ? p->num_paths : -1; }
 size_t ppt_plan_workspace_bytes(const ppt_plan* p, int32_t op) {
     if (!p || op < 0 || op > 1) return 0;
-    return ws_layout(p, op).total;
+    return ws_layout(p, op, p->Q).total;
 }
 int ppt_plan_set_stats(ppt_plan* p, int32_t enabled) {
     if (!p) return fail(PPT_EINVAL, "null plan");
@@ -705,7 +707,7 @@ static int fill_table(const ppt_plan* p, const float* const* params, int32_t n_p
     return PPT_OK;
 }
 
-static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayout& L) {
+static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayout& L, int32_t Q) {
     WArgs a{};
     char* w = (char*)ws;
     a.worlds = (const DevWorld*)p->scene->dev_worlds.p;
@@ -718,7 +720,7 @@ static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayou
     a.table = (CallTable*)(w + L.table);
     a.stats = p->stats ? (Stats*)(w + L.stats) : nullptr;
     a.S = path_state(ws, L);
-    a.Q = p->Q;
+    a.Q = Q;
     a.mask = p->mask;
     a.ext = p->scene->has_ext ? 1 : 0;  // kernels with normal/specular maps and circular emitters
     if (p->scene->worlds.size() == 1) {
@@ -730,7 +732,7 @@ static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayou
 
 static int check_ws(const ppt_plan* p, void* ws, size_t ws_bytes, int op, WsLayout& L) {
     if (!p) return fail(PPT_EINVAL, "null plan");
-    L = ws_layout(p, op);
+    L = ws_layout(p, op, p->Q);
     if (!ws || ws_bytes < L.total) return fail(PPT_EINVAL, "workspace too small");
     if (((uintptr_t)ws & 255) != 0) return fail(PPT_EINVAL, "workspace must be 256-byte aligned");
     return PPT_OK;
@@ -740,11 +742,12 @@ static LaunchMarker marker(const ppt_plan* p, int op) {
     return p->timing ? LaunchMarker{&KTimer::mark_fn, &p->timer[op]} : LaunchMarker{nullptr, nullptr};
 }
 
-static int run_chunks(const ppt_plan* p, WArgs a, int mode, hipStream_t s) {
-    const LaunchMarker M = marker(p, mode);
-    for (int c = 0; c < p->n_chunks; ++c) {
-        a.g0 = (int64_t)c * p->Q;
-        a.n_chunk = (int32_t)std::min<int64_t>(p->Q, p->num_paths - a.g0);
+// every chunk of a.Q paths (the plan's chunk size unless the caller's memory holds less)
+static int run_chunks(const ppt_plan* p, WArgs a, int mode, hipStream_t s, const LaunchMarker& M) {
+    const int64_t n_chunks = std::max<int64_t>(1, (p->num_paths + a.Q - 1) / a.Q);
+    for (int64_t c = 0; c < n_chunks; ++c) {
+        a.g0 = c * a.Q;
+        a.n_chunk = (int32_t)std::min<int64_t>(a.Q, p->num_paths - a.g0);
         if (a.n_chunk <= 0) break;
         HIP_TRY(launch_chunk(a, mode, p->grid, s, M), mode == 0 ? "render launch" : "backward launch");
     }
@@ -760,7 +763,7 @@ static int render_impl(const ppt_plan* p, const float* const* params, int32_t n_
     CallTable t;
     if ((rc = fill_table(p, params, n_params, nullptr, L, t, nullptr))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    WArgs a = make_args(p, seed, ws, L);
+    WArgs a = make_args(p, seed, ws, L, p->Q);
     a.out = out;
     a.sig = sig;
     const LaunchMarker M = marker(p, 0);
@@ -768,7 +771,7 @@ static int render_impl(const ppt_plan* p, const float* const* params, int32_t n_
     M(KF_OTHER, s);
     HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), p->stats, s), "setup launch");
     if (out) HIP_TRY(launch_fill_f32(out, p->image_numel, s), "clear launch");
-    if ((rc = run_chunks(p, a, 0, s))) return rc;
+    if ((rc = run_chunks(p, a, 0, s, M))) return rc;
     M(-1, s);
     return PPT_OK;
 }
@@ -785,33 +788,67 @@ int ppt_signatures(const ppt_plan* p, const float* const* params, int32_t n_para
     return render_impl(p, params, n_params, seed, nullptr, sig, ws, ws_bytes, stream);
 }
 
-int ppt_backward(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed,
-                 const float* d_stokes, float* const* grads, void* ws, size_t ws_bytes, void* stream) {
-    WsLayout L;
-    int rc = check_ws(p, ws, ws_bytes, 1, L);
-    if (rc) return rc;
+// The backward pass over workspace ws laid out by L for chunks of Q paths; M times the launches.
+static int backward_impl(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed,
+                         const float* d_stokes, float* const* grads, void* ws, WsLayout& L, int32_t Q, bool stats,
+                         int op_timer, void* stream) {
     if (!d_stokes) return fail(PPT_EINVAL, "null d_stokes");
     if (!grads) return fail(PPT_EINVAL, "null gradient table");
     CallTable t;
     int64_t mx = 1;
+    int rc;
     if ((rc = fill_table(p, params, n_params, grads, L, t, &mx))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    WArgs a = make_args(p, seed, ws, L);
+    WArgs a = make_args(p, seed, ws, L, Q);
+    if (!stats) a.stats = nullptr;
     a.dout = d_stokes;
     a.gacc = (double*)((char*)ws + L.gacc);
     a.lds_nd = L.lds_nd;
     a.lds_nf = L.lds_nf;
     a.ckpt = p->ckpt;
-    const LaunchMarker M = marker(p, 1);
-    if (p->timing) p->timer[1].begin();
+    const LaunchMarker M = op_timer >= 0 ? marker(p, op_timer) : LaunchMarker{nullptr, nullptr};
+    if (op_timer >= 0 && p->timing) p->timer[op_timer].begin();
     M(KF_OTHER, s);
-    HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), p->stats, s), "setup launch");
+    HIP_TRY(launch_setup(t, a.table, (Stats*)((char*)ws + L.stats), stats, s), "setup launch");
     HIP_TRY(launch_fill_f64(a.gacc, L.gacc_n, s), "clear launch");
-    if ((rc = run_chunks(p, a, 1, s))) return rc;
+    if ((rc = run_chunks(p, a, 1, s, M))) return rc;
     M(KF_OTHER, s);
     HIP_TRY(launch_finalize(a.table, a.gacc, n_params, mx, s), "finalize launch");
     M(-1, s);
     return PPT_OK;
+}
+
+int ppt_backward(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed,
+                 const float* d_stokes, float* const* grads, void* ws, size_t ws_bytes, void* stream) {
+    WsLayout L;
+    int rc = check_ws(p, ws, ws_bytes, 1, L);
+    if (rc) return rc;
+    return backward_impl(p, params, n_params, seed, d_stokes, grads, ws, L, p->Q, p->stats, 1, stream);
+}
+
+int ppt_backward_noalloc(const ppt_plan* p, const float* const* params, int32_t n_params, uint64_t seed,
+                         const float* d_stokes, float* const* grads, void* stream) {
+    if (!p) return fail(PPT_EINVAL, "null plan");
+    // the largest chunk (a multiple of the wavefront size, at most the plan's) whose records and
+    // the gradient accumulators fit in the fixed scratch
+    const size_t cap = NOALLOC_SCRATCH_BYTES;
+    if (ws_layout(p, 1, WAVE).total > cap) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "the fixed scratch (%zu bytes) cannot hold the gradient accumulators and one %d-path chunk "
+                      "at depth %d (%zu bytes needed)", cap, WAVE, p->max_depth, ws_layout(p, 1, WAVE).total);
+        return fail(PPT_EUNSUPPORTED, msg);
+    }
+    int64_t lo = 1, hi = std::max<int64_t>(1, p->Q / WAVE);  // in wavefronts
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (ws_layout(p, 1, (int32_t)(mid * WAVE)).total <= cap) lo = mid; else hi = mid - 1;
+    }
+    const int32_t Q = (int32_t)(lo * WAVE);
+    void* ws = nullptr;
+    HIP_TRY(noalloc_scratch(&ws), "scratch address lookup");
+    WsLayout L = ws_layout(p, 1, Q);
+    return backward_impl(p, params, n_params, seed, d_stokes, grads, ws, L, Q, false, -1, stream);
 }
 
 int ppt_plan_set_timing(ppt_plan* p, int32_t enabled) {

@@ -172,4 +172,7 @@ struct LaunchGrid { int extend, shade, adjoint, other, cu; };  // workgroups per
 
 constexpr uint32_t FLAG_NO_NEE = 1u;
 
+// Size of the fixed device scratch of the allocation-free backward entry point (per GPU).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+
 }  // namespace ppt

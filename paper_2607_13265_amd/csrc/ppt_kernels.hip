@@ -18,6 +18,8 @@
 // vertex against the cached L[b+1].  No Mueller matrix is inverted.
 #include "ppt_device.h"
 
+#include <mutex>
+
 namespace ppt {
 
 // ============================================================================ wave helpers
@@ -976,6 +978,34 @@ __global__ void k_rng(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t
     uint32_t c0 = ctr[4 * i], c1 = ctr[4 * i + 1], c2 = ctr[4 * i + 2], c3 = ctr[4 * i + 3];
     philox(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     out[4 * i] = c0; out[4 * i + 1] = c1; out[4 * i + 2] = c2; out[4 * i + 3] = c3;
+}
+
+// ============================================================================ fixed scratch
+// Device memory of the allocation-free backward entry point: the per-path records of one chunk and
+// the FP64 gradient accumulators live here instead of in a caller workspace.  Each GPU the library
+// runs on holds its own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device array: its device address is looked up once per device
+// (hipGetSymbolAddress with that device current) and only that address is used afterwards.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** ptr) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255) != 0) return hipErrorInvalidValue;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 // ============================================================================ launchers
