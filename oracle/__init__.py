@@ -60,6 +60,12 @@ def lib():
         L.ppto_rotator.argtypes = [vp, vp, vp, vp]
         L.ppto_canon_x.argtypes = [vp, vp]
         L.ppto_ggx_eval.argtypes = [vp, vp, vp, c_dbl, c_dbl, c_dbl, vp]
+        L.ppto_ggx_D.restype = c_dbl
+        L.ppto_ggx_D.argtypes = [c_dbl, c_dbl]
+        L.ppto_smith_G1.restype = c_dbl
+        L.ppto_smith_G1.argtypes = [c_dbl, c_dbl]
+        L.ppto_sample_glossy.restype = c_int
+        L.ppto_sample_glossy.argtypes = [vp, vp, c_dbl, c_dbl, c_dbl, vp, vp]
         L.ppto_trace.restype = c_int
         L.ppto_trace.argtypes = [vp, c_int, vp, vp, c_dbl, c_int, c_int, vp]
         _lib = L
@@ -203,6 +209,26 @@ def ggx_eval(ns, wi, wo, alpha, m):
     a = [np.ascontiguousarray(v, np.float64) for v in (ns, wi, wo)]
     lib().ppto_ggx_eval(_ptr(a[0]), _ptr(a[1]), _ptr(a[2]), float(alpha), m.real, m.imag, _ptr(f))
     return f.reshape(4, 4)
+
+
+def ggx_D(cos_h, alpha):
+    return float(lib().ppto_ggx_D(float(cos_h), float(alpha)))
+
+
+def smith_G1(cos_w, alpha):
+    return float(lib().ppto_smith_G1(float(cos_w), float(alpha)))
+
+
+LOBE_GLOSSY, LOBE_INVALID = 4, 6
+
+
+def sample_glossy(ns, wo, alpha, u1, u2):
+    """One GGX half-vector sample: (lobe, wi, pdf); lobe is LOBE_INVALID for a rejected sample."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (ns, wo)]
+    wi = np.zeros(3)
+    pdf = np.zeros(1)
+    lobe = lib().ppto_sample_glossy(_ptr(a[0]), _ptr(a[1]), float(alpha), float(u1), float(u2), _ptr(wi), _ptr(pdf))
+    return int(lobe), wi, float(pdf[0])
 
 
 def trace(scene: OracleScene, o, d, tmax=1e30, any_hit=False, brute=False, world=0):

@@ -1476,6 +1476,19 @@ void ppto_ggx_eval(const double* ns, const double* wi, const double* wo, double 
                                  alpha, Cx<double>{m_re, m_im});
     for (int i = 0; i < 16; ++i) f16[i] = f.m[i / 4][i % 4];
 }
+// The microfacet distribution D(cos_h), the Smith masking term G1(cos_w) and one Walter et al.
+// half-vector sample (returns the lobe; wi and pdf are written for a valid sample).
+double ppto_ggx_D(double cos_h, double alpha) { return ggx_D<double>(cos_h, alpha); }
+double ppto_smith_G1(double cos_w, double alpha) { return smith_G1<double>(cos_w, alpha); }
+int ppto_sample_glossy(const double* ns, const double* wo, double alpha, double u1, double u2, double* wi,
+                       double* pdf) {
+    V3 w{0.0, 0.0, 0.0};
+    double p = 0.0;
+    int lobe = sample_glossy(V3{ns[0], ns[1], ns[2]}, V3{wo[0], wo[1], wo[2]}, alpha, u1, u2, w, p);
+    wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
+    *pdf = p;
+    return lobe;
+}
 int ppto_trace(void* scene, int world, const double* o, const double* d, double tmax, int any_hit, int brute,
                double* t_out) {
     Scene* sc = (Scene*)scene;
