@@ -9,6 +9,7 @@ Modes of :func:`OracleScene.run` (paper Sec. 3.2, 4.1, 4.3, 5.1):
   1 conventional AD   one stored tape per path with detached sampling ("Conv. AD")
   2 cached replay     per-vertex cache + backward fold + local-AD replay (Sec. 4.3)
   3 basic P-PRB       suffix recovered by Mueller inversion (Alg. 2), negative control
+  4 hybrid replay     checkpoints every k vertices and Eq. 3's rule in between (Sec. 4.4)
 """
 from __future__ import annotations
 
@@ -51,7 +52,7 @@ def lib():
         L.ppto_scene_counts.argtypes = [vp, c_int, vp]
         L.ppto_run.restype = c_int
         L.ppto_run.argtypes = [vp, vp, vp, c_int, vp, c_int, c_int, ctypes.c_uint32, c_u64, c_int,
-                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp, c_int]
+                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp, c_int, c_dbl, c_dbl]
         L.ppto_philox.argtypes = [c_u64, vp, vp]
         L.ppto_philox_n.argtypes = [c_u64, vp, vp, ctypes.c_int64]
         L.ppto_fresnel.argtypes = [c_dbl, c_dbl, c_dbl, vp, vp]
@@ -110,14 +111,19 @@ class OracleScene:
 
     def run(self, params, views, max_depth, seed, flags=0, mode=MODE_RENDER, d_image=None, params_val=None,
             grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0, pixel_grad_slot=None,
-            ckpt=1):
+            ckpt=1, hybrid_gamma=0.0, hybrid_eps=float("inf")):
         """Run the oracle.  ``params`` (and ``params_val``) are per-slot arrays (converted to float64).
 
         Returns a dict with ``image`` (float64, [V][A][h][w][3][4] flattened per view),
+        ``hybrid_branches`` (mode 4: how many suffixes each branch of Eq. 3 recovered),
         ``grads`` (list per slot, None where not requested), ``sig`` (uint64 per path),
         ``n_vertices`` and ``n_paths``; with ``pixel_grad_slot`` also ``pixel_grad``: that slot's
-        gradient split by pixel (the gradient image of Sec. 5.1), one value per (view, crop pixel).
-        ``ckpt``: checkpoint interval k of the hybrid replay (``MODE_HYBRID``).
+        gradient split by pixel (the gradient images of Sec. 5.1), shape (pixels, slot elements) with
+        the pixels in (view, crop row, crop column) order.
+        ``ckpt``: checkpoint interval k of the hybrid replay (``MODE_HYBRID``); ``hybrid_gamma`` and
+        ``hybrid_eps``: the thresholds of its decision rule (Eq. 3): the scalar PRB update where the
+        block throughput's depolarization index is below gamma, the inverse where |det| > eps
+        beta_00^4, else recomputation (gamma = 0 and eps = inf: recomputation only).
         """
         from scenegen import VIEW_DTYPE, image_numel  # input-layout helpers only
 
@@ -136,9 +142,9 @@ class OracleScene:
             assert d_image.size == n_img
         sig = np.zeros(n_paths, np.uint64) if want_sig else None
         mk = None if mask is None else np.ascontiguousarray(mask, np.uint8)
-        stats = np.zeros(2, np.int64)
+        stats = np.zeros(5, np.int64)
         n_pix = int(np.sum(views["crop_w"].astype(np.int64) * views["crop_h"]))
-        pg = np.zeros(n_pix) if pixel_grad_slot is not None else None
+        pg = np.zeros(n_pix * self.slot_numel[pixel_grad_slot]) if pixel_grad_slot is not None else None
         err = ctypes.create_string_buffer(256)
         ptp, ptv, pgr = _ptr_array(pp), _ptr_array(pv), _ptr_array(grads)
         rc = lib().ppto_run(self.h, ptp, ptv, len(pp), _ptr(views), len(views), int(max_depth), int(flags),
@@ -148,11 +154,12 @@ class OracleScene:
                             None if sig is None else _ptr(sig), None if mk is None else _ptr(mk),
                             _ptr(stats), int(nthreads), err, 256,
                             -1 if pixel_grad_slot is None else int(pixel_grad_slot), None if pg is None else _ptr(pg),
-                            int(ckpt))
+                            int(ckpt), float(hybrid_gamma), float(hybrid_eps))
         if rc != 0:
             raise ValueError("oracle run failed: " + err.value.decode())
         return {"image": image, "grads": grads, "sig": sig, "n_vertices": int(stats[0]), "n_paths": int(stats[1]),
-                "pixel_grad": pg}
+                "hybrid_branches": {"scalar": int(stats[2]), "invert": int(stats[3]), "recompute": int(stats[4])},
+                "pixel_grad": None if pg is None else pg.reshape(n_pix, -1)}
 
 
 # ---- unit-level helpers for the pin tests

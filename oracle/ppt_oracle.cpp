@@ -23,11 +23,16 @@
 //       mode 3  basic polarized PRB (Sec. 4.1, Alg. 2): the suffix is recovered by inverting
 //               the sampled Mueller weight; kept only as the negative control the paper
 //               describes for rank-deficient operators;
-//       mode 4  hybrid cached replay (Sec. 4.4) with checkpoint interval k: only the suffix
-//               values at vertices 0, k, 2k, ... are kept; any other one is recovered by
-//               recomputing the vertices up to the next checkpoint and folding back from it
-//               (the recomputation branch of Eq. 3, which is exact; the scalar-PRB and
-//               inversion branches need thresholds the text does not give).
+//       mode 4  hybrid cached replay (Sec. 4.4, Eq. 3) with checkpoint interval k: only the
+//               suffix values at vertices 0, k, 2k, ... are kept.  Inside a block the replay
+//               tracks the detached block throughput beta (the product of the weights since the
+//               block's checkpoint) and the radiance the block has not yet emitted; any other
+//               suffix is recovered by Eq. 3's rule: the scalar PRB update when the
+//               depolarization index DI(beta) is below gamma, the inverse of beta applied to the
+//               remaining radiance when |det beta| > eps beta_00^4, else recomputation of the
+//               vertices up to the next checkpoint and a fold back from it (the rest of that
+//               block then reads the recomputed values).  gamma = 0 and eps = infinity give
+//               recomputation only.
 //
 // Conventions that the paper delegates to its renderer (Sec. 3.3) are fixed here as
 // plain textbook definitions (Stokes frames, rotators, Fresnel amplitudes in the Born &
@@ -1074,6 +1079,33 @@ static M4<double> inverse4(const M4<double>& a) {
     return r;
 }
 
+// Determinant by Gaussian elimination with partial pivoting.
+static double det4(const M4<double>& a) {
+    double m[4][4];
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) m[i][j] = a.m[i][j];
+    double det = 1.0;
+    for (int c = 0; c < 4; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 4; ++r) if (std::fabs(m[r][c]) > std::fabs(m[p][c])) p = r;
+        if (m[p][c] == 0.0) return 0.0;
+        if (p != c) { for (int j = 0; j < 4; ++j) std::swap(m[p][j], m[c][j]); det = -det; }
+        det *= m[c][c];
+        for (int r = c + 1; r < 4; ++r) {
+            double f = m[r][c] / m[c][c];
+            for (int j = c; j < 4; ++j) m[r][j] -= f * m[c][j];
+        }
+    }
+    return det;
+}
+
+// Depolarization index of Gil & Bernabeu (1985): sqrt(sum_ij M_ij^2 - M_00^2) / (sqrt(3) M_00); 1 for a
+// non-depolarizing Mueller matrix, 0 for an ideal depolarizer (Sec. 4.4, the test of Eq. 3).
+static double depol_index(const M4<double>& a) {
+    double s = 0.0;
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) s += a.m[i][j] * a.m[i][j];
+    return std::sqrt(std::max(0.0, s - a.m[0][0] * a.m[0][0])) / (std::sqrt(3.0) * a.m[0][0]);
+}
+
 // ============================================================================ drivers
 struct RunArgs {
     const Scene* sc;
@@ -1085,6 +1117,7 @@ struct RunArgs {
     uint64_t seed;
     int mode;
     int ckpt;                 // hybrid replay (mode 4): checkpoint interval k >= 1
+    double gamma, eps;        // hybrid replay decision rule (Eq. 3): DI threshold, determinant threshold
     const double* d_image;
     double* image;
     uint64_t* sig;
@@ -1094,8 +1127,9 @@ struct RunArgs {
 struct ThreadAcc {
     std::vector<std::vector<double>> g;
     int64_t n_vert = 0, n_path = 0;
-    int pix_slot = -1;      // slot whose per-pixel gradient image is requested
-    double pix_g = 0.0;     // that slot's gradient from the current pixel
+    int64_t n_branch[3] = {0, 0, 0};  // hybrid replay (mode 4): suffixes by scalar update, inversion, recomputation
+    int pix_slot = -1;              // slot whose per-pixel gradient image is requested
+    std::vector<double> pix_g;      // that slot's gradient (every element) from the current pixel
 };
 
 static void collect(const PAcc<Var>& PV, const std::vector<double>& adj, ThreadAcc& acc) {
@@ -1103,7 +1137,7 @@ static void collect(const PAcc<Var>& PV, const std::vector<double>& adj, ThreadA
         int s = (int)(kv.first >> 40);
         uint32_t i = (uint32_t)(kv.first & ((1ll << 40) - 1));
         if (!acc.g[s].empty()) acc.g[s][i] += adj[kv.second.i];
-        if (s == acc.pix_slot) acc.pix_g += adj[kv.second.i];
+        if (s == acc.pix_slot) acc.pix_g[i] += adj[kv.second.i];
     }
 }
 
@@ -1178,29 +1212,72 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
         PathGeom g2;
         trace_path(w, vw, px, py, s, A.seed, A.max_depth, A.flags, PP, g2);
         const int B2 = (int)g2.v.size();
-        // suffix source: cached fold (mode 2), inversion of the sampled weight (mode 3), or the
-        // next checkpoint folded back over the recomputed vertices in between (mode 4)
+        // suffix source: cached fold (mode 2), inversion of the sampled weight (mode 3), or, in
+        // mode 4, Eq. 3's rule inside each block of k vertices
         std::array<S4<double>, 3> Lcur;
         for (int ch = 0; ch < 3; ++ch) Lcur[ch] = A.mode == 4 ? szero<double>() : L[0][ch];
+        std::array<M4<double>, 3> bt;   // mode 4: detached block throughput W_s .. W_b
+        std::array<S4<double>, 3> Lrem; // mode 4: L[s] minus what vertices s .. b emit toward the block start
+        bool recomputed = false;        // mode 4: this block's suffixes were recomputed
         for (int b = 0; b < B2; ++b) {
             std::array<S4<double>, 3> Lnext;
             if (A.mode == 2) {
                 Lnext = L[b + 1];
             } else if (A.mode == 4) {
-                // suffix beyond vertex b: start at the first checkpoint c >= b + 1 (zero past the
-                // last vertex) and recompute L[v] = E_v + W_v L[v+1] for v = c-1 .. b+1
                 const int nb = b + 1;
-                int c = ((nb + K - 1) / K) * K;
-                if (c >= B2) {
-                    c = B2;
-                    for (int ch = 0; ch < 3; ++ch) Lnext[ch] = szero<double>();
-                } else {
-                    Lnext = Lck[c / K];
+                if (b % K == 0) {  // block start: its checkpoint holds the suffix L[s]
+                    for (int ch = 0; ch < 3; ++ch) { bt[ch] = meye<double>(); Lrem[ch] = Lck[b / K][ch]; }
+                    recomputed = false;
                 }
-                for (int v = c - 1; v >= nb; --v) {
-                    VEval<double> ev2;
-                    eval_vertex(w, g2.v[v], PVd, ev2);
-                    for (int ch = 0; ch < 3; ++ch) Lnext[ch] = sadd(ev2.E[ch], mvec(ev2.W[ch], Lnext[ch]));
+                // the detached weight and emission of vertex b extend the block throughput and use
+                // up part of the remaining radiance: Lrem = bt L[b+1] afterwards
+                VEval<double> evb;
+                eval_vertex(w, g2.v[b], PVd, evb);
+                for (int ch = 0; ch < 3; ++ch) {
+                    S4<double> e = mvec(bt[ch], evb.E[ch]);
+                    for (int q = 0; q < 4; ++q) Lrem[ch].s[q] -= e.s[q];
+                    bt[ch] = mmul(bt[ch], evb.W[ch]);
+                }
+                const int c = ((nb + K - 1) / K) * K;  // the next checkpoint
+                enum { CACHED, SCALAR, INVERT, RECOMPUTE } br = RECOMPUTE;
+                if (nb >= B2 || nb == c) {
+                    br = CACHED;
+                } else if (!recomputed) {
+                    // one decision for the three channels, on the channel of largest throughput
+                    // (the weights of a vertex differ between channels by a scale, which neither
+                    // test sees); a channel without throughput leaves only recomputation
+                    int cm = 0;
+                    double mmin = bt[0].m[0][0];
+                    for (int ch = 1; ch < 3; ++ch) {
+                        if (bt[ch].m[0][0] > bt[cm].m[0][0]) cm = ch;
+                        mmin = std::min(mmin, bt[ch].m[0][0]);
+                    }
+                    const double m00 = bt[cm].m[0][0];
+                    if (mmin > 0.0 && depol_index(bt[cm]) < A.gamma) br = SCALAR;
+                    else if (mmin > 0.0 && std::fabs(det4(bt[cm])) > A.eps * m00 * m00 * m00 * m00) br = INVERT;
+                }
+                if (br == RECOMPUTE) recomputed = true;
+                if (br == SCALAR) ++acc.n_branch[0];
+                else if (br == INVERT) ++acc.n_branch[1];
+                else if (br == RECOMPUTE) ++acc.n_branch[2];
+                if (br == CACHED) {
+                    for (int ch = 0; ch < 3; ++ch) Lnext[ch] = nb >= B2 ? szero<double>() : Lck[c / K][ch];
+                } else if (br == SCALAR) {  // treated as depolarizing: intensity only
+                    for (int ch = 0; ch < 3; ++ch) {
+                        Lnext[ch] = szero<double>();
+                        Lnext[ch].s[0] = Lrem[ch].s[0] / bt[ch].m[0][0];
+                    }
+                } else if (br == INVERT) {
+                    for (int ch = 0; ch < 3; ++ch) Lnext[ch] = mvec(inverse4(bt[ch]), Lrem[ch]);
+                } else {
+                    // recompute L[v] = E_v + W_v L[v+1] for v = c-1 .. b+1 from the next checkpoint
+                    Lnext = c >= B2 ? std::array<S4<double>, 3>{szero<double>(), szero<double>(), szero<double>()}
+                                    : Lck[c / K];
+                    for (int v = std::min(c, B2) - 1; v >= nb; --v) {
+                        VEval<double> ev2;
+                        eval_vertex(w, g2.v[v], PVd, ev2);
+                        for (int ch = 0; ch < 3; ++ch) Lnext[ch] = sadd(ev2.E[ch], mvec(ev2.W[ch], Lnext[ch]));
+                    }
                 }
             } else {
                 bool cont = g2.v[b].lobe != LOBE_NONE && g2.v[b].lobe != LOBE_INVALID;
@@ -1340,7 +1417,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
              const void* views_, int n_views, int max_depth, uint32_t flags, uint64_t seed, int mode,
              const double* d_image, double* image_out, double* const* grads_out, uint64_t* sig_out,
              const uint8_t* path_mask, int64_t* stats, int nthreads, char* err, int errlen, int pix_slot,
-             double* pix_grad, int ckpt_interval) {
+             double* pix_grad, int ckpt_interval, double hybrid_gamma, double hybrid_eps) {
     Scene* sc = (Scene*)scene;
     const View* views = (const View*)views_;
     if (!sc || n_slots != (int)sc->slot_numel.size()) { set_err(err, errlen, "slot count mismatch"); return -1; }
@@ -1365,7 +1442,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
     }
     g_gauge = (flags & FLAG_GAUGE) ? 1 : 0;
     RunArgs A{sc, params_path, params_val ? params_val : params_path, views, n_views, max_depth, flags, seed, mode,
-              ckpt_interval, d_image, image_out, sig_out, path_mask};
+              ckpt_interval, hybrid_gamma, hybrid_eps, d_image, image_out, sig_out, path_mask};
     // per-pixel index (view, crop row, crop column) for the gradient-image output
     std::vector<int64_t> pix_off(n_views + 1, 0);
     for (int v = 0; v < n_views; ++v) pix_off[v + 1] = pix_off[v] + (int64_t)views[v].crop_w * views[v].crop_h;
@@ -1382,6 +1459,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
     std::vector<ThreadAcc> accs(nt);
     for (auto& a : accs) {
         a.pix_slot = pix_grad ? pix_slot : -1;
+        if (a.pix_slot >= 0) a.pix_g.assign(sc->slot_numel[pix_slot], 0.0);
         a.g.resize(n_slots);
         if (mode > 0)
             for (int s = 0; s < n_slots; ++s)
@@ -1414,7 +1492,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
                     for (int a = 0; a < na; ++a)
                         for (int k = 0; k < 12; ++k) dC[a * 12 + k] = d_image[pix_img + a * a_stride + k] / vw.spp;
                 double sum[4][3][4] = {};
-                acc.pix_g = 0.0;
+                std::fill(acc.pix_g.begin(), acc.pix_g.end(), 0.0);
                 for (int s = 0; s < vw.spp; ++s) {
                     int64_t pidx = path_off[v] + ((int64_t)ly * vw.crop_w + lx) * vw.spp + s;
                     if (path_mask && !path_mask[pidx]) { if (sig_out) sig_out[pidx] = 0; continue; }
@@ -1424,7 +1502,9 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
                         for (int c = 0; c < 3; ++c)
                             for (int k = 0; k < 4; ++k) sum[a][c][k] += C[a][c][k];
                 }
-                if (pix_grad && mode > 0) pix_grad[pix_index(v, lx, ly)] = acc.pix_g;
+                if (pix_grad && mode > 0)
+                    for (size_t i = 0; i < acc.pix_g.size(); ++i)
+                        pix_grad[pix_index(v, lx, ly) * (int64_t)acc.pix_g.size() + (int64_t)i] = acc.pix_g[i];
                 if (image_out)
                     for (int a = 0; a < na; ++a)
                         for (int c = 0; c < 3; ++c)
@@ -1433,15 +1513,19 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
             }
         }
     }
-    int64_t nv = 0, np = 0;
+    int64_t nv = 0, np = 0, nbr[3] = {0, 0, 0};
     for (auto& a : accs) {
         nv += a.n_vert; np += a.n_path;
+        for (int k = 0; k < 3; ++k) nbr[k] += a.n_branch[k];
         if (mode > 0)
             for (int s = 0; s < n_slots; ++s)
                 if (grads_out && grads_out[s])
                     for (size_t i = 0; i < a.g[s].size(); ++i) grads_out[s][i] += a.g[s][i];
     }
-    if (stats) { stats[0] = nv; stats[1] = np; }
+    if (stats) {
+        stats[0] = nv; stats[1] = np;
+        for (int k = 0; k < 3; ++k) stats[2 + k] = nbr[k];
+    }
     g_gauge = 0;
     return 0;
 }

@@ -555,6 +555,33 @@ def polarizer_stack(n_sheets: int = 85, width: int = 1280, height: int = 720, sp
                     grad_slots=("floor_albedo",))
 
 
+def glossy_scene(seed: int = 3, width: int = 24, height: int = 16, spp: int = 4, max_depth: int = 8) -> Workload:
+    """Microfacet-only scene (GGX conductors and a GGX dielectric, no depolarizing or polarizer
+    surfaces) under one area light: every block of path vertices has an invertible Mueller
+    throughput away from Brewster-like reflections.  Full Stokes camera."""
+    rng = np.random.default_rng(seed)
+    sc = Scene()
+    s_rgh = sc.add_slot("roughness", [0.3, 0.2, 0.25])
+    s_eta = sc.add_slot("eta", [0.8, 1.5])
+    s_kap = sc.add_slot("kappa", [3.5])
+    s_le = sc.add_slot("light_Le", [10.0, 10.0, 10.0])
+    w = sc.add_world()
+    m_gc = w.add_material(type=MAT_GGX_CONDUCTOR, alpha_slot=s_rgh, alpha_off=0, eta_slot=s_eta, eta_off=0,
+                          kappa_slot=s_kap)
+    m_gd = w.add_material(type=MAT_GGX_DIELECTRIC, alpha_slot=s_rgh, alpha_off=1, eta_slot=s_eta, eta_off=1)
+    m_gc2 = w.add_material(type=MAT_GGX_CONDUCTOR, alpha_slot=s_rgh, alpha_off=2, eta_slot=s_eta, eta_off=0,
+                           kappa_slot=s_kap)
+    _ground(w, -1.0, 8.0, m_gc)
+    for k in range(5):
+        c = np.array([rng.uniform(-2, 2), rng.uniform(-0.3, 0.8), rng.uniform(-2, 1)])
+        w.add_tris(0.6 * icosphere(2) + c, None, (m_gd, m_gc2)[k % 2])
+    w.add_quad((-4, -1, -3), (8, 0, 0), (0, 6, 0), m_gc2)
+    w.add_light((-1.5, 3.5, -1.5), (3, 0, 0), (0, 0, 3), s_le)
+    views = np.asarray([make_view(0, width, height, spp, (0, 1.5, 6), (0, 0, 0), (0, 1, 0), 50.0, SENSOR_NONE)],
+                       VIEW_DTYPE)
+    return Workload("glossy", sc, views, max_depth=max_depth, seed=5, grad_slots=("roughness", "eta", "kappa"))
+
+
 # ----------------------------------------------------------------------------- light stage
 def normal_map(rng, h, w, amp, coarse=8):
     """Tangent-space normal map input (t, b, n) = (gx, gy, 1) with smooth seeded slopes in
