@@ -90,7 +90,10 @@ def parse():
     ap.add_argument("--per-view-steps", type=int, default=2)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=48, help="full views in the oracle sample")
+    ap.add_argument("--cpu-views", type=int, default=48, help="full views in the oracle sample (all host threads)")
+    ap.add_argument("--cpu-views-1t", type=int, default=2, help="full views in the one-thread oracle sample")
+    ap.add_argument("--bounded-chunk", type=int, default=1 << 22,
+                    help="chunk size of the memory-bounded measurement (0: skip)")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
     ap.add_argument("--workload", choices=("batched128", "uneven8", "lightstage", "optimise", "depth_sweep"),
                     default="batched128",
@@ -319,6 +322,10 @@ def main():
         plan.render(params, wl.seed, out=out, ws=ws_r)
         plan.backward(params, wl.seed, d, grads=grads, ws=ws_b)
 
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)  # (the autotuner's trial plans are gone)
+
     # eager warm-up, counters, and per-kernel timing with events on the launch stream
     for _ in range(max(1, args.warmup)):
         step()
@@ -378,20 +385,57 @@ def main():
                    "autotune_ms": tuned},
     }
 
-    # per-view launches on the same paths (view_id keeps the random streams identical)
+    peak_timed = torch.cuda.max_memory_allocated(dev)
+    result["memory"] = {"render_workspace_gb": round(plan.workspace_bytes(0) / 1e9, 3),
+                        "backward_workspace_gb": round(plan.workspace_bytes(1) / 1e9, 3),
+                        "peak_allocated_gb": round(peak_timed / 1e9, 3)}
+
+    # the same step with a memory-bounded chunk (the path records of 2^22 paths in flight)
+    if args.bounded_chunk and args.bounded_chunk < info["chunk_paths"]:
+        pb = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, chunk_paths=args.bounded_chunk)
+        pb.set_stats(False)
+        wb_r, wb_b = pb.workspace(0), pb.workspace(1)
+        gb_ = [torch.empty_like(p) if w else None for p, w in zip(params, want)]
+        for _ in range(2):
+            pb.render(params, wl.seed, out=out, ws=wb_r)
+            pb.backward(params, wl.seed, d, grads=gb_, ws=wb_b)
+        torch.cuda.synchronize()
+        nb = max(2, args.steps // 4)
+        e0.record()
+        for _ in range(nb):
+            pb.render(params, wl.seed, out=out, ws=wb_r)
+            pb.backward(params, wl.seed, d, grads=gb_, ws=wb_b)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / nb
+        gdiff = max(float((a - b).norm() / max(float(b.norm()), 1e-30)) for a, b in zip(gb_, grads) if a is not None)
+        result["memory_bounded"] = {"chunk_paths": pb.launch_info()["chunk_paths"], "chunks": pb.launch_info()["n_chunks"],
+                                    "value": round(verts / (ms_b * 1e-3) / 1e6, 2), "ms_per_step": round(ms_b, 3),
+                                    "render_workspace_gb": round(pb.workspace_bytes(0) / 1e9, 3),
+                                    "backward_workspace_gb": round(pb.workspace_bytes(1) / 1e9, 3),
+                                    "grad_rel_diff_vs_timed": gdiff}
+        log(f"[bench] memory-bounded chunk {args.bounded_chunk}: {ms_b:.2f} ms/step, "
+            f"{result['memory_bounded']['value']} Mpath-vertices/s, backward workspace "
+            f"{result['memory_bounded']['backward_workspace_gb']} GB, grad rel diff {gdiff:.2e}")
+        del pb, wb_r, wb_b, gb_
+        torch.cuda.empty_cache()
+
+    # per-view launches on the same paths (view_id keeps the random streams identical); every view
+    # keeps its own gradient tensors, summed afterwards and compared with the batched gradients
     if not args.no_per_view:
         plans = []
         for v in range(len(wl.views)):
             pv = ppt.Plan(scene, wl.views[v:v + 1], wl.max_depth, wl.flags, chunk_paths=chunk)
             plans.append(pv)
         outs = [torch.empty(p.image_numel, dtype=torch.float32, device=dev) for p in plans]
+        gviews = [[torch.empty_like(p) if w else None for p, w in zip(params, want)] for _ in plans]
         offs = sg.view_offsets(wl.views)
         ds = [d[int(offs[v]):int(offs[v]) + plans[v].image_numel] for v in range(len(plans))]
 
         def step_pv():
             for v, pv in enumerate(plans):
                 pv.render(params, wl.seed, out=outs[v], ws=ws_r)
-                pv.backward(params, wl.seed, ds[v], grads=grads, ws=ws_b)
+                pv.backward(params, wl.seed, ds[v], grads=gviews[v], ws=ws_b)
 
         step_pv()
         torch.cuda.synchronize()
@@ -401,14 +445,22 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_pv = e0.elapsed_time(e1) / args.per_view_steps
-        plan.render(params, wl.seed, out=out, ws=ws_r)
+        step()
         torch.cuda.synchronize()
         img_pv = torch.cat(outs)
         img_rel = float((img_pv - out).norm() / out.norm())
+        grad_rel = {}
+        for i, name in enumerate(wl.scene.slot_names):
+            if grads[i] is None:
+                continue
+            gsum = torch.stack([gv[i].double() for gv in gviews]).sum(0)
+            grad_rel[name] = float((gsum - grads[i].double()).norm() / max(float(grads[i].double().norm()), 1e-30))
         result["per_view"] = {"value": round(verts / (ms_pv * 1e-3) / 1e6, 2), "ms_per_step": round(ms_pv, 3),
-                              "launches_per_step": 2 * len(plans), "image_rel_diff_vs_batched": img_rel}
+                              "launches_per_step": 2 * len(plans), "image_rel_diff_vs_batched": img_rel,
+                              "grad_rel_diff_vs_batched": grad_rel}
         result["speedup_batched_vs_per_view"] = round(ms_pv / ms_step, 3)
-        log(f"[bench] per-view: {ms_pv:.2f} ms/step, image rel diff {img_rel:.2e}")
+        log(f"[bench] per-view: {ms_pv:.2f} ms/step, image rel diff {img_rel:.2e}, summed gradients rel diff {grad_rel}")
+        del plans, outs, gviews
 
     # per-kernel HIP-event timing on the launch stream (eager steps right after the timed region)
     plan.set_timing(True)
@@ -458,32 +510,132 @@ def main():
                           "kernels": {KERNEL_SYMBOL[f]: v for f, v in fams.items()},
                           "counters": {"render": st_r, "backward": st_b}}
 
-    # CPU baseline: the FP64 oracle (render + cached-suffix replay) on a bounded sample of whole views
+    # CPU baseline and accuracy of the timed configuration: the FP64 oracle (render + cached-suffix
+    # replay) on a bounded sample of the workload, whose image and gradients are also the reference
+    # for the timed plan's output on the same paths
     if not args.no_cpu:
-        import oracle
-        nthreads = min(16, os.cpu_count() or 1)
-        if args.workload == "batched128":
-            sample_views = wl.views[:max(1, min(args.cpu_views, len(wl.views)))]
-            sample_desc = f"{len(sample_views)} of the {len(wl.views)} views, whole {args.res}x{args.res} images"
+        result.update(cpu_leg(args, torch, ppt, sg, wl, plan, params, d, out, want))
+
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_leg(args, torch, ppt, sg, wl, plan, params, d, out, want):
+    """The oracle timed at all host threads of this GPU's share and at one thread, and the parity of
+    the timed configuration: the timed plan's image and gradients on the sampled views (dL/dI zero
+    elsewhere; paths whose discrete decisions differ masked on both sides) against the oracle's."""
+    import oracle
+    # threads: the CPU share of this GPU's job (OMP_NUM_THREADS where the launcher sets it), else
+    # every CPU this process may run on
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    if args.workload == "batched128":
+        sel = np.arange(max(1, min(args.cpu_views, len(wl.views))))
+        sample_views = wl.views[sel]
+        sample_desc = f"{len(sel)} of the {len(wl.views)} views, whole {args.res}x{args.res} images"
+        crop = None
+    else:
+        sel = np.arange(len(wl.views))
+        sample_views = sg.crop_views(wl.views, 0, 0, 64, 64)
+        sample_views["crop_x0"] = (sample_views["width"] - 64) // 2
+        sample_views["crop_y0"] = (sample_views["height"] - 64) // 2
+        sample_desc = f"the central 64x64 crop of each of the {len(wl.views)} views"
+        crop = sample_views
+    osc = oracle.OracleScene.from_scene(wl.scene)
+    p64 = [p.astype(np.float64) for p in wl.scene.params()]
+    # the GPU's per-path index of every sampled path, and the sampled part of the image vector
+    offs = sg.view_offsets(wl.views)
+    path_off = np.concatenate([[0], np.cumsum(wl.views["crop_w"].astype(np.int64) * wl.views["crop_h"]
+                                              * wl.views["spp"])])
+    gidx, iidx = [], []
+    for j, v in enumerate(sel):
+        vw = wl.views[v]
+        W, H, spp, A = int(vw["crop_w"]), int(vw["crop_h"]), int(vw["spp"]), sg.analyzer_count(int(vw["sensor"]))
+        if crop is None:
+            x0, y0, w, h = 0, 0, W, H
         else:
-            sample_views = sg.crop_views(wl.views, 0, 0, 64, 64)
-            sample_views["crop_x0"] = (sample_views["width"] - 64) // 2
-            sample_views["crop_y0"] = (sample_views["height"] - 64) // 2
-            sample_desc = f"the central 64x64 crop of each of the {len(wl.views)} views"
-        osc = oracle.OracleScene.from_scene(wl.scene)
-        p64 = [p.astype(np.float64) for p in wl.scene.params()]
-        dd = np.random.default_rng(1).standard_normal(sg.image_numel(sample_views))
-        t0 = time.perf_counter()
-        r = osc.run(p64, sample_views, wl.max_depth, wl.seed, nthreads=nthreads)
-        r2 = osc.run(p64, sample_views, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=dd,
-                     want_image=False, nthreads=nthreads)
-        tc = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": round(r["n_vertices"] / tc / 1e6, 4), "unit": "Mpath-vertices/s",
-                                  "cores": nthreads, "kind": "oracle",
-                                  "sample": f"{sample_desc} at full spp, depth {wl.max_depth} "
-                                            f"({r['n_paths']} paths, {r['n_vertices']} vertices): FP64 render + "
-                                            f"cached-suffix replay, {tc:.1f} s"}
-        log(f"[bench] cpu oracle: {result['cpu_baseline']}")
+            x0, y0, w, h = int(crop[j]["crop_x0"]), int(crop[j]["crop_y0"]), 64, 64
+        ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
+        pix = (ys * W + xs).ravel()
+        gidx.append(path_off[v] + (pix[:, None] * spp + np.arange(spp)[None, :]).ravel())
+        ent = (pix[:, None] * 12 + np.arange(12)[None, :]).ravel()
+        iidx.append(np.concatenate([int(offs[v]) + a * W * H * 12 + ent for a in range(A)]))
+    gidx, iidx = np.concatenate(gidx), np.concatenate(iidx)
+    d_all = d.cpu().numpy()
+    dd = d_all[iidx].astype(np.float64)
+    grad_slots = [i for i, w in enumerate(want) if w]
+    # all threads: render (with the per-path signatures) + cached-suffix replay
+    t0 = time.perf_counter()
+    r = osc.run(p64, sample_views, wl.max_depth, wl.seed, want_sig=True, nthreads=nthreads)
+    r2 = osc.run(p64, sample_views, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=dd,
+                 want_image=False, grad_slots=grad_slots, nthreads=nthreads)
+    tc = time.perf_counter() - t0
+    base = {"value": round(r["n_vertices"] / tc / 1e6, 4), "unit": "Mpath-vertices/s", "cores": nthreads,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "sample": f"{sample_desc} at full spp, depth {wl.max_depth} ({r['n_paths']} paths, {r['n_vertices']} "
+                      f"vertices): FP64 render + cached-suffix replay, {tc:.1f} s on {nthreads} threads"}
+    log(f"[bench] cpu oracle ({nthreads} threads): {base['value']} Mpath-vertices/s")
+    # one thread on a smaller sample
+    n1 = max(1, min(args.cpu_views_1t, len(sample_views)))
+    v1 = sample_views[:n1]
+    d1 = np.random.default_rng(1).standard_normal(sg.image_numel(v1))
+    t0 = time.perf_counter()
+    q = osc.run(p64, v1, wl.max_depth, wl.seed, nthreads=1)
+    osc.run(p64, v1, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=d1, want_image=False,
+            grad_slots=grad_slots, nthreads=1)
+    t1 = time.perf_counter() - t0
+    base["one_thread"] = {"value": round(q["n_vertices"] / t1 / 1e6, 4), "cores": 1,
+                          "sample": f"{n1} of the sampled views ({q['n_paths']} paths, {q['n_vertices']} vertices), "
+                                    f"{t1:.1f} s"}
+    log(f"[bench] cpu oracle (1 thread): {base['one_thread']['value']} Mpath-vertices/s")
+    # parity of the timed plan on the sampled paths
+    sig_g = plan.signatures(params, wl.seed).cpu().numpy().view(np.uint64)[gidx]
+    agree = sig_g == r["sig"]
+    img_ref, grads_ref = r["image"], r2["grads"]
+    if not agree.all():  # mask the divergent paths on both sides
+        mk = agree.astype(np.uint8)
+        img_ref = osc.run(p64, sample_views, wl.max_depth, wl.seed, mask=mk, nthreads=nthreads)["image"]
+        grads_ref = osc.run(p64, sample_views, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=dd,
+                            want_image=False, grad_slots=grad_slots, mask=mk, nthreads=nthreads)["grads"]
+        mask_full = torch.ones(plan.num_paths, dtype=torch.uint8, device=params[0].device)
+        mask_full[torch.from_numpy(gidx[~agree]).to(params[0].device)] = 0
+        plan.set_path_mask(mask_full)
+    plan.render(params, wl.seed, out=out)
+    img_g = out.cpu().numpy()[iidx].astype(np.float64)
+    d_s = torch.zeros_like(d)
+    d_s[torch.from_numpy(iidx).to(d.device)] = d[torch.from_numpy(iidx).to(d.device)]
+    g = plan.backward(params, wl.seed, d_s, want=want)
+    plan.set_path_mask(None)
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        nb = float(np.linalg.norm(b))
+        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+    par = {"img_rel": rel(img_g, img_ref), "grad_rel": {}, "divergent_paths": int((~agree).sum()),
+           "paths_compared": int(agree.size), "reference": "FP64 oracle, cached-suffix replay",
+           "gates": {"img_rel": 1e-4, "grad_rel": 1e-3}}
+    for i in grad_slots:
+        par["grad_rel"][wl.scene.slot_names[i]] = rel(g[i].double().cpu().numpy(), grads_ref[i])
+    par["pass"] = bool(par["img_rel"] <= 1e-4 and all(v <= 1e-3 for v in par["grad_rel"].values())
+                       and par["divergent_paths"] <= 0.01 * agree.size)
+    log(f"[bench] parity of the timed configuration: {par}")
+    return {"cpu_baseline": base, "parity": par}
+
 
     line = json.dumps(result)
     print(line, flush=True)

@@ -1,6 +1,7 @@
 """Autotuner for the batched launch: picks the chunk size (paths in flight per launch sequence)
-that minimises render + backward time for a given scene / views / depth, and caches the choice
-in a JSON file keyed by a digest of the workload."""
+that minimises render + backward time (the median of several timed steps after a warm-up) for a
+given scene / views / depth, and caches the choice in a JSON file keyed by a digest of the
+workload."""
 from __future__ import annotations
 
 import hashlib
@@ -27,24 +28,27 @@ def workload_key(blob: bytes, views, max_depth: int, flags: int, device_name: st
 
 
 def _time_step(plan, params, d, want, reps):
+    """Median over reps timed render + backward steps, after one untimed step."""
     out = torch.empty(plan.image_numel, dtype=torch.float32, device=params[0].device)
     grads = [torch.empty_like(p) if w else None for p, w in zip(params, want)]
     ws0, ws1 = plan.workspace(0), plan.workspace(1)
     plan.render(params, 1, out=out, ws=ws0)
     plan.backward(params, 1, d, grads=grads, ws=ws1)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    ms = []
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         plan.render(params, 1, out=out, ws=ws0)
         plan.backward(params, 1, d, grads=grads, ws=ws1)
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms))
 
 
 def tune(scene, blob: bytes, views, max_depth: int, params, want=None, flags: int = 0, candidates=CANDIDATES,
-         reps: int = 1, cache_path: str = DEFAULT_CACHE, force: bool = False, log=None):
+         reps: int = 3, cache_path: str = DEFAULT_CACHE, force: bool = False, log=None):
     """Returns (chunk_paths, {candidate: ms}) and records the choice in the cache file."""
     dev_name = torch.cuda.get_device_name(params[0].device)
     key = workload_key(blob, views, max_depth, flags, dev_name)
