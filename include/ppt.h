@@ -70,6 +70,20 @@ typedef struct ppt_plan_opts {
                                    * replay, only a 16-byte hit record per vertex, the suffix every k
                                    * vertices, and the vertices in between recomputed from it (exact;
                                    * less workspace for deep paths, more arithmetic).  k <= 128. */
+    int32_t hybrid_rule;          /* hybrid replay only.  0: a suffix inside a block is recovered by
+                                   * recomputing the block from its checkpoint.  1: Eq. 3's decision
+                                   * rule (Sec. 4.4): the replay tracks the detached block throughput
+                                   * beta since the block's checkpoint and the radiance its vertices
+                                   * have not yet emitted, and recovers a suffix by the scalar PRB
+                                   * update (intensity only) when the depolarization index of beta
+                                   * (Gil-Bernabeu) is below hybrid_gamma, by inverting beta when
+                                   * |det beta| > hybrid_eps beta_00^4, else by recomputing the rest
+                                   * of the block.  The scalar update is exact where the suffix's
+                                   * polarization is not needed (depolarizing blocks) and an
+                                   * approximation elsewhere; inversion is exact up to rounding, which
+                                   * it amplifies by the condition number of beta. */
+    float hybrid_gamma;           /* >= 0; 0 disables the scalar update */
+    float hybrid_eps;             /* >= 0 (infinity disables inversion) */
 } ppt_plan_opts;
 
 typedef struct ppt_scene ppt_scene;
@@ -179,7 +193,9 @@ int ppt_backward_noalloc(const ppt_plan* plan, const float* const* params, int32
                          const float* d_stokes, float* const* grads, void* stream);
 
 /* Per-path 64-bit signatures (FNV-1a over primitive id, light-sample state and lobe of every
- * vertex) used to detect paths whose discrete decisions differ from another implementation.
+ * vertex, the lobe word of a sampled direction also holding the branch of its sampling frame, the
+ * sign of the shading normal's z in the Duff et al. basis) used to detect paths whose discrete decisions differ
+ * from another implementation.
  * sig_out: device, num_paths uint64.  ws as for ppt_render. */
 int ppt_signatures(const ppt_plan* plan, const float* const* params, int32_t n_params, uint64_t seed,
                    uint64_t* sig_out, void* ws, size_t ws_bytes, void* stream);
@@ -192,6 +208,12 @@ int ppt_signatures(const ppt_plan* plan, const float* const* params, int32_t n_p
  * out: host, 8 entries. */
 int ppt_plan_set_stats(ppt_plan* plan, int32_t enabled);
 int ppt_read_stats(const void* ws, int64_t* out, void* stream);
+
+/* Branch counts of the hybrid replay's decision rule in the last backward call made with workspace
+ * ws while the plan's counters were enabled: out[0] suffixes recovered by the scalar update,
+ * out[1] by inversion, out[2] by recomputation (a recomputation covers the rest of its block).
+ * Synchronizes the stream.  out: host, 3 entries. */
+int ppt_read_hybrid_stats(const void* ws, int64_t* out, void* stream);
 
 /* Per-kernel event timing (diagnostics).  While enabled, every render/backward call on the plan
  * records a HIP event on its stream before each kernel launch and one after its last launch.

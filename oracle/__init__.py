@@ -115,7 +115,8 @@ class OracleScene:
         """Run the oracle.  ``params`` (and ``params_val``) are per-slot arrays (converted to float64).
 
         Returns a dict with ``image`` (float64, [V][A][h][w][3][4] flattened per view),
-        ``hybrid_branches`` (mode 4: how many suffixes each branch of Eq. 3 recovered),
+        ``hybrid_branches`` (mode 4: how often Eq. 3's rule chose each branch; one recomputation
+        covers the rest of its block),
         ``grads`` (list per slot, None where not requested), ``sig`` (uint64 per path),
         ``n_vertices`` and ``n_paths``; with ``pixel_grad_slot`` also ``pixel_grad``: that slot's
         gradient split by pixel (the gradient images of Sec. 5.1), shape (pixels, slot elements) with

@@ -875,7 +875,13 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
             double side = dot(ngf, x.wi);
             if (x.lobe == LOBE_TRANSMIT ? !(side < 0.0) : !(side > 0.0)) x.lobe = LOBE_INVALID;
         }
-        sig.add((uint32_t)x.prim); sig.add((uint32_t)x.lobe); sig.add((uint32_t)x.nee);
+        // (parity signature: the lobe word of a sampled direction also carries the branch of the
+        // sampling frame, the sign of ns.z in the Duff et al. basis, which rounding can flip for a
+        // normal with z near 0)
+        const bool framed = x.lobe == LOBE_DIFFUSE || x.lobe == LOBE_GLOSSY;
+        sig.add((uint32_t)x.prim);
+        sig.add((uint32_t)x.lobe | (framed && std::signbit(x.ns.z) ? 16u : 0u));
+        sig.add((uint32_t)x.nee);
         g.v.push_back(x);
         if (x.lobe == LOBE_INVALID) break;
         prev_delta = is_delta(m.type);
@@ -1127,7 +1133,8 @@ struct RunArgs {
 struct ThreadAcc {
     std::vector<std::vector<double>> g;
     int64_t n_vert = 0, n_path = 0;
-    int64_t n_branch[3] = {0, 0, 0};  // hybrid replay (mode 4): suffixes by scalar update, inversion, recomputation
+    int64_t n_branch[3] = {0, 0, 0};  // hybrid replay (mode 4): decisions for the scalar update, inversion and
+                                      // recomputation (one recomputation covers the rest of its block)
     int pix_slot = -1;              // slot whose per-pixel gradient image is requested
     std::vector<double> pix_g;      // that slot's gradient (every element) from the current pixel
 };
@@ -1240,9 +1247,11 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
                 }
                 const int c = ((nb + K - 1) / K) * K;  // the next checkpoint
                 enum { CACHED, SCALAR, INVERT, RECOMPUTE } br = RECOMPUTE;
+                bool decided = false;
                 if (nb >= B2 || nb == c) {
                     br = CACHED;
                 } else if (!recomputed) {
+                    decided = true;
                     // one decision for the three channels, on the channel of largest throughput
                     // (the weights of a vertex differ between channels by a scale, which neither
                     // test sees); a channel without throughput leaves only recomputation
@@ -1257,9 +1266,7 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
                     else if (mmin > 0.0 && std::fabs(det4(bt[cm])) > A.eps * m00 * m00 * m00 * m00) br = INVERT;
                 }
                 if (br == RECOMPUTE) recomputed = true;
-                if (br == SCALAR) ++acc.n_branch[0];
-                else if (br == INVERT) ++acc.n_branch[1];
-                else if (br == RECOMPUTE) ++acc.n_branch[2];
+                if (decided) ++acc.n_branch[br == SCALAR ? 0 : br == INVERT ? 1 : 2];
                 if (br == CACHED) {
                     for (int ch = 0; ch < 3; ++ch) Lnext[ch] = nb >= B2 ? szero<double>() : Lck[c / K][ch];
                 } else if (br == SCALAR) {  // treated as depolarizing: intensity only

@@ -33,6 +33,7 @@ SIGNATURES = {
     "ppt_backward_noalloc": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _vp]),
     "ppt_signatures": (_i32, [_vp, _vp, _i32, _u64, _vp, _vp, _sz, _vp]),
     "ppt_read_stats": (_i32, [_vp, _vp, _vp]),
+    "ppt_read_hybrid_stats": (_i32, [_vp, _vp, _vp]),
     "ppt_debug_rng": (_i32, [_u64, _vp, _vp, _i64, _vp]),
     "ppt_plan_launch_info": (_i32, [_vp, _vp, _vp, _vp]),
     "ppt_last_error": (ctypes.c_char_p, []),
@@ -44,7 +45,8 @@ class PPTError(RuntimeError):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("chunk_paths", ctypes.c_int64), ("checkpoint_interval", ctypes.c_int64)]
+    _fields_ = [("chunk_paths", ctypes.c_int64), ("checkpoint_interval", ctypes.c_int64),
+                ("hybrid_rule", ctypes.c_int32), ("hybrid_gamma", ctypes.c_float), ("hybrid_eps", ctypes.c_float)]
 
 
 _lib = None

@@ -57,15 +57,17 @@ class Scene:
 
 class Plan:
     """Views + max depth + flags; paths of all views are processed in chunks of chunk_paths.
-    checkpoint_interval k > 0 selects the hybrid cached replay for the backward pass."""
+    checkpoint_interval k > 0 selects the hybrid cached replay for the backward pass; with
+    hybrid_rule (a (gamma, eps) pair) it recovers suffixes inside a block by Eq. 3's decision rule."""
 
     def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, chunk_paths: int = 0,
-                 checkpoint_interval: int = 0):
+                 checkpoint_interval: int = 0, hybrid_rule=None):
         self.scene = scene
         self.views = np.ascontiguousarray(views, VIEW_DTYPE)
         self.max_depth = int(max_depth)
         self.flags = int(flags)
-        opts = PlanOpts(int(chunk_paths), int(checkpoint_interval))
+        rule = (0, 0.0, 0.0) if hybrid_rule is None else (1, float(hybrid_rule[0]), float(hybrid_rule[1]))
+        opts = PlanOpts(int(chunk_paths), int(checkpoint_interval), *rule)
         h = ctypes.c_void_p()
         check(lib().ppt_plan_create(scene.handle, self.views.ctypes.data_as(ctypes.c_void_p), len(self.views),
                                     self.max_depth, self.flags, ctypes.byref(opts), ctypes.byref(h)))
@@ -195,6 +197,13 @@ class Plan:
         check(lib().ppt_signatures(self._h, ptr_table(params), len(params), int(seed) & (2**64 - 1),
                                    ctypes.c_void_p(sig.data_ptr()), wp, wn, _stream(stream)))
         return sig
+
+    def hybrid_stats(self, stream=None):
+        """Branch counts (scalar, invert, recompute) of the decision rule in the last backward call."""
+        ws = self._ws[(1, str(torch.device("cuda", torch.cuda.current_device())))]
+        out = (ctypes.c_int64 * 3)()
+        check(lib().ppt_read_hybrid_stats(self._ws_args(ws)[0], out, _stream(stream)))
+        return {"scalar": int(out[0]), "invert": int(out[1]), "recompute": int(out[2])}
 
     def stats(self, op: int, stream=None):
         ws = self._ws[(op, str(torch.device("cuda", torch.cuda.current_device())))]

@@ -232,6 +232,8 @@ struct ppt_plan {
     bool stats = true;
     bool timing = false;
     int32_t ckpt = 0;           // hybrid replay checkpoint interval, 0 = cached
+    int32_t hyb_rule = 0;       // hybrid replay decision rule (Eq. 3) and its thresholds
+    float hyb_gamma = 0.0f, hyb_eps = 0.0f;
     mutable KTimer timer[2];  // most recent render / backward call while timing is enabled
 };
 
@@ -638,6 +640,15 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
         return fail(PPT_EINVAL, "checkpoint_interval must be in [0, 128]");
     }
     P->ckpt = opts ? (int32_t)opts->checkpoint_interval : 0;
+    if (opts && opts->hybrid_rule) {
+        if (opts->hybrid_rule != 1 || P->ckpt < 1 || !(opts->hybrid_gamma >= 0.0f) || !(opts->hybrid_eps >= 0.0f)) {
+            delete P;
+            return fail(PPT_EINVAL, "hybrid_rule needs checkpoint_interval >= 1, hybrid_gamma >= 0 and hybrid_eps >= 0");
+        }
+        P->hyb_rule = 1;
+        P->hyb_gamma = opts->hybrid_gamma;
+        P->hyb_eps = opts->hybrid_eps;
+    }
     int64_t q = opts && opts->chunk_paths > 0 ? opts->chunk_paths : (int64_t)1 << 24;
     q = std::min<int64_t>(q, std::max<int64_t>(path_off, 1));
     q = ((q + WAVE - 1) / WAVE) * WAVE;
@@ -806,6 +817,10 @@ static int backward_impl(const ppt_plan* p, const float* const* params, int32_t 
     a.lds_nd = L.lds_nd;
     a.lds_nf = L.lds_nf;
     a.ckpt = p->ckpt;
+    a.hyb_rule = p->hyb_rule;
+    a.hyb_gamma = p->hyb_gamma;
+    a.hyb_eps = p->hyb_eps;
+    a.hyb_stats = a.stats ? ((Stats*)((char*)ws + L.stats))->hyb : nullptr;
     const LaunchMarker M = op_timer >= 0 ? marker(p, op_timer) : LaunchMarker{nullptr, nullptr};
     if (op_timer >= 0 && p->timing) p->timer[op_timer].begin();
     M(KF_OTHER, s);
@@ -884,6 +899,16 @@ int ppt_read_stats(const void* ws, int64_t* out, void* stream) {
     HIP_TRY(hipMemcpyAsync(&st, (const char*)ws + off, sizeof st, hipMemcpyDeviceToHost, (hipStream_t)stream), "stats copy");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "stats sync");
     for (int k = 0; k < ST_COUNT; ++k) out[k] = (int64_t)st.c[k];
+    return PPT_OK;
+}
+
+int ppt_read_hybrid_stats(const void* ws, int64_t* out, void* stream) {
+    if (!ws || !out) return fail(PPT_EINVAL, "null argument");
+    size_t off = align256(sizeof(CallTable));
+    Stats st;
+    HIP_TRY(hipMemcpyAsync(&st, (const char*)ws + off, sizeof st, hipMemcpyDeviceToHost, (hipStream_t)stream), "stats copy");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "stats sync");
+    for (int k = 0; k < 3; ++k) out[k] = (int64_t)st.hyb[k];
     return PPT_OK;
 }
 

@@ -111,6 +111,7 @@ constexpr int LDS_GRAD_F = 12800;   // FP32 entries (textures)
 enum { ST_VERTICES, ST_PATHS, ST_NODES, ST_PRIMS, ST_SHADOW_RAYS, ST_RAYS, ST_SHADOW_NODES, ST_SHADOW_PRIMS, ST_COUNT };
 struct Stats {
     unsigned long long c[ST_COUNT];
+    unsigned long long hyb[3];  // hybrid replay decision rule: suffixes by scalar update, inversion, recomputation
 };
 
 // Kernel families for the optional per-launch event timing.
@@ -158,6 +159,10 @@ struct WArgs {
     int32_t first;          // first bounce: the queue is the identity over the chunk's slots
     int32_t lds_nd, lds_nf;  // used entries of the workgroup gradient accumulators
     int32_t ckpt;           // hybrid replay checkpoint interval k, 0 = cached suffix replay
+    int32_t hyb_rule;       // hybrid replay: Eq. 3's decision rule (else recomputation only)
+    float hyb_gamma;        // scalar PRB update below this depolarization index
+    float hyb_eps;          // inversion above this determinant of the normalised block throughput
+    unsigned long long* hyb_stats;  // NULL or 3 counters of the rule's branches
     int32_t ext;            // the scene uses normal maps, specular maps or circular emitters
     float* out;             // render output
     const float* dout;      // backward: dL/dStokes

@@ -416,7 +416,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 if (A.sig) {
                     uint64_t sg = A.sig[g];
                     sig_add(sg, (uint32_t)x.orig);
-                    sig_add(sg, (uint32_t)x.lobe);
+                    // (a sampled direction's lobe word also carries the branch of the sampling frame,
+                    // the sign of ns.z in the Duff et al. basis, which rounding can flip for a normal
+                    // with z near 0)
+                    const bool framed = x.lobe == LOBE_DIFFUSE || x.lobe == LOBE_GLOSSY;
+                    sig_add(sg, (uint32_t)x.lobe | (framed && signbit(x.ns.z) ? 16u : 0u));
                     if (x.nee != NEE_PENDING) sig_add(sg, (uint32_t)x.nee);
                     A.sig[g] = sg;
                 }
@@ -616,13 +620,13 @@ DEV void w_apply_select(const WC& w, int c, const float* in, float* out) {
 // Hybrid cached replay (Sec. 4.4): the primal pass keeps a hit record per vertex and, every k
 // vertices, the ray into the block's first vertex; suffix values are kept only at block ends.
 // block_eval re-evaluates vertices [s, e) of the path in `slot` from the ray (o, d) into vertex s,
-// with each vertex's recorded next-event visibility, into the scratch cache records 0 .. e-s-1
-// (W_b and E_b); block_fold then folds them back from the suffix L beyond the block's last vertex,
-// leaving in L the suffix at its first vertex (with store_suffix, each record's E words receive
-// the suffix beyond its vertex, which the replay reads).
+// with each vertex's recorded next-event visibility, into the scratch cache records rec0 ..
+// rec0 + e-s-1 (W_b and E_b); block_fold then folds records rec0 .. rec0 + n-1 back from the
+// suffix L beyond the last of them, leaving in L the suffix at the first one's vertex (with
+// store_suffix, each record's E words receive the suffix beyond its vertex, which the replay reads).
 template <bool EXT>
 DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWorld& W, int slot, uint32_t pix,
-                    uint32_t smp, int s, int e, v3 o, v3 d, bool prev_delta) {
+                    uint32_t smp, int s, int e, v3 o, v3 d, bool prev_delta, int rec0 = 0) {
     const PathState& S = A.S;
     const int Q = A.Q;
     for (int v = s; v < e; ++v) {
@@ -640,7 +644,7 @@ DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWo
         WC w;
         float Ee[12], En[12];
         eval_vertex<false, EXT>(W, K, x, w, Ee, En, nullptr, nullptr);
-        float4* C = cache_rec(S, Q, v - s, slot);
+        float4* C = cache_rec(S, Q, rec0 + v - s, slot);
         C[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
         C[1] = f4(w.B, w.C, w.D, w.ci);
         C[2] = f4(w.si, w.co, w.so, __int_as_float(w.kind << 29));
@@ -652,8 +656,8 @@ DEV void block_eval(const WArgs& A, const Call& K, const DevView& V, const DevWo
         d = x.wi;
     }
 }
-DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool store_suffix) {
-    for (int u = n - 1; u >= 0; --u) {
+DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool store_suffix, int rec0 = 0) {
+    for (int u = rec0 + n - 1; u >= rec0; --u) {
         float4* C = cache_rec(S, Q, u, slot);
         const float4 c0 = C[0], c1 = C[1], c2 = C[2];
         float e[12];
@@ -728,6 +732,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                     st12(CK + 2, L);
                     block_fold(S, Q, i, e0 - s0, L, false);
                 }
+                // the suffix at the first vertex, the decision rule's remaining radiance of block 0
+                if (A.hyb_rule) st12(shd_rec(S, i) + 5, L);
             }
             for (int b = HYB ? -1 : B - 1; b >= 0; --b) {
                 float4* C = cache_rec(S, Q, b, i);
@@ -821,13 +827,129 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
     }
 }
 
+// ============================================================================ hybrid replay: decision rule
+// 4x4 inverse by Laplace expansion along the first two rows: returns det m and writes its adjugate
+// (row-major; inverse = adj / det).
+DEV float adjugate4(const float* m, float* adj) {
+    const float a0 = m[0], a1 = m[1], a2 = m[2], a3 = m[3], b0 = m[4], b1 = m[5], b2 = m[6], b3 = m[7];
+    const float c0 = m[8], c1 = m[9], c2 = m[10], c3 = m[11], d0 = m[12], d1 = m[13], d2 = m[14], d3 = m[15];
+    const float s0 = a0 * b1 - a1 * b0, s1 = a0 * b2 - a2 * b0, s2 = a0 * b3 - a3 * b0;
+    const float s3 = a1 * b2 - a2 * b1, s4 = a1 * b3 - a3 * b1, s5 = a2 * b3 - a3 * b2;
+    const float t0 = c0 * d1 - c1 * d0, t1 = c0 * d2 - c2 * d0, t2 = c0 * d3 - c3 * d0;
+    const float t3 = c1 * d2 - c2 * d1, t4 = c1 * d3 - c3 * d1, t5 = c2 * d3 - c3 * d2;
+    adj[0] = b1 * t5 - b2 * t4 + b3 * t3;   adj[1] = -a1 * t5 + a2 * t4 - a3 * t3;
+    adj[2] = d1 * s5 - d2 * s4 + d3 * s3;   adj[3] = -c1 * s5 + c2 * s4 - c3 * s3;
+    adj[4] = -b0 * t5 + b2 * t2 - b3 * t1;  adj[5] = a0 * t5 - a2 * t2 + a3 * t1;
+    adj[6] = -d0 * s5 + d2 * s2 - d3 * s1;  adj[7] = c0 * s5 - c2 * s2 + c3 * s1;
+    adj[8] = b0 * t4 - b1 * t2 + b3 * t0;   adj[9] = -a0 * t4 + a1 * t2 - a3 * t0;
+    adj[10] = d0 * s4 - d1 * s2 + d3 * s0;  adj[11] = -c0 * s4 + c1 * s2 - c3 * s0;
+    adj[12] = -b0 * t3 + b1 * t1 - b2 * t0; adj[13] = a0 * t3 - a1 * t1 + a2 * t0;
+    adj[14] = -d0 * s3 + d1 * s1 - d2 * s0; adj[15] = c0 * s3 - c1 * s1 + c2 * s0;
+    return s0 * t5 - s1 * t4 + s2 * t3 + s3 * t2 - s4 * t1 + s5 * t0;
+}
+
+// Eq. 3 at vertex v0 of the block [s0, e0) (v0 + 1 < e0): adds the vertex's detached weight and
+// emission to the block throughput (Mb, bs) and the remaining radiance, then recovers the suffix
+// L[v0+1] into Ln by the scalar PRB update, the inverse, or recomputation of vertices v0+1 .. e0-1
+// into the scratch records (rec_from = v0 + 1 afterwards).  One decision serves the three channels:
+// their throughputs differ by a scale, which neither test sees.
+template <bool EXT>
+DEV void suffix_by_rule(const WArgs& A, const Call& K, const DevView& V, const DevWorld& W, const Vtx& x, int slot,
+                        uint32_t pix, uint32_t smp, int v0, int s0, int e0, float* Mb, float* bs, float* Lrem,
+                        float* Ln, int& rec_from, uint32_t* n_br) {
+    WC wf;
+    float Ef[12], Enf[12];
+    eval_vertex<false, EXT>(W, K, x, wf, Ef, Enf, nullptr, nullptr);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float se = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) se += Mb[4 * r + j] * (Ef[4 * c + j] + Enf[4 * c + j]);
+            Lrem[4 * c + r] -= bs[c] * se;
+        }
+    if (wf.kind == 2) {
+        WC ws = wf;
+        ws.rgb[0] = 1.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float row[4] = {Mb[4 * r], Mb[4 * r + 1], Mb[4 * r + 2], Mb[4 * r + 3]}, o4[4];
+            w_row(ws, 0, row, o4);
+            Mb[4 * r] = o4[0]; Mb[4 * r + 1] = o4[1]; Mb[4 * r + 2] = o4[2]; Mb[4 * r + 3] = o4[3];
+        }
+    } else {  // diffuse: only the first column survives; no weight: nothing does
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (wf.kind == 0) Mb[4 * r] = 0.0f;
+            Mb[4 * r + 1] = Mb[4 * r + 2] = Mb[4 * r + 3] = 0.0f;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bs[c] *= wf.kind == 0 ? 0.0f : wf.rgb[c];
+    const float m00 = Mb[0];
+    const bool live = m00 > 0.0f && bs[0] > 0.0f && bs[1] > 0.0f && bs[2] > 0.0f;
+    int br = 2;
+    float adj[16], det = 0.0f;
+    if (live) {
+        const float im = 1.0f / m00;
+        float ss = 0.0f, Mn[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) { Mn[k] = Mb[k] * im; ss += Mn[k] * Mn[k]; }
+        const float di = sqrtf(fmaxf(0.0f, ss - 1.0f)) * 0.57735026918962576f;  // (normalised: M00 = 1)
+        if (di < A.hyb_gamma) {
+            br = 0;
+        } else {
+            det = adjugate4(Mn, adj);
+            if (fabsf(det) > A.hyb_eps) br = 1;
+        }
+    }
+    n_br[0] += br == 0 ? 1u : 0u;  // (constant indices: the counters stay in registers)
+    n_br[1] += br == 1 ? 1u : 0u;
+    n_br[2] += br == 2 ? 1u : 0u;
+    if (br == 0) {  // treated as depolarizing: the suffix's intensity only
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Ln[4 * c] = Lrem[4 * c] / (m00 * bs[c]);
+            Ln[4 * c + 1] = Ln[4 * c + 2] = Ln[4 * c + 3] = 0.0f;
+        }
+    } else if (br == 1) {  // beta^-1 Lrem = (Mn^-1 Lrem) / (m00 bs_c)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float f = 1.0f / (det * m00 * bs[c]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Ln[4 * c + r] = f * (adj[4 * r] * Lrem[4 * c] + adj[4 * r + 1] * Lrem[4 * c + 1] +
+                                     adj[4 * r + 2] * Lrem[4 * c + 2] + adj[4 * r + 3] * Lrem[4 * c + 3]);
+        }
+    } else {  // recompute the rest of the block from the ray leaving this vertex
+        const PathState& S = A.S;
+        const int rec0 = v0 + 1 - s0;
+        block_eval<EXT>(A, K, V, W, slot, pix, smp, v0 + 1, e0, spawn(x.p, x.ng, x.wi), x.wi,
+                        is_delta(gval(W.mats, (size_t)x.mat).type), rec0);
+        ld12(ckpt_rec(S, A.Q, s0 / A.ckpt, slot) + 2, Ln);
+        block_fold(S, A.Q, slot, e0 - v0 - 1, Ln, true, rec0);
+        rec_from = v0 + 1;
+    }
+}
+
 // ============================================================================ backward: replay
 // Persistent replay of the queued paths from their hit records (no second traversal): every lane
 // replays one vertex per iteration and takes the next queued path as soon as its own ends, so
 // short and long paths share a wavefront without idling.  At vertex b the lane differentiates
 // E_b + W_b L[b+1] against its adjoint rows, then advances them, a <- a W_b.  Gradients go to
 // workgroup LDS accumulators, flushed at the end.
-template <bool HYB, bool EXT>
+//
+// Hybrid replay (HYB): the suffix beyond a vertex comes from the scratch records of its block.
+// Without RULE the whole block is recomputed from its checkpoint ray when the replay enters it.
+// With RULE (Sec. 4.4, Eq. 3) the lane instead carries the detached block throughput beta (the
+// product of the block's weights so far: a shared 4x4 and RGB scales) and the radiance of the
+// block's checkpoint that its vertices have not yet emitted, Lrem = beta L[b+1], and recovers a
+// suffix by the scalar PRB update (Lrem_0 / beta_00, unpolarized) when the depolarization index
+// of beta is below gamma, by beta^-1 Lrem when |det beta| > eps beta_00^4, and otherwise by
+// recomputing the rest of the block into the scratch records, which the block's later vertices
+// then read.  The block's last suffix is the next checkpoint's.
+template <bool HYB, bool EXT, bool RULE = false>
 __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
@@ -850,6 +972,11 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     v3 o = mk(0.0f, 0.0f, 0.0f), d = o;
 #pragma unroll
     for (int k = 0; k < 12; ++k) av[k] = 0.0f;
+    // decision-rule state (RULE): block throughput (shared part and RGB scales), remaining radiance,
+    // first vertex of the block whose suffix sits in the scratch records, and branch counts
+    float Mb[RULE ? 16 : 1], bs[RULE ? 3 : 1], Lrem[RULE ? 12 : 1];
+    int rec_from = 0;
+    uint32_t n_br[3] = {0u, 0u, 0u};
     while (true) {
         // hand queue entries to the lanes without a path
         const int idx = F.take(slot < 0, n, &S.counts[4]);
@@ -874,18 +1001,25 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             uint32_t hw;
             float hu, hv;
             const float4* C;  // the record whose E words hold the suffix beyond this vertex
+            const int v0 = b - 1;
+            const int s0 = HYB ? v0 - v0 % A.ckpt : 0, e0 = HYB ? min(B, s0 + A.ckpt) : 0;
             if (HYB) {
-                const int v0 = b - 1;
-                if (v0 % A.ckpt == 0) {  // block start: recompute the block's suffix values
-                    const int e0 = min(B, v0 + A.ckpt);
+                if (!RULE && v0 == s0) {  // block start: recompute the block's suffix values
                     block_eval<EXT>(A, K, V, W, slot, pix, smp, v0, e0, o, d, prev_delta);
                     float Lb[12];
                     ld12(ckpt_rec(S, Q, v0 / A.ckpt, slot) + 2, Lb);
                     block_fold(S, Q, slot, e0 - v0, Lb, true);
                 }
+                if (RULE && v0 == s0) {  // block start: beta = I, Lrem = the suffix at the block's first vertex
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) Mb[k] = (k % 5 == 0) ? 1.0f : 0.0f;
+                    bs[0] = bs[1] = bs[2] = 1.0f;
+                    ld12(s0 == 0 ? shd_rec(S, slot) + 5 : ckpt_rec(S, Q, s0 / A.ckpt - 1, slot) + 2, Lrem);
+                    rec_from = 0x7fffffff;
+                }
                 const float4 hr = *hit_rec(S, Q, v0, slot);
                 hw = __float_as_uint(hr.x); hu = hr.y; hv = hr.z;
-                C = cache_rec(S, Q, v0 % A.ckpt, slot);
+                C = cache_rec(S, Q, v0 - s0, slot);
             } else {
                 C = cache_rec(S, Q, b - 1, slot);
                 const float4 c2 = C[2], c3 = C[3];
@@ -902,11 +1036,17 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             vertex_setup<EXT>(W, K, V.view_id, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
             if (x.nee == NEE_PENDING) x.nee = rec_nee;
             float Ln[12];  // L[b+1], stored in this vertex's record by the fold (zero after the last)
-            if (b < B) {
-                ld12(C + 4, Ln);
-            } else {
+            if (b >= B) {
 #pragma unroll
                 for (int q = 0; q < 12; ++q) Ln[q] = 0.0f;
+            } else if (!RULE) {
+                ld12(C + 4, Ln);
+            } else if (v0 + 1 == e0) {  // the block's last suffix: the next checkpoint's
+                ld12(ckpt_rec(S, Q, s0 / A.ckpt, slot) + 2, Ln);
+            } else if (v0 >= rec_from) {  // recomputed earlier in this block
+                ld12(C + 4, Ln);
+            } else {
+                suffix_by_rule<EXT>(A, K, V, W, x, slot, pix, smp, v0, s0, e0, Mb, bs, Lrem, Ln, rec_from, n_br);
             }
             WC w;
             float Ee[12], En[12];
@@ -930,6 +1070,13 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     }
     // flush the workgroup accumulators into the global FP64 accumulator
     __syncthreads();
+    if (RULE && A.hyb_stats) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t t = wave_sum_u(n_br[k]);
+            if (lane_id() == 0 && t) atomicAdd(&A.hyb_stats[k], (unsigned long long)t);
+        }
+    }
     const CallTable* T = A.table;
     for (int s = 0; s < MAX_SLOTS; ++s) {
         int od = T->lds_d[s], of = T->lds_f[s];
@@ -954,6 +1101,7 @@ __global__ void k_setup(CallTable tab, CallTable* dst, Stats* stats, int reset_s
         dst->lds_f[i] = tab.lds_f[i];
     }
     if (i < ST_COUNT && reset_stats) stats->c[i] = 0ull;
+    if (i < 3 && reset_stats) stats->hyb[i] = 0ull;
 }
 __global__ void k_fill_f32(float* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1110,14 +1258,19 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         M(KF_REPLAY, s);
         // the persistent replay grid: as many workgroups per compute unit as this call's
         // accumulator size and the variant's registers allow
-        const void* fn = a.ext ? (a.ckpt > 0 ? (const void*)k_replay<true, true> : (const void*)k_replay<false, true>)
-                               : (a.ckpt > 0 ? (const void*)k_replay<true, false> : (const void*)k_replay<false, false>);
+        const bool rule = a.ckpt > 0 && a.hyb_rule;
+        const void* fn = a.ext ? (rule ? (const void*)k_replay<true, true, true>
+                                       : a.ckpt > 0 ? (const void*)k_replay<true, true> : (const void*)k_replay<false, true>)
+                               : (rule ? (const void*)k_replay<true, false, true>
+                                       : a.ckpt > 0 ? (const void*)k_replay<true, false> : (const void*)k_replay<false, false>);
         const int rg = resident_grid(fn, glds, a.n_chunk, G);
         if (a.ext) {
-            if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+            if (rule) hipLaunchKernelGGL((k_replay<true, true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+            else if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
             else hipLaunchKernelGGL((k_replay<false, true>), dim3(rg), dim3(BLOCK), glds, s, a);
         } else {
-            if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, false>), dim3(rg), dim3(BLOCK), glds, s, a);
+            if (rule) hipLaunchKernelGGL((k_replay<true, false, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+            else if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, false>), dim3(rg), dim3(BLOCK), glds, s, a);
             else hipLaunchKernelGGL((k_replay<false, false>), dim3(rg), dim3(BLOCK), glds, s, a);
         }
     }

@@ -99,7 +99,7 @@ def loss_delta_c1(wl, params=None):
 
 
 def run(wl, params=None, seed=None, d=None, grad_slots=None, with_grads=True, oracle_mode=oracle.MODE_TAPE_AD,
-        device="cuda", plan_kw=None, pixel_grad_slots=(), max_pixels=None):
+        device="cuda", plan_kw=None, pixel_grad_slots=(), max_pixels=None, oracle_kw=None):
     """Render (+ backward) on the GPU and with the oracle on the same seeded inputs.
 
     ``pixel_grad_slots``: slots whose gradient is also compared split by pixel (the gradient
@@ -134,8 +134,10 @@ def run(wl, params=None, seed=None, d=None, grad_slots=None, with_grads=True, or
                                                                      for s in grad_slots]
         want = [i in slots for i in range(len(params))]
         g = plan.backward(tp, seed, torch.from_numpy(d).to(device), want=want)
-        go = osc.run(p64, wl.views, wl.max_depth, seed, flags=wl.flags, mode=oracle_mode,
-                     d_image=d.astype(np.float64), grad_slots=slots, mask=mask)["grads"]
+        ro_g = osc.run(p64, wl.views, wl.max_depth, seed, flags=wl.flags, mode=oracle_mode,
+                       d_image=d.astype(np.float64), grad_slots=slots, mask=mask, **(oracle_kw or {}))
+        go = ro_g["grads"]
+        out["oracle_branches"] = ro_g["hybrid_branches"]
         out["grads_gpu"] = {i: g[i].cpu().numpy().astype(np.float64) for i in slots}
         out["grads_ref"] = {i: go[i] for i in slots}
         out["grad_rel"] = {}

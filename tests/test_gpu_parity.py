@@ -211,3 +211,59 @@ def test_polarizer_stack_tape_ad_parity():
     wl.views = sg.crop_views(wl.views, 636, 356, 6, 5)
     d = _stack_delta(sg.image_numel(wl.views), 87)
     _check(run(wl, d=d, oracle_mode=oracle.MODE_TAPE_AD, plan_kw={"checkpoint_interval": 16}))
+
+
+# the hybrid replay's decision rule (Sec. 4.4, Eq. 3) on the GPU against the oracle's
+def _rule_run(wl, k, gamma, eps, d=None, **kw):
+    res = run(wl, d=d, oracle_mode=oracle.MODE_HYBRID,
+              plan_kw={"checkpoint_interval": k, "hybrid_rule": (gamma, eps)},
+              oracle_kw={"ckpt": k, "hybrid_gamma": gamma, "hybrid_eps": eps}, **kw)
+    res["gpu_branches"] = res["plan"].hybrid_stats()
+    print("branches: gpu", res["gpu_branches"], "oracle", res["oracle_branches"])
+    return res
+
+
+def _same_branches(res, tol=0.02):
+    g, o = res["gpu_branches"], res["oracle_branches"]
+    for key in ("scalar", "invert", "recompute"):
+        assert abs(g[key] - o[key]) <= tol * max(1, sum(o.values())), (key, g, o)
+
+
+def test_hybrid_rule_off_thresholds_recompute_only():
+    # gamma = 0 and eps = inf: every suffix inside a block is recomputed, as without the rule
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+    res = _rule_run(wl, 3, 0.0, float("inf"))
+    _check(res, gate_groups=("albedo_tex", "roughness", "cond_n", "cond_k", "light_Le"))
+    assert res["gpu_branches"]["scalar"] == res["gpu_branches"]["invert"] == 0
+    assert res["gpu_branches"]["recompute"] > 0
+    _same_branches(res, 0.0)
+
+
+def test_hybrid_rule_inversion_on_microfacet_blocks():
+    # GGX-only scene: most suffixes recovered by inverting the block throughput
+    wl = sg.glossy_scene(width=48, height=32, spp=8)
+    res = _rule_run(wl, 4, 0.0, 1e-3)
+    _check(res)
+    assert res["gpu_branches"]["invert"] > 10 * res["gpu_branches"]["recompute"]
+    _same_branches(res)
+
+
+def test_hybrid_rule_scalar_update_on_depolarizing_blocks():
+    # Lambertian floor and wall: every block is an ideal depolarizer, the scalar update is exact
+    wl = sg.polarizer_stack(n_sheets=0, width=64, height=36, spp=4, max_depth=8)
+    res = _rule_run(wl, 4, 0.5, float("inf"))
+    _check(res)
+    assert res["gpu_branches"]["scalar"] > 0 and res["gpu_branches"]["invert"] == 0
+    assert res["gpu_branches"]["recompute"] == 0
+    _same_branches(res, 0.0)
+
+
+def test_hybrid_rule_all_branches_c2_crop():
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+    res = _rule_run(wl, 3, 0.5, 1e-3, pixel_grad_slots=("roughness", "ior"), max_pixels=32)
+    _check(res, gate_groups=("albedo_tex", "roughness", "cond_n", "cond_k", "light_Le"))
+    b = res["gpu_branches"]
+    assert b["scalar"] > 0 and b["invert"] > 0
+    _same_branches(res)
