@@ -84,7 +84,19 @@ typedef struct ppt_plan_opts {
                                    * it amplifies by the condition number of beta. */
     float hybrid_gamma;           /* >= 0; 0 disables the scalar update */
     float hybrid_eps;             /* >= 0 (infinity disables inversion) */
+    int32_t adjoint;              /* PPT_ADJOINT_CACHED (0): the method above.  PPT_ADJOINT_PPRB: the
+                                   * comparator of Sec. 4.2, polarized PRB with noise regularisation:
+                                   * every sampled weight becomes W_b + u_b I with u_b ~ N(0, pprb_sigma)
+                                   * drawn per vertex from the path's counters (Box-Muller of two
+                                   * uniforms of counter call 2), the same in the primal and the
+                                   * adjoint, and the replay recovers each suffix by inverting it.  An
+                                   * unbiased but noisier estimator of the gradient; pprb_sigma = 0
+                                   * inverts rank-deficient weights and gives non-finite gradients.
+                                   * Requires checkpoint_interval = 0. */
+    float pprb_sigma;             /* >= 0, finite */
 } ppt_plan_opts;
+#define PPT_ADJOINT_CACHED 0
+#define PPT_ADJOINT_PPRB 1
 
 typedef struct ppt_scene ppt_scene;
 typedef struct ppt_plan ppt_plan;

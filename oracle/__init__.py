@@ -8,7 +8,8 @@ Modes of :func:`OracleScene.run` (paper Sec. 3.2, 4.1, 4.3, 5.1):
   0 render            Monte Carlo Stokes image (Eq. 2 in Mueller-Stokes calculus)
   1 conventional AD   one stored tape per path with detached sampling ("Conv. AD")
   2 cached replay     per-vertex cache + backward fold + local-AD replay (Sec. 4.3)
-  3 basic P-PRB       suffix recovered by Mueller inversion (Alg. 2), negative control
+  3 basic P-PRB       suffix recovered by Mueller inversion (Alg. 2), negative control; with
+                      pprb_sigma > 0 the noise-regularised P-PRB comparator (Sec. 4.2)
   4 hybrid replay     checkpoints every k vertices and Eq. 3's rule in between (Sec. 4.4)
 """
 from __future__ import annotations
@@ -52,7 +53,8 @@ def lib():
         L.ppto_scene_counts.argtypes = [vp, c_int, vp]
         L.ppto_run.restype = c_int
         L.ppto_run.argtypes = [vp, vp, vp, c_int, vp, c_int, c_int, ctypes.c_uint32, c_u64, c_int,
-                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp, c_int, c_dbl, c_dbl]
+                               vp, vp, vp, vp, vp, vp, c_int, ctypes.c_char_p, c_int, c_int, vp, c_int, c_dbl, c_dbl,
+                               c_dbl]
         L.ppto_philox.argtypes = [c_u64, vp, vp]
         L.ppto_philox_n.argtypes = [c_u64, vp, vp, ctypes.c_int64]
         L.ppto_fresnel.argtypes = [c_dbl, c_dbl, c_dbl, vp, vp]
@@ -111,7 +113,7 @@ class OracleScene:
 
     def run(self, params, views, max_depth, seed, flags=0, mode=MODE_RENDER, d_image=None, params_val=None,
             grad_slots=None, want_image=True, want_sig=False, mask=None, nthreads=0, pixel_grad_slot=None,
-            ckpt=1, hybrid_gamma=0.0, hybrid_eps=float("inf")):
+            ckpt=1, hybrid_gamma=0.0, hybrid_eps=float("inf"), pprb_sigma=0.0):
         """Run the oracle.  ``params`` (and ``params_val``) are per-slot arrays (converted to float64).
 
         Returns a dict with ``image`` (float64, [V][A][h][w][3][4] flattened per view),
@@ -125,6 +127,7 @@ class OracleScene:
         ``hybrid_eps``: the thresholds of its decision rule (Eq. 3): the scalar PRB update where the
         block throughput's depolarization index is below gamma, the inverse where |det| > eps
         beta_00^4, else recomputation (gamma = 0 and eps = inf: recomputation only).
+        ``pprb_sigma``: mode 3's regularisation noise (Sec. 4.2), 0 for the plain inversion.
         """
         from scenegen import VIEW_DTYPE, image_numel  # input-layout helpers only
 
@@ -155,7 +158,7 @@ class OracleScene:
                             None if sig is None else _ptr(sig), None if mk is None else _ptr(mk),
                             _ptr(stats), int(nthreads), err, 256,
                             -1 if pixel_grad_slot is None else int(pixel_grad_slot), None if pg is None else _ptr(pg),
-                            int(ckpt), float(hybrid_gamma), float(hybrid_eps))
+                            int(ckpt), float(hybrid_gamma), float(hybrid_eps), float(pprb_sigma))
         if rc != 0:
             raise ValueError("oracle run failed: " + err.value.decode())
         return {"image": image, "grads": grads, "sig": sig, "n_vertices": int(stats[0]), "n_paths": int(stats[1]),

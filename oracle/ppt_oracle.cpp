@@ -21,8 +21,11 @@
 //               the adjoint replay differentiates each vertex locally against the cached
 //               L[b+1] -- automatic differentiation only inside the loop body (Sec. 3.2);
 //       mode 3  basic polarized PRB (Sec. 4.1, Alg. 2): the suffix is recovered by inverting
-//               the sampled Mueller weight; kept only as the negative control the paper
-//               describes for rank-deficient operators;
+//               the sampled Mueller weight; the negative control the paper describes for
+//               rank-deficient operators, and with sigma > 0 the noise-regularised P-PRB
+//               comparator (Sec. 4.2): every weight becomes W_b + u_b I, u_b ~ N(0, sigma) drawn
+//               per vertex from the path's counters, in the primal fold, the inversion and the
+//               adjoint (an unbiased estimator of the same gradient, with its own variance);
 //       mode 4  hybrid cached replay (Sec. 4.4, Eq. 3) with checkpoint interval k: only the
 //               suffix values at vertices 0, k, 2k, ... are kept.  Inside a block the replay
 //               tracks the detached block throughput beta (the product of the weights since the
@@ -86,6 +89,15 @@ static inline void uniforms(uint64_t seed, uint32_t pix, uint32_t smp, uint32_t 
     uint32_t c[4] = {pix, smp, (view << 8) | (bounce & 0xffu), call}, o[4];
     philox(c, seed, o);
     for (int i = 0; i < 4; ++i) u[i] = u01(o[i]);
+}
+
+// Regularisation noise of the noise-regularised polarized PRB (Sec. 4.2): one normal variate
+// u ~ N(0, sigma) per path vertex (1-based vertex index vtx), from two uniforms of the vertex's counter
+// (call 2) by the Box-Muller transform, so that the primal and the adjoint phase see the same noise.
+static inline double pprb_noise(uint64_t seed, uint32_t pix, uint32_t smp, uint32_t view, uint32_t vtx, double sigma) {
+    double u[4];
+    uniforms(seed, pix, smp, view, vtx, 2, u);
+    return sigma * std::sqrt(-2.0 * std::log(1.0 - u[0])) * std::cos(2.0 * M_PI * u[1]);
 }
 
 // ============================================================================ tape AD
@@ -1124,6 +1136,7 @@ struct RunArgs {
     int mode;
     int ckpt;                 // hybrid replay (mode 4): checkpoint interval k >= 1
     double gamma, eps;        // hybrid replay decision rule (Eq. 3): DI threshold, determinant threshold
+    double sigma;             // mode 3: standard deviation of the regularisation noise u I (Sec. 4.2)
     const double* d_image;
     double* image;
     uint64_t* sig;
@@ -1167,6 +1180,17 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
         // primal: per-vertex W_b, E_b; forward sum and backward fold
         std::vector<VEval<double>> ev(B);
         for (int b = 0; b < B; ++b) eval_vertex(w, g.v[b], PVd, ev[b]);
+        // mode 3 with noise (Sec. 4.2): every weight becomes W_b + u_b I, in the fold, the inversion
+        // and the adjoint alike (the same noise in the primal and the adjoint phase)
+        std::vector<double> nz(B, 0.0);
+        if (A.mode == 3 && A.sigma > 0.0) {
+            const uint32_t pix = (uint32_t)(py * vw.width + px);
+            for (int b = 0; b < B; ++b) {
+                nz[b] = pprb_noise(A.seed, pix, (uint32_t)s, vw.view_id, (uint32_t)(b + 1), A.sigma);
+                for (int c = 0; c < 3; ++c)
+                    for (int i = 0; i < 4; ++i) ev[b].W[c].m[i][i] += nz[b];
+            }
+        }
         M4<double> S[4];
         int na = sensor(vw, g.k_cam, g.x_sensor, PVd, S);
         std::vector<std::array<S4<double>, 3>> L(B + 1);
@@ -1309,11 +1333,13 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
                 tape.backward(adj);
                 collect(PV, adj, acc);
             }
-            // a <- a W_b (detached)
+            // a <- a W_b (detached; with the regularisation noise in mode 3)
             for (int c = 0; c < 3; ++c) {
                 double na_[4] = {};
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j) {
                     for (int i = 0; i < 4; ++i) na_[j] += av[c][i] * e.W[c].m[i][j].v;
+                    if (A.mode == 3) na_[j] += av[c][j] * nz[b];
+                }
                 for (int j = 0; j < 4; ++j) av[c][j] = na_[j];
             }
             Lcur = Lnext;
@@ -1424,7 +1450,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
              const void* views_, int n_views, int max_depth, uint32_t flags, uint64_t seed, int mode,
              const double* d_image, double* image_out, double* const* grads_out, uint64_t* sig_out,
              const uint8_t* path_mask, int64_t* stats, int nthreads, char* err, int errlen, int pix_slot,
-             double* pix_grad, int ckpt_interval, double hybrid_gamma, double hybrid_eps) {
+             double* pix_grad, int ckpt_interval, double hybrid_gamma, double hybrid_eps, double pprb_sigma) {
     Scene* sc = (Scene*)scene;
     const View* views = (const View*)views_;
     if (!sc || n_slots != (int)sc->slot_numel.size()) { set_err(err, errlen, "slot count mismatch"); return -1; }
@@ -1449,7 +1475,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
     }
     g_gauge = (flags & FLAG_GAUGE) ? 1 : 0;
     RunArgs A{sc, params_path, params_val ? params_val : params_path, views, n_views, max_depth, flags, seed, mode,
-              ckpt_interval, hybrid_gamma, hybrid_eps, d_image, image_out, sig_out, path_mask};
+              ckpt_interval, hybrid_gamma, hybrid_eps, pprb_sigma, d_image, image_out, sig_out, path_mask};
     // per-pixel index (view, crop row, crop column) for the gradient-image output
     std::vector<int64_t> pix_off(n_views + 1, 0);
     for (int v = 0; v < n_views; ++v) pix_off[v + 1] = pix_off[v] + (int64_t)views[v].crop_w * views[v].crop_h;

@@ -46,7 +46,8 @@ class PPTError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("chunk_paths", ctypes.c_int64), ("checkpoint_interval", ctypes.c_int64),
-                ("hybrid_rule", ctypes.c_int32), ("hybrid_gamma", ctypes.c_float), ("hybrid_eps", ctypes.c_float)]
+                ("hybrid_rule", ctypes.c_int32), ("hybrid_gamma", ctypes.c_float), ("hybrid_eps", ctypes.c_float),
+                ("adjoint", ctypes.c_int32), ("pprb_sigma", ctypes.c_float)]
 
 
 _lib = None

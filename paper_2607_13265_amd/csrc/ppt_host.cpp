@@ -234,6 +234,8 @@ struct ppt_plan {
     int32_t ckpt = 0;           // hybrid replay checkpoint interval, 0 = cached
     int32_t hyb_rule = 0;       // hybrid replay decision rule (Eq. 3) and its thresholds
     float hyb_gamma = 0.0f, hyb_eps = 0.0f;
+    int32_t adjoint = 0;        // PPT_ADJOINT_*
+    float pprb_sigma = 0.0f;
     mutable KTimer timer[2];  // most recent render / backward call while timing is enabled
 };
 
@@ -649,6 +651,16 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
         P->hyb_gamma = opts->hybrid_gamma;
         P->hyb_eps = opts->hybrid_eps;
     }
+    if (opts && opts->adjoint) {
+        if (opts->adjoint != PPT_ADJOINT_PPRB || P->ckpt != 0 || !(opts->pprb_sigma >= 0.0f) ||
+            !std::isfinite(opts->pprb_sigma)) {
+            delete P;
+            return fail(PPT_EINVAL, "adjoint must be PPT_ADJOINT_CACHED or PPT_ADJOINT_PPRB (without checkpoints, "
+                                    "finite pprb_sigma >= 0)");
+        }
+        P->adjoint = opts->adjoint;
+        P->pprb_sigma = opts->pprb_sigma;
+    }
     int64_t q = opts && opts->chunk_paths > 0 ? opts->chunk_paths : (int64_t)1 << 24;
     q = std::min<int64_t>(q, std::max<int64_t>(path_off, 1));
     q = ((q + WAVE - 1) / WAVE) * WAVE;
@@ -821,6 +833,8 @@ static int backward_impl(const ppt_plan* p, const float* const* params, int32_t 
     a.hyb_gamma = p->hyb_gamma;
     a.hyb_eps = p->hyb_eps;
     a.hyb_stats = a.stats ? ((Stats*)((char*)ws + L.stats))->hyb : nullptr;
+    a.pprb = p->adjoint == PPT_ADJOINT_PPRB;
+    a.pprb_sigma = p->pprb_sigma;
     const LaunchMarker M = op_timer >= 0 ? marker(p, op_timer) : LaunchMarker{nullptr, nullptr};
     if (op_timer >= 0 && p->timing) p->timer[op_timer].begin();
     M(KF_OTHER, s);

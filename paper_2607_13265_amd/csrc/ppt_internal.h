@@ -163,6 +163,8 @@ struct WArgs {
     float hyb_gamma;        // scalar PRB update below this depolarization index
     float hyb_eps;          // inversion above this determinant of the normalised block throughput
     unsigned long long* hyb_stats;  // NULL or 3 counters of the rule's branches
+    int32_t pprb;           // backward by the noise-regularised P-PRB comparator (Sec. 4.2)
+    float pprb_sigma;       // its noise deviation
     int32_t ext;            // the scene uses normal maps, specular maps or circular emitters
     float* out;             // render output
     const float* dout;      // backward: dL/dStokes

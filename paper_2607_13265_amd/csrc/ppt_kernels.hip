@@ -678,6 +678,26 @@ DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool s
     }
 }
 
+// ============================================================================ P-PRB comparator
+// Regularisation noise of the noise-regularised polarized PRB (Sec. 4.2): one normal variate
+// u ~ N(0, sigma) per path vertex (1-based index vtx) from two uniforms of the vertex's counter
+// (call 2) by the Box-Muller transform; the fold and the replay draw the same value.
+DEV float pprb_noise(const WArgs& A, uint32_t pix, uint32_t smp, uint32_t view_id, int vtx) {
+    float u[4];
+    uniforms(A.seed, pix, smp, view_id, (uint32_t)vtx, 2, u);
+    return A.pprb_sigma * sqrtf(-2.0f * logf(1.0f - u[0])) * cosf(6.28318530717958648f * u[1]);
+}
+// W_c of a compact weight as a row-major 4x4 (column j = W_c e_j)
+DEV void w_matrix(const WC& w, int c, float* m) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float e[4] = {j == 0 ? 1.0f : 0.0f, j == 1 ? 1.0f : 0.0f, j == 2 ? 1.0f : 0.0f, j == 3 ? 1.0f : 0.0f}, o[4];
+        w_apply(w, c, e, o);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[4 * r + j] = o[r];
+    }
+}
+
 // ============================================================================ backward: fold
 
 // Per path with at least one vertex: folds the cache into the suffix radiance
@@ -687,7 +707,10 @@ DEV void block_fold(const PathState& S, int Q, int slot, int n, float* L, bool s
 // (into ro/rd) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
 // contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
 // register until the view changes.
-template <bool HYB, bool EXT>
+// PPRB (the noise-regularised comparator of Sec. 4.2): the fold uses W_b + u_b I, keeps the records'
+// E words (the replay inverts the weights instead of reading suffixes) and stores the path's
+// regularised radiance L'[1] in the shadow record's words 5..7.
+template <bool HYB, bool EXT, bool PPRB = false>
 // (six waves per SIMD for the cached fold: its registers then fit without spills, measured faster)
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 6, 8))) k_fold(WArgs A) {
     PathState& S = A.S;
@@ -740,7 +763,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                 const float4 c0 = C[0], c1 = C[1], c2 = C[2];
                 float e[12];
                 ld12(C + 4, e);
-                if (b < B - 1) st12(C + 4, L);
+                if (!PPRB && b < B - 1) st12(C + 4, L);
+                const float u = PPRB ? pprb_noise(A, pix, smp, __float_as_uint(r3.w), b + 1) : 0.0f;
                 WC w;
                 w.rgb[0] = c0.x; w.rgb[1] = c0.y; w.rgb[2] = c0.z;
                 w.A = c0.w; w.B = c1.x; w.C = c1.y; w.D = c1.z;
@@ -751,9 +775,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                     float o4[4];
                     w_apply_select(w, c, L + 4 * c, o4);
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) L[4 * c + k] = e[4 * c + k] + o4[k];
+                    for (int k = 0; k < 4; ++k) L[4 * c + k] = e[4 * c + k] + o4[k] + (PPRB ? u * L[4 * c + k] : 0.0f);
                 }
             }
+            if (PPRB) st12(shd_rec(S, i) + 5, L);
             // pixel of the path from its stored keys (no index arithmetic over the batch)
             const DevView V = gval(A.views, (size_t)v);
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
@@ -949,7 +974,11 @@ DEV void suffix_by_rule(const WArgs& A, const Call& K, const DevView& V, const D
 // of beta is below gamma, by beta^-1 Lrem when |det beta| > eps beta_00^4, and otherwise by
 // recomputing the rest of the block into the scratch records, which the block's later vertices
 // then read.  The block's last suffix is the next checkpoint's.
-template <bool HYB, bool EXT, bool RULE = false>
+//
+// PPRB (the comparator of Sec. 4.2): no cached suffix; the lane carries the regularised radiance
+// L'_b still to be explained and recovers the suffix as (W_b + u_b I)^-1 (L'_b - E_b) from the
+// primal's weight and emission records, advancing its adjoint rows by W_b + u_b I.
+template <bool HYB, bool EXT, bool RULE = false, bool PPRB = false>
 __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     extern __shared__ double lds_grad[];
     PathState& S = A.S;
@@ -975,6 +1004,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     // decision-rule state (RULE): block throughput (shared part and RGB scales), remaining radiance,
     // first vertex of the block whose suffix sits in the scratch records, and branch counts
     float Mb[RULE ? 16 : 1], bs[RULE ? 3 : 1], Lrem[RULE ? 12 : 1];
+    float Lcur[PPRB ? 12 : 1];  // PPRB: the regularised suffix at the current vertex
     int rec_from = 0;
     uint32_t n_br[3] = {0u, 0u, 0u};
     while (true) {
@@ -992,6 +1022,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             pix = __float_as_uint(r3.y);
             smp = __float_as_uint(r3.z);
             ld12(shd_rec(S, slot) + 2, av);
+            if (PPRB) ld12(shd_rec(S, slot) + 5, Lcur);
             ray_od(R, o, d);
         }
         if (!__any(slot >= 0)) break;
@@ -1039,6 +1070,31 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             if (b >= B) {
 #pragma unroll
                 for (int q = 0; q < 12; ++q) Ln[q] = 0.0f;
+            } else if (PPRB) {
+                // (W_b + u I)^-1 (L'_b - E_b) per channel, from the primal's records
+                const float4 c0 = C[0], c1 = C[1], c2 = C[2];
+                WC wr;
+                wr.rgb[0] = c0.x; wr.rgb[1] = c0.y; wr.rgb[2] = c0.z;
+                wr.A = c0.w; wr.B = c1.x; wr.C = c1.y; wr.D = c1.z;
+                wr.ci = c1.w; wr.si = c2.x; wr.co = c2.y; wr.so = c2.z;
+                wr.kind = (__float_as_int(c2.w) >> 29) & 3;
+                float e[12];
+                ld12(C + 4, e);
+                const float u = pprb_noise(A, pix, smp, V.view_id, b);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float m[16], adj[16];
+                    w_matrix(wr, c, m);
+                    m[0] += u; m[5] += u; m[10] += u; m[15] += u;
+                    const float idet = 1.0f / adjugate4(m, adj);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float t = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) t += adj[4 * r + j] * (Lcur[4 * c + j] - e[4 * c + j]);
+                        Ln[4 * c + r] = t * idet;
+                    }
+                }
             } else if (!RULE) {
                 ld12(C + 4, Ln);
             } else if (v0 + 1 == e0) {  // the block's last suffix: the next checkpoint's
@@ -1054,13 +1110,17 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             if (b >= B || x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) {
                 slot = -1;
             } else {
+                const float un = PPRB ? pprb_noise(A, pix, smp, V.view_id, b) : 0.0f;
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
                     float o4[4];
                     w_row(w, cc, av + 4 * cc, o4);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) av[4 * cc + q] = o4[q];
+                    for (int q = 0; q < 4; ++q) av[4 * cc + q] = o4[q] + (PPRB ? un * av[4 * cc + q] : 0.0f);
                 }
+                if (PPRB)
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) Lcur[q] = Ln[q];
                 prev_delta = is_delta(gval(W.mats, (size_t)x.mat).type);
                 o = spawn(x.p, x.ng, x.wi);
                 d = x.wi;
@@ -1250,21 +1310,28 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         // each fold workgroup takes one contiguous slice of the chunk, so the grid is the resident
         // one (a second, partial round of workgroups would leave most of the GPU idle)
         const void* fold_fn = a.ckpt > 0 ? (a.ext ? (const void*)k_fold<true, true> : (const void*)k_fold<true, false>)
-                                         : (const void*)k_fold<false, false>;
+                                         : a.pprb ? (const void*)k_fold<false, false, true> : (const void*)k_fold<false, false>;
         const int fg = resident_grid(fold_fn, 0, a.n_chunk, G);
         if (a.ckpt > 0 && a.ext) hipLaunchKernelGGL((k_fold<true, true>), dim3(fg), dim3(BLOCK), 0, s, a);
         else if (a.ckpt > 0) hipLaunchKernelGGL((k_fold<true, false>), dim3(fg), dim3(BLOCK), 0, s, a);
+        else if (a.pprb) hipLaunchKernelGGL((k_fold<false, false, true>), dim3(fg), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL((k_fold<false, false>), dim3(fg), dim3(BLOCK), 0, s, a);
         M(KF_REPLAY, s);
         // the persistent replay grid: as many workgroups per compute unit as this call's
         // accumulator size and the variant's registers allow
         const bool rule = a.ckpt > 0 && a.hyb_rule;
+        const bool pprb = a.ckpt == 0 && a.pprb;
         const void* fn = a.ext ? (rule ? (const void*)k_replay<true, true, true>
+                                       : pprb ? (const void*)k_replay<false, true, false, true>
                                        : a.ckpt > 0 ? (const void*)k_replay<true, true> : (const void*)k_replay<false, true>)
                                : (rule ? (const void*)k_replay<true, false, true>
+                                       : pprb ? (const void*)k_replay<false, false, false, true>
                                        : a.ckpt > 0 ? (const void*)k_replay<true, false> : (const void*)k_replay<false, false>);
         const int rg = resident_grid(fn, glds, a.n_chunk, G);
-        if (a.ext) {
+        if (pprb) {
+            if (a.ext) hipLaunchKernelGGL((k_replay<false, true, false, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+            else hipLaunchKernelGGL((k_replay<false, false, false, true>), dim3(rg), dim3(BLOCK), glds, s, a);
+        } else if (a.ext) {
             if (rule) hipLaunchKernelGGL((k_replay<true, true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
             else if (a.ckpt > 0) hipLaunchKernelGGL((k_replay<true, true>), dim3(rg), dim3(BLOCK), glds, s, a);
             else hipLaunchKernelGGL((k_replay<false, true>), dim3(rg), dim3(BLOCK), glds, s, a);

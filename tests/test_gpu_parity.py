@@ -267,3 +267,19 @@ def test_hybrid_rule_all_branches_c2_crop():
     b = res["gpu_branches"]
     assert b["scalar"] > 0 and b["invert"] > 0
     _same_branches(res)
+
+
+# the noise-regularised P-PRB comparator (Sec. 4.2) on the GPU against the oracle's
+@pytest.mark.parametrize("sigma", [0.3, 1.0])
+def test_pprb_comparator_parity_c1(sigma):
+    wl = sg.config1()
+    res = run(wl, d=loss_delta_c1(wl), oracle_mode=oracle.MODE_BASIC_PRB, plan_kw={"pprb_sigma": sigma},
+              oracle_kw={"pprb_sigma": sigma})
+    _check(res)
+
+
+def test_pprb_comparator_parity_c2_crop():
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+    res = run(wl, oracle_mode=oracle.MODE_BASIC_PRB, plan_kw={"pprb_sigma": 0.3}, oracle_kw={"pprb_sigma": 0.3})
+    _check(res, gate_groups=("albedo_tex", "light_Le"))
