@@ -92,11 +92,19 @@ typedef struct ppt_plan_opts {
                                    * adjoint, and the replay recovers each suffix by inverting it.  An
                                    * unbiased but noisier estimator of the gradient; pprb_sigma = 0
                                    * inverts rank-deficient weights and gives non-finite gradients.
-                                   * Requires checkpoint_interval = 0. */
+                                   * Requires checkpoint_interval = 0.
+                                   * PPT_ADJOINT_TAPE: the conventional-AD baseline ("Conv. AD", Sec. 5.1,
+                                   * 5.4): the forward pass stores every vertex's loop state (prefix
+                                   * throughput, weight, emission, hit, incoming ray: 240 B per vertex of
+                                   * max_depth per path of the chunk) and a reverse sweep walks each path
+                                   * from its last vertex back, carrying the throughput's adjoint as a
+                                   * full 4x4 matrix per channel.  Same gradient as the cached replay; no
+                                   * normal/specular maps or circular emitters; no checkpoints. */
     float pprb_sigma;             /* >= 0, finite */
 } ppt_plan_opts;
 #define PPT_ADJOINT_CACHED 0
 #define PPT_ADJOINT_PPRB 1
+#define PPT_ADJOINT_TAPE 2
 
 typedef struct ppt_scene ppt_scene;
 typedef struct ppt_plan ppt_plan;
@@ -162,8 +170,8 @@ int64_t ppt_plan_num_paths(const ppt_plan* plan);
 
 /* Device workspace bytes needed by ppt_render (op = 0) or ppt_backward (op = 1): the
  * per-path records of one chunk of paths (for the backward pass including the per-vertex cache
- * of max_depth 128-byte records per path of the chunk), independent of the total number of
- * paths, and the FP64 gradient accumulators. */
+ * of max_depth 128-byte records per path of the chunk, or the tape of the conventional-AD
+ * baseline), independent of the total number of paths, and the FP64 gradient accumulators. */
 size_t ppt_plan_workspace_bytes(const ppt_plan* plan, int32_t op);
 
 /* Optional per-path mask (device, one byte per path, NULL = all paths).  A path whose byte is

@@ -872,6 +872,38 @@ DEV void w_local_grad(const WC& w, const float* a, const float* L, float& gA, fl
         gD += s * (r2 * Lc[3] - ac[3] * l2);
     }
 }
+// The same for a general adjoint W̄_c of every channel's weight (Wbar: 3 row-major 4x4 blocks, the
+// adjoint a conventional reverse sweep carries): gA..gD = sum_c s_c of the entries of
+// G_c = R_out^T Wbar_c R_in^T that multiply A, B, C, D in F.
+DEV void w_local_grad_full(const WC& w, const float* Wbar, float& gA, float& gB, float& gC, float& gD) {
+    gA = gB = gC = gD = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float* M = Wbar + 16 * c;
+        // rows 1, 2 mixed by R_out^T, then columns 1, 2 by R_in^T
+        float T[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            T[j] = M[j];
+            T[4 + j] = w.co * M[4 + j] - w.so * M[8 + j];
+            T[8 + j] = w.so * M[4 + j] + w.co * M[8 + j];
+            T[12 + j] = M[12 + j];
+        }
+        float G[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            G[4 * i] = T[4 * i];
+            G[4 * i + 1] = w.ci * T[4 * i + 1] + w.si * T[4 * i + 2];
+            G[4 * i + 2] = -w.si * T[4 * i + 1] + w.ci * T[4 * i + 2];
+            G[4 * i + 3] = T[4 * i + 3];
+        }
+        const float s = w.rgb[c];
+        gA += s * (G[0] + G[5]);
+        gB += s * (G[1] + G[4]);
+        gC += s * (G[10] + G[15]);
+        gD += s * (G[11] - G[14]);
+    }
+}
 
 // frames of a specular event with incident propagation k_in, incident-side normal n_inc, output k_out
 DEV void spec_frames(v3 k_in, v3 n_inc, v3 k_out, WC& w) {
@@ -965,9 +997,13 @@ DEV v3 spec_frames_grad(v3 k_in, v3 n_inc, v3 k_out, float gci, float gsi, float
 // normal map the shading normal x.ns is differentiated too: every cosine, the GGX D and G
 // terms, the dielectric's Fresnel incidence cosine and its s/p frames.  EXT: the extended
 // material features are compiled in (without them: no circular emission, no maps).
-template <bool GRAD, bool EXT>
+// FULL (conventional reverse sweep, scenes without the light-stage features): Ln is the general
+// adjoint of the weight, 3 row-major 4x4 blocks, instead of the suffix whose outer product with a
+// gives it.
+template <bool GRAD, bool EXT, bool FULL = false>
 DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, float* Eemit, float* Enee, const float* a,
                      const float* Ln) {
+    static_assert(!(FULL && EXT), "the general weight adjoint is not implemented with the light-stage features");
     const DevMaterial m = gval(W.mats, (size_t)x.mat);
     const bool nm = EXT && x.nmap;
 #pragma unroll
@@ -1065,7 +1101,8 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 w.rgb[c] = albedo(K, m, c, x.u, x.v);
-                if (GRAD) {
+                if (GRAD && FULL) gv.rho[c] += Ln[16 * c];
+                if (GRAD && !FULL) {
                     gv.rho[c] += a[4 * c] * Ln[4 * c];
                     jw += a[4 * c] * w.rgb[c] * Ln[4 * c];
                 }
@@ -1087,7 +1124,8 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
             w.A = k * g.a; w.B = k * g.b; w.C = k * g.c; w.D = k * g.d;
             if (GRAD) {
                 float gA, gB, gC, gD;
-                w_local_grad(w, a, Ln, gA, gB, gC, gD);
+                if (FULL) w_local_grad_full(w, Ln, gA, gB, gC, gD);
+                else w_local_grad(w, a, Ln, gA, gB, gC, gD);
                 float jk = ggx_backprop(x, eta, g, s, ks, gA, gB, gC, gD, gv);
                 if (nm && jk != 0.0f) gv.gns = gv.gns + ggx_dln_dns(g, x.wi, x.wo) * jk;
             }
@@ -1117,7 +1155,8 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
             w.A = a0 * ip; w.B = b0 * ip; w.C = c0 * ip; w.D = d0 * ip;
             if (GRAD) {
                 float gA, gB, gC, gD;
-                w_local_grad(w, a, Ln, gA, gB, gC, gD);
+                if (FULL) w_local_grad_full(w, Ln, gA, gB, gC, gD);
+                else w_local_grad(w, a, Ln, gA, gB, gC, gD);
                 cf gm = refl ? fresnel_R_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip)
                              : fresnel_T_vjp(ci, mm, gA * ip, gB * ip, gC * ip, gD * ip);
                 // m = eta (camera outside, reflection) or 1/eta, and the reverse for transmission

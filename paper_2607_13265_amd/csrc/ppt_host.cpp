@@ -483,10 +483,11 @@ static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     L.counts = take(32);
     L.ray = take(RAY_F4 * 16 * Q);
     L.shd = take(SHD_F4 * 16 * Q);
-    L.acc = take(op == 0 ? ACC_F4 * 16 * Q : 0);
+    const bool tape = op == 1 && p->adjoint == PPT_ADJOINT_TAPE;  // (forward accumulator + per-vertex tape)
+    L.acc = take(op == 0 || tape ? ACC_F4 * 16 * Q : 0);
     const bool hybrid = op == 1 && p->ckpt > 0;
     const size_t records = hybrid ? (size_t)std::min(p->ckpt, p->max_depth) : (size_t)p->max_depth;
-    L.cache = take(op == 1 ? records * CACHE_F4 * 16 * Q : 0);
+    L.cache = take(op == 1 ? records * (tape ? TAPE_F4 : CACHE_F4) * 16 * Q : 0);
     L.hits = take(hybrid ? (size_t)p->max_depth * 16 * Q : 0);
     L.ckpt = take(hybrid ? (size_t)((p->max_depth + p->ckpt - 1) / p->ckpt) * CKPT_F4 * 16 * Q : 0);
     L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q); L.hq = take(4 * Q); L.hf = take(Q);
@@ -652,14 +653,20 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
         P->hyb_eps = opts->hybrid_eps;
     }
     if (opts && opts->adjoint) {
-        if (opts->adjoint != PPT_ADJOINT_PPRB || P->ckpt != 0 || !(opts->pprb_sigma >= 0.0f) ||
-            !std::isfinite(opts->pprb_sigma)) {
+        const bool ok_pprb = opts->adjoint == PPT_ADJOINT_PPRB && opts->pprb_sigma >= 0.0f && std::isfinite(opts->pprb_sigma);
+        const bool ok_tape = opts->adjoint == PPT_ADJOINT_TAPE;
+        if (!(ok_pprb || ok_tape) || P->ckpt != 0) {
             delete P;
-            return fail(PPT_EINVAL, "adjoint must be PPT_ADJOINT_CACHED or PPT_ADJOINT_PPRB (without checkpoints, "
-                                    "finite pprb_sigma >= 0)");
+            return fail(PPT_EINVAL, "adjoint must be PPT_ADJOINT_CACHED, PPT_ADJOINT_PPRB (finite pprb_sigma >= 0) or "
+                                    "PPT_ADJOINT_TAPE, the latter two without checkpoints");
+        }
+        if (ok_tape && sc->has_ext) {
+            delete P;
+            return fail(PPT_EUNSUPPORTED, "the tape baseline does not support normal maps, specular maps or "
+                                          "circularly polarized emitters");
         }
         P->adjoint = opts->adjoint;
-        P->pprb_sigma = opts->pprb_sigma;
+        P->pprb_sigma = ok_pprb ? opts->pprb_sigma : 0.0f;
     }
     int64_t q = opts && opts->chunk_paths > 0 ? opts->chunk_paths : (int64_t)1 << 24;
     q = std::min<int64_t>(q, std::max<int64_t>(path_off, 1));
@@ -834,6 +841,7 @@ static int backward_impl(const ppt_plan* p, const float* const* params, int32_t 
     a.hyb_eps = p->hyb_eps;
     a.hyb_stats = a.stats ? ((Stats*)((char*)ws + L.stats))->hyb : nullptr;
     a.pprb = p->adjoint == PPT_ADJOINT_PPRB;
+    a.tape = p->adjoint == PPT_ADJOINT_TAPE;
     a.pprb_sigma = p->pprb_sigma;
     const LaunchMarker M = op_timer >= 0 ? marker(p, op_timer) : LaunchMarker{nullptr, nullptr};
     if (op_timer >= 0 && p->timing) p->timer[op_timer].begin();

@@ -34,7 +34,11 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [0] o.x o.y o.z prev-delta   [1] d.x d.y d.z -   (the ray into the block's first vertex)
 //     [2..4] suffix radiance beyond the block's last vertex (written by the fold);
 //   and k cache records of scratch for the block being re-evaluated.
-constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8, CKPT_F4 = 5;
+//   tape record (conventional-AD baseline), one per (vertex b, slot), TAPE_F4 = 15 vectors (240 B):
+//     [0..7] as the cache record (E_b stays: the reverse sweep reads it)   [8..11] the prefix
+//     throughput beta_b (shared 4x4)   [12] its RGB scales, previous vertex delta   [13..14] the ray into
+//     the vertex (o, d)
+constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8, CKPT_F4 = 5, TAPE_F4 = 15;
 
 enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
                          MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };
@@ -163,6 +167,7 @@ struct WArgs {
     float hyb_gamma;        // scalar PRB update below this depolarization index
     float hyb_eps;          // inversion above this determinant of the normalised block throughput
     unsigned long long* hyb_stats;  // NULL or 3 counters of the rule's branches
+    int32_t tape;           // backward by the conventional-AD baseline (stored tape, reverse sweep)
     int32_t pprb;           // backward by the noise-regularised P-PRB comparator (Sec. 4.2)
     float pprb_sigma;       // its noise deviation
     int32_t ext;            // the scene uses normal maps, specular maps or circular emitters

@@ -178,6 +178,9 @@ DEV float4* cache_rec(const PathState& S, int Q, int b0, int i) {  // b0: 0-base
     return S.cache + ((size_t)b0 * Q + i) * CACHE_F4;
 }
 DEV float4* hit_rec(const PathState& S, int Q, int b0, int i) { return S.hits + ((size_t)b0 * Q + i); }
+DEV float4* tape_rec(const PathState& S, int Q, int b0, int i) {  // (the tape occupies the cache region)
+    return S.cache + ((size_t)b0 * Q + i) * TAPE_F4;
+}
 DEV float4* ckpt_rec(const PathState& S, int Q, int blk, int i) { return S.ckpt + ((size_t)blk * Q + i) * CKPT_F4; }
 DEV float4 f4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
 DEV void ld12(const float4* r, float* v) {
@@ -310,16 +313,26 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                 const bool occ = T.h.prim >= 0;
                 const float4* H = shd_rec(S, slot);
                 if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
-                    float4* dst = SMODE == 0 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+                    // (the tape forward adds it to both the radiance and the vertex's E_b)
+                    float4* dst = SMODE == 0 || SMODE == 3 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
                     if (!occ)
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
                             float4 a = dst[k], p = H[2 + k];
                             dst[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
                         }
+                    if (SMODE == 3 && !occ) {
+                        float4* te = tape_rec(S, Q, (info & 255) - 1, slot) + 4;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            float4 a = te[k], p = H[5 + k];
+                            te[k] = f4(a.x + p.x, a.y + p.y, a.z + p.z, a.w + p.w);
+                        }
+                    }
                 }
                 if (SMODE != 0) {  // record the visibility in the hit word of the vertex whose light sample this is
                     float* hwp = SMODE == 1 ? &cache_rec(S, Q, (info & 255) - 1, slot)[2].w
+                               : SMODE == 3 ? &tape_rec(S, Q, (info & 255) - 1, slot)[2].w
                                             : &hit_rec(S, Q, (info & 255) - 1, slot)->x;
                     uint32_t hw = (uint32_t)__float_as_int(*hwp);
                     hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
@@ -440,7 +453,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                         CK[0] = f4(o.x, o.y, o.z, prev_delta ? 1.0f : 0.0f);
                         CK[1] = f4(d.x, d.y, d.z, 0.0f);
                     }
-                } else if (MODE == 0) {
+                } else if (MODE == 0 || MODE == 3) {
                     float4* AC = acc_rec(S, slot);
                     float beta[16], brgb[3], Lo[12];
                     if (nb == 0) {  // first vertex: beta = I, no radiance yet
@@ -476,6 +489,24 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     }
                     if (shadow) st12(H + 2, pn);
                     st12(AC + 5, Lo);
+                    if (MODE == 3) {
+                        // the tape record of this vertex: weight, hit, emission (its next-event part is
+                        // added when the shadow ray is resolved), the prefix throughput before the
+                        // vertex, and the ray into it
+                        float4* T = tape_rec(S, A.Q, b - 1, slot);
+                        const bool sphere = !x.tri;
+                        T[0] = f4(w.rgb[0], w.rgb[1], w.rgb[2], w.A);
+                        T[1] = f4(w.B, w.C, w.D, w.ci);
+                        T[2] = f4(w.si, w.co, w.so, __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29)));
+                        T[3] = f4(sphere ? h.t : h.u, h.v, 0.0f, 0.0f);
+                        st12(T + 4, Ee);
+                        T[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) T[8 + k] = f4(beta[4 * k], beta[4 * k + 1], beta[4 * k + 2], beta[4 * k + 3]);
+                        T[12] = f4(brgb[0], brgb[1], brgb[2], prev_delta ? 1.0f : 0.0f);
+                        T[13] = f4(o.x, o.y, o.z, d.x);
+                        T[14] = f4(d.y, d.z, 0.0f, 0.0f);
+                    }
                     if (cont) {
                         if (w.kind == 1) {
 #pragma unroll
@@ -508,7 +539,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 if (shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
                     H[1] = f4(sd.x, sd.y, sd.z, 0.0f);
-                    H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (MODE == 3) st12(H + 5, En);  // (the tape's E_b takes the unweighted part)
+                    else H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 float4* Rw = ray_rec(S, slot);
                 if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi);
@@ -710,7 +742,9 @@ DEV void w_matrix(const WC& w, int c, float* m) {
 // PPRB (the noise-regularised comparator of Sec. 4.2): the fold uses W_b + u_b I, keeps the records'
 // E words (the replay inverts the weights instead of reading suffixes) and stores the path's
 // regularised radiance L'[1] in the shadow record's words 5..7.
-template <bool HYB, bool EXT, bool PPRB = false>
+// TAPE (the conventional-AD baseline): no fold; the path's radiance comes from the forward
+// accumulator, for the polarizer-angle term and the adjoint rows.
+template <bool HYB, bool EXT, bool PPRB = false, bool TAPE = false>
 // (six waves per SIMD for the cached fold: its registers then fit without spills, measured faster)
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB ? 1 : 6, 8))) k_fold(WArgs A) {
     PathState& S = A.S;
@@ -758,7 +792,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                 // the suffix at the first vertex, the decision rule's remaining radiance of block 0
                 if (A.hyb_rule) st12(shd_rec(S, i) + 5, L);
             }
-            for (int b = HYB ? -1 : B - 1; b >= 0; --b) {
+            if (TAPE) ld12(acc_rec(S, i) + 5, L);
+            for (int b = HYB || TAPE ? -1 : B - 1; b >= 0; --b) {
                 float4* C = cache_rec(S, Q, b, i);
                 const float4 c0 = C[0], c1 = C[1], c2 = C[2];
                 float e[12];
@@ -849,6 +884,23 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
         float s = wave_sum(mine ? gtheta : 0.0f);
         if (lane_id() == leader) K.g(A.views[key].theta_slot, A.views[key].theta_off, s);
         pending = pending && !mine;
+    }
+}
+
+// ============================================================================ gradient accumulators
+// Adds a workgroup's LDS gradient accumulators into the global FP64 accumulator (every thread calls
+// it after a workgroup barrier).
+DEV void flush_lds_grads(const WArgs& A, const Call& K) {
+    __syncthreads();
+    const CallTable* T = A.table;
+    for (int s = 0; s < MAX_SLOTS; ++s) {
+        int od = T->lds_d[s], of = T->lds_f[s];
+        if (od < 0 && of < 0) continue;
+        int64_t go = T->goff[s], nn = T->numel[s];
+        for (int64_t q = threadIdx.x; q < nn; q += BLOCK) {
+            double val = od >= 0 ? K.lds_d[od + q] : (double)K.lds_f[of + q];
+            if (val != 0.0) unsafeAtomicAdd(A.gacc + go + q, val);
+        }
     }
 }
 
@@ -1137,16 +1189,130 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             if (lane_id() == 0 && t) atomicAdd(&A.hyb_stats[k], (unsigned long long)t);
         }
     }
-    const CallTable* T = A.table;
-    for (int s = 0; s < MAX_SLOTS; ++s) {
-        int od = T->lds_d[s], of = T->lds_f[s];
-        if (od < 0 && of < 0) continue;
-        int64_t go = T->goff[s], nn = T->numel[s];
-        for (int64_t q = threadIdx.x; q < nn; q += BLOCK) {
-            double val = od >= 0 ? K.lds_d[od + q] : (double)K.lds_f[of + q];
-            if (val != 0.0) unsafeAtomicAdd(A.gacc + go + q, val);
+    flush_lds_grads(A, K);
+}
+
+// ============================================================================ tape AD baseline: reverse sweep
+// Conventional reverse-mode AD of the path loop (the "Conv. AD" the paper compares against, Sec. 5.1,
+// 5.4): the forward pass stored every vertex's loop state on the tape (prefix throughput beta_b,
+// weight W_b, emission E_b, hit and incoming ray); this kernel walks each path from its last vertex
+// to its first, carrying the adjoint of the throughput as a full 4x4 matrix per channel, as a
+// generic reverse sweep does (it does not know that the adjoint is an outer product):
+//   Ebar_b = beta_b^T a0,   Wbar_b = beta_b^T betabar_{b+1},   betabar_b = a0 E_b^T + betabar_{b+1} W_b^T,
+// with a0 the adjoint of the path's radiance at the sensor; each vertex's parameter derivatives
+// come from its re-evaluated interaction with (Ebar_b, Wbar_b).  Scenes without the light-stage
+// features only.
+__global__ void __launch_bounds__(BLOCK) k_tape_reverse(WArgs A) {
+    extern __shared__ double lds_grad[];
+    PathState& S = A.S;
+    const int Q = A.Q;
+    Call K{A.table, A.gacc};
+    __shared__ CallTable tab;
+    table_to_lds(&tab, A.table);
+    K.tab = &tab;
+    K.lds_d = lds_grad;
+    K.lds_f = (float*)(lds_grad + A.lds_nd);
+    for (int k = threadIdx.x; k < A.lds_nd; k += BLOCK) K.lds_d[k] = 0.0;
+    for (int k = threadIdx.x; k < A.lds_nf; k += BLOCK) K.lds_f[k] = 0.0f;
+    __syncthreads();
+    const int n = S.counts[3];
+    WaveFetch F(n);
+    int slot = -1, b = 0, v = 0;
+    uint32_t pix = 0, smp = 0;
+    float a0[12], bbar[48];  // adjoint at the sensor; adjoint of beta_{b+1} per channel (4x4, row-major)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a0[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 48; ++k) bbar[k] = 0.0f;
+    while (true) {
+        const int idx = F.take(slot < 0, n, &S.counts[4]);
+        if (idx >= 0) {
+            slot = S.queue0[idx];
+            const float4 r3 = ray_rec(S, slot)[3];
+            const int info = __float_as_int(r3.x);
+            b = info & 255;
+            v = info >> 12;
+            pix = __float_as_uint(r3.y);
+            smp = __float_as_uint(r3.z);
+            ld12(shd_rec(S, slot) + 2, a0);
+#pragma unroll
+            for (int k = 0; k < 48; ++k) bbar[k] = 0.0f;
+        }
+        if (!__any(slot >= 0)) break;
+        if (slot >= 0) {
+            const DevView V = gval(A.views, (size_t)v);
+            const DevWorld W = world_of(A, V);
+            const float4* T = tape_rec(S, Q, b - 1, slot);
+            const float4 t0 = T[0], t1 = T[1], t2 = T[2], t3 = T[3], t12 = T[12], t13 = T[13], t14 = T[14];
+            WC wt;
+            wt.rgb[0] = t0.x; wt.rgb[1] = t0.y; wt.rgb[2] = t0.z;
+            wt.A = t0.w; wt.B = t1.x; wt.C = t1.y; wt.D = t1.z;
+            wt.ci = t1.w; wt.si = t2.x; wt.co = t2.y; wt.so = t2.z;
+            const uint32_t hw = __float_as_uint(t2.w);
+            wt.kind = (int)((hw >> 29) & 3);
+            float E[12], M[16];
+            ld12(T + 4, E);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 q = T[8 + k];
+                M[4 * k] = q.x; M[4 * k + 1] = q.y; M[4 * k + 2] = q.z; M[4 * k + 3] = q.w;
+            }
+            const float brgb[3] = {t12.x, t12.y, t12.z};
+            // Ebar_b = beta_b^T a0 and Wbar_b = beta_b^T betabar_{b+1}, per channel (beta_c = brgb_c M)
+            float Eb[12], Wb[48];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float t = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) t += M[4 * i + j] * a0[4 * c + i];
+                    Eb[4 * c + j] = brgb[c] * t;
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        float u = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) u += M[4 * i + j] * bbar[16 * c + 4 * i + l];
+                        Wb[16 * c + 4 * j + l] = brgb[c] * u;
+                    }
+                }
+            // the interaction again, from the stored ray and hit
+            Hit h;
+            h.prim = (int)(hw & ((1u << 26) - 1));
+            h.u = t3.x; h.t = t3.x; h.v = t3.y;
+            const v3 o = mk(t13.x, t13.y, t13.z), d = mk(t13.w, t14.x, t14.y);
+            Vtx x;
+            surface(W, h, o, d, x);
+            v3 so, sd;
+            float stmax;
+            vertex_setup<false>(W, K, V.view_id, A.seed, pix, smp, b, A.max_depth, A.flags, t12.w != 0.0f, d, x,
+                                so, sd, stmax);
+            if (x.nee == NEE_PENDING) x.nee = (int)((hw >> 26) & 7);
+            WC w;
+            float Ee[12], En[12];
+            eval_vertex<true, false, true>(W, K, x, w, Ee, En, Eb, Wb);
+            // betabar_b = a0 E_b^T + betabar_{b+1} W_b^T (the stored weight)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float Wm[16];
+                w_matrix(wt, c, Wm);
+                float nb_[16];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        float t = a0[4 * c + i] * E[4 * c + j];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) t += bbar[16 * c + 4 * i + k] * Wm[4 * j + k];
+                        nb_[4 * i + j] = t;
+                    }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) bbar[16 * c + k] = nb_[k];
+            }
+            if (--b == 0) slot = -1;
         }
     }
+    flush_lds_grads(A, K);
 }
 
 // ============================================================================ small kernels
@@ -1279,7 +1445,9 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         M(KF_SHADE, s);
         // (a grid sized to each variant's own occupancy measured slower for the render variant)
         const int sg = blocks_for(a.n_chunk, G.shade);
-        if (a.ext) {
+        if (mode == 1 && a.tape) {
+            hipLaunchKernelGGL((k_shade<3, false>), dim3(sg), dim3(BLOCK), 0, s, a);
+        } else if (a.ext) {
             if (mode == 0) hipLaunchKernelGGL((k_shade<0, true>), dim3(sg), dim3(BLOCK), 0, s, a);
             else if (a.ckpt > 0) hipLaunchKernelGGL((k_shade<2, true>), dim3(sg), dim3(BLOCK), 0, s, a);
             else hipLaunchKernelGGL((k_shade<1, true>), dim3(sg), dim3(BLOCK), 0, s, a);
@@ -1295,6 +1463,7 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
             a.first = 0;
             M(KF_EXTEND, s);
             if (mode == 0) hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, a);
+            else if (a.tape) hipLaunchKernelGGL(k_extend<3>, dim3(xg), dim3(BLOCK), lds, s, a);
             else if (a.ckpt > 0) hipLaunchKernelGGL(k_extend<2>, dim3(xg), dim3(BLOCK), lds, s, a);
             else hipLaunchKernelGGL(k_extend<1>, dim3(xg), dim3(BLOCK), lds, s, a);
         }
@@ -1310,15 +1479,22 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         // each fold workgroup takes one contiguous slice of the chunk, so the grid is the resident
         // one (a second, partial round of workgroups would leave most of the GPU idle)
         const void* fold_fn = a.ckpt > 0 ? (a.ext ? (const void*)k_fold<true, true> : (const void*)k_fold<true, false>)
-                                         : a.pprb ? (const void*)k_fold<false, false, true> : (const void*)k_fold<false, false>;
+                              : a.tape ? (const void*)k_fold<false, false, false, true>
+                              : a.pprb ? (const void*)k_fold<false, false, true> : (const void*)k_fold<false, false>;
         const int fg = resident_grid(fold_fn, 0, a.n_chunk, G);
-        if (a.ckpt > 0 && a.ext) hipLaunchKernelGGL((k_fold<true, true>), dim3(fg), dim3(BLOCK), 0, s, a);
+        if (a.tape) hipLaunchKernelGGL((k_fold<false, false, false, true>), dim3(fg), dim3(BLOCK), 0, s, a);
+        else if (a.ckpt > 0 && a.ext) hipLaunchKernelGGL((k_fold<true, true>), dim3(fg), dim3(BLOCK), 0, s, a);
         else if (a.ckpt > 0) hipLaunchKernelGGL((k_fold<true, false>), dim3(fg), dim3(BLOCK), 0, s, a);
         else if (a.pprb) hipLaunchKernelGGL((k_fold<false, false, true>), dim3(fg), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL((k_fold<false, false>), dim3(fg), dim3(BLOCK), 0, s, a);
         M(KF_REPLAY, s);
         // the persistent replay grid: as many workgroups per compute unit as this call's
         // accumulator size and the variant's registers allow
+        if (a.tape) {  // the reverse sweep of the stored tape
+            const int tg = resident_grid((const void*)k_tape_reverse, glds, a.n_chunk, G);
+            hipLaunchKernelGGL(k_tape_reverse, dim3(tg), dim3(BLOCK), glds, s, a);
+            return hipGetLastError();
+        }
         const bool rule = a.ckpt > 0 && a.hyb_rule;
         const bool pprb = a.ckpt == 0 && a.pprb;
         const void* fn = a.ext ? (rule ? (const void*)k_replay<true, true, true>

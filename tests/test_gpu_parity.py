@@ -283,3 +283,38 @@ def test_pprb_comparator_parity_c2_crop():
     wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
     res = run(wl, oracle_mode=oracle.MODE_BASIC_PRB, plan_kw={"pprb_sigma": 0.3}, oracle_kw={"pprb_sigma": 0.3})
     _check(res, gate_groups=("albedo_tex", "light_Le"))
+
+
+# the conventional-AD baseline (stored tape of every vertex's loop state, reverse sweep with full
+# 4x4 adjoints) on the GPU against the oracle's stored-tape AD
+def test_tape_ad_baseline_parity_c1():
+    wl = sg.config1()
+    res = run(wl, d=loss_delta_c1(wl), oracle_mode=oracle.MODE_TAPE_AD, plan_kw={"tape": True})
+    _check(res)
+
+
+def test_tape_ad_baseline_parity_c2_crop():
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+    res = run(wl, oracle_mode=oracle.MODE_TAPE_AD, plan_kw={"tape": True},
+              pixel_grad_slots=("roughness", "ior", "cond_k"), max_pixels=32)
+    _check(res, gate_groups=("albedo_tex", "light_Le"))
+
+
+def test_tape_ad_baseline_equals_cached_replay_and_needs_more_memory():
+    import paper_2607_13265_amd as ppt
+    wl = sg.config3(n_angles=2, n_poses=2)
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = [torch.from_numpy(p).cuda() for p in wl.scene.params()]
+    cached = ppt.Plan(scene, wl.views, wl.max_depth)
+    tape = ppt.Plan(scene, wl.views, wl.max_depth, tape=True)
+    d = torch.randn(cached.image_numel, device="cuda")
+    gc, gt = cached.backward(params, 3, d), tape.backward(params, 3, d)
+    for name, a, b in zip(wl.scene.slot_names, gc, gt):
+        na = float(a.double().norm())
+        assert float((a.double() - b.double()).norm()) <= 1e-4 * max(na, 1e-12), name
+    assert tape.workspace_bytes(1) > 1.8 * cached.workspace_bytes(1)
+    # normal maps and circular emitters are outside the baseline
+    ls = sg.lightstage(res=16, spp=1)
+    with pytest.raises(ppt.PPTError, match="EUNSUPPORTED"):
+        ppt.Plan(ppt.Scene(ls.scene.to_blob()), ls.views, ls.max_depth, tape=True)
