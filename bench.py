@@ -120,8 +120,9 @@ def optimise(args, torch, ppt, sg, dev):
     """Inverse rendering through PolarizedRender: 8 polarizer angles, 512x512, 16 spp, depth 6;
     Adam on the hidden 256x256 albedo and roughness maps and the two lights' RGB intensities,
     with a decorrelated backward seed every step.  Reports the loss curve, the time per step and
-    the peak device memory of the chunked PRB backward next to a stored-record reverse pass that
-    keeps every path's per-vertex records at once."""
+    the peak device memory and time of one backward: PRB in chunks, the cached replay with all paths
+    in one chunk, and the conventional-AD baseline (a stored tape of every vertex's loop state for
+    every path, reverse sweep)."""
     wl = sg.config4(truth=False)
     truth = sg.config4(truth=True)
     scene = ppt.Scene(wl.scene.to_blob())
@@ -164,21 +165,42 @@ def optimise(args, torch, ppt, sg, dev):
             log(f"[optimise] step {it}: loss {losses[-1]:.6e}, {times[-1]:.1f} ms")
     peak_prb = torch.cuda.max_memory_allocated(dev)
     err1 = errors()
-    # one backward with every path's per-vertex records held at once (a stored-record reverse pass)
     n_paths = plan.num_paths
     del opt
     torch.cuda.empty_cache()
-    torch.cuda.reset_peak_memory_stats(dev)
     d = (2.0 / target.numel()) * (plan.render([p.detach() for p in params], 1) - target)
+    want_opt = [n in opt_names for n in names]
+    pd = [p.detach() for p in params]
+
+    def one_backward(pl):
+        """Peak device memory (GB) and time (ms) of one backward of plan pl, and its gradients."""
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats(dev)
+        pl.set_stats(False)
+        pl.backward(pd, 1, d, want=want_opt)  # (allocates the workspace)
+        torch.cuda.synchronize()
+        e0.record()
+        g = pl.backward(pd, 1, d, want=want_opt)
+        e1.record()
+        torch.cuda.synchronize()
+        return torch.cuda.max_memory_allocated(dev), e0.elapsed_time(e1), g
+
+    peak_chunk, ms_chunk, g_chunk = one_backward(plan)
+    # the cached replay with every path's per-vertex records at once (one chunk)
     store = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=((n_paths + 63) // 64) * 64)
-    store.set_stats(False)
     ws_bytes = store.workspace_bytes(1)
-    e0.record()
-    store.backward([p.detach() for p in params], 1, d, want=[n in opt_names for n in names])
-    e1.record()
-    torch.cuda.synchronize()
-    ms_store = e0.elapsed_time(e1)
-    peak_store = torch.cuda.max_memory_allocated(dev)
+    peak_store, ms_store, _ = one_backward(store)
+    del store
+    # the conventional-AD baseline: a tape of every vertex's loop state for every path, reverse sweep
+    tape = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=((n_paths + 63) // 64) * 64, tape=True)
+    tape_ws = tape.workspace_bytes(1)
+    peak_tape, ms_tape, g_tape = one_backward(tape)
+    del tape
+    tape_rel = {n: float((a.double() - b.double()).norm() / max(float(b.double().norm()), 1e-30))
+                for n, a, b in zip(names, g_tape, g_chunk) if a is not None}
+    log(f"[optimise] backward peak GB: PRB chunked {peak_chunk / 1e9:.2f}, one-chunk cached {peak_store / 1e9:.2f}, "
+        f"tape AD {peak_tape / 1e9:.2f}; tape vs PRB gradient rel {tape_rel}")
     res = {
         "metric": "inverse rendering: Adam steps through the autograd wrapper (render + PRB backward)",
         "workload": f"{len(wl.views)} polarizer angles, 512x512, 16 spp, depth {wl.max_depth}, 40.96k triangles, "
@@ -187,10 +209,14 @@ def optimise(args, torch, ppt, sg, dev):
         "ms_per_step_median": float(np.median(times)), "loss_first": losses[0], "loss_last": losses[-1],
         "loss_curve": [round(x, 9) for x in losses],
         "rmse_to_truth_start": err0, "rmse_to_truth_end": err1,
-        "peak_device_memory_gb": {"prb_chunked": round(peak_prb / 1e9, 3),
-                                  "stored_records_all_paths": round(peak_store / 1e9, 3)},
-        "stored_records_workspace_gb": round(ws_bytes / 1e9, 3),
-        "stored_records_backward_ms": round(ms_store, 2),
+        "peak_device_memory_gb": {"optimisation_loop_prb_chunked": round(peak_prb / 1e9, 3),
+                                  "backward_prb_chunked": round(peak_chunk / 1e9, 3),
+                                  "backward_cached_replay_one_chunk": round(peak_store / 1e9, 3),
+                                  "backward_tape_ad": round(peak_tape / 1e9, 3)},
+        "backward_ms": {"prb_chunked": round(ms_chunk, 2), "cached_replay_one_chunk": round(ms_store, 2),
+                        "tape_ad": round(ms_tape, 2)},
+        "workspace_gb": {"cached_replay_one_chunk": round(ws_bytes / 1e9, 3), "tape_ad": round(tape_ws / 1e9, 3)},
+        "tape_ad_grad_rel_diff_vs_prb": tape_rel,
         "prb_workspace_gb": {"render": round(plan.workspace_bytes(0) / 1e9, 3),
                              "backward": round(plan.workspace_bytes(1) / 1e9, 3)},
     }
@@ -202,18 +228,20 @@ def optimise(args, torch, ppt, sg, dev):
 
 
 def depth_sweep(args, torch, ppt, sg, dev):
-    """Render + PRB backward (gradient of the floor albedo) of the 1280x720, 1 spp scene behind 85
+    """Render + backward (gradient of the floor albedo) of the 1280x720, 1 spp scene behind 85
     polarizer sheets for maximum depths 1..128: time, vertices, workspace and peak device memory,
-    with all paths in one chunk and with 128k-path chunks (cached suffix replay), and with all
-    paths in one chunk under the hybrid replay with checkpoints every 16 vertices."""
+    with all paths in one chunk and with 128k-path chunks (cached suffix replay), with all paths in
+    one chunk under the hybrid replay with checkpoints every 16 vertices (recomputation only, and
+    with Eq. 3's decision rule), and for the conventional-AD baseline (stored tape, all paths)."""
     rows = []
     for D in (1, 2, 4, 8, 16, 32, 48, 64, 86, 96, 112, 128):
         wl = sg.polarizer_stack(max_depth=D)
         scene = ppt.Scene(wl.scene.to_blob())
         params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
         want = [n in wl.grad_slots for n in wl.scene.slot_names]
-        for chunk, kc in ((0, 0), (1 << 17, 0), (0, 16)):
-            plan = ppt.Plan(scene, wl.views, D, chunk_paths=chunk or wl.n_paths(), checkpoint_interval=kc)
+        for chunk, kc, extra in ((0, 0, {}), (1 << 17, 0, {}), (0, 16, {}), (0, 16, {"hybrid_rule": (0.5, 1e-3)}),
+                                 (0, 0, {"tape": True})):
+            plan = ppt.Plan(scene, wl.views, D, chunk_paths=chunk or wl.n_paths(), checkpoint_interval=kc, **extra)
             d = torch.from_numpy(np.random.default_rng(D).standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
@@ -234,8 +262,11 @@ def depth_sweep(args, torch, ppt, sg, dev):
                 e2.record()
                 torch.cuda.synchronize()
                 tr.append(e0.elapsed_time(e1)); tb.append(e1.elapsed_time(e2))
+            label = ("tape AD" if extra.get("tape") else
+                     f"hybrid k={kc}" + (" + Eq. 3 rule (gamma 0.5, eps 1e-3)" if extra.get("hybrid_rule") else "")
+                     if kc else "cached")
             rows.append({"max_depth": D, "chunk_paths": plan.launch_info()["chunk_paths"],
-                         "replay": f"hybrid k={kc}" if kc else "cached",
+                         "replay": label,
                          "vertices": st["vertices"], "render_ms": round(float(np.median(tr)), 3),
                          "backward_ms": round(float(np.median(tb)), 3),
                          "workspace_gb": {"render": round(plan.workspace_bytes(0) / 1e9, 4),

@@ -99,12 +99,21 @@ typedef struct ppt_plan_opts {
                                    * max_depth per path of the chunk) and a reverse sweep walks each path
                                    * from its last vertex back, carrying the throughput's adjoint as a
                                    * full 4x4 matrix per channel.  Same gradient as the cached replay; no
-                                   * normal/specular maps or circular emitters; no checkpoints. */
+                                   * normal/specular maps or circular emitters; no checkpoints.
+                                   * PPT_ADJOINT_PRB: the comparator of Sec. 5.1, polarized radiative
+                                   * backpropagation: the replay reads, for each vertex b, an independent
+                                   * estimate of the suffix beyond it, a new path traced from the ray
+                                   * leaving b under the key seed + (b + 1) * 0x9E3779B97F4A7C15 (its
+                                   * vertices keep their numbers b + 1, b + 2, ... in the counters); one
+                                   * sub-path pass per vertex index.  Unbiased, with the variance of that
+                                   * estimate; no light-stage features; no checkpoints; 337 more bytes of
+                                   * workspace per path of the chunk. */
     float pprb_sigma;             /* >= 0, finite */
 } ppt_plan_opts;
 #define PPT_ADJOINT_CACHED 0
 #define PPT_ADJOINT_PPRB 1
 #define PPT_ADJOINT_TAPE 2
+#define PPT_ADJOINT_PRB 3
 
 typedef struct ppt_scene ppt_scene;
 typedef struct ppt_plan ppt_plan;

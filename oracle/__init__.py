@@ -11,6 +11,7 @@ Modes of :func:`OracleScene.run` (paper Sec. 3.2, 4.1, 4.3, 5.1):
   3 basic P-PRB       suffix recovered by Mueller inversion (Alg. 2), negative control; with
                       pprb_sigma > 0 the noise-regularised P-PRB comparator (Sec. 4.2)
   4 hybrid replay     checkpoints every k vertices and Eq. 3's rule in between (Sec. 4.4)
+  5 P-RB              radiative backpropagation: each suffix an independent path estimate (Sec. 5.1)
 """
 from __future__ import annotations
 
@@ -24,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "ppt_oracle.cpp")
 LIB_PATH = os.path.join(_HERE, "libppt_oracle.so")
 
-MODE_RENDER, MODE_TAPE_AD, MODE_CACHED_PRB, MODE_BASIC_PRB, MODE_HYBRID = 0, 1, 2, 3, 4
+MODE_RENDER, MODE_TAPE_AD, MODE_CACHED_PRB, MODE_BASIC_PRB, MODE_HYBRID, MODE_PRB_INDEPENDENT = 0, 1, 2, 3, 4, 5
 FLAG_NO_NEE = 1
 FLAG_GAUGE = 1 << 16
 

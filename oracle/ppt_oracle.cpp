@@ -26,6 +26,10 @@
 //               comparator (Sec. 4.2): every weight becomes W_b + u_b I, u_b ~ N(0, sigma) drawn
 //               per vertex from the path's counters, in the primal fold, the inversion and the
 //               adjoint (an unbiased estimator of the same gradient, with its own variance);
+//       mode 5  polarized radiative backpropagation (P-RB), the other comparator of Sec. 5.1:
+//               the replay's suffix beyond each vertex is an independent estimate, a new path
+//               traced from the ray leaving the vertex under a key of its own (unbiased, with the
+//               variance of that estimate and the cost of one more path per vertex);
 //       mode 4  hybrid cached replay (Sec. 4.4, Eq. 3) with checkpoint interval k: only the
 //               suffix values at vertices 0, k, 2k, ... are kept.  Inside a block the replay
 //               tracks the detached block throughput beta (the product of the weights since the
@@ -99,6 +103,11 @@ static inline double pprb_noise(uint64_t seed, uint32_t pix, uint32_t smp, uint3
     uniforms(seed, pix, smp, view, vtx, 2, u);
     return sigma * std::sqrt(-2.0 * std::log(1.0 - u[0])) * std::cos(2.0 * M_PI * u[1]);
 }
+
+// Key of the independent suffix estimate of polarized radiative backpropagation (P-RB): the sub-path
+// whose first vertex is vertex v_first of the path draws its random numbers from the usual counters
+// under this key instead of the path's own.
+static inline uint64_t prb_seed(uint64_t seed, uint32_t v_first) { return seed + (uint64_t)v_first * 0x9E3779B97F4A7C15ull; }
 
 // ============================================================================ tape AD
 struct Tape {
@@ -725,6 +734,10 @@ struct PathGeom {
     uint64_t sig;
 };
 
+static void trace_from(const World& w, const View& vw, uint32_t pix, int smp, uint64_t seed, int max_depth,
+                       uint32_t flags, const PAcc<double>& P, V3 o, V3 d, int b_start, bool prev_delta, PathGeom& g,
+                       Sig& sig);
+
 // Trace one camera path: RNG counter (pixel, sample, view<<8 | bounce, call).  Sampling
 // decisions read the parameters through P (the "path" parameters).
 static void trace_path(const World& w, const View& vw, int px, int py, int smp, uint64_t seed, int max_depth,
@@ -741,9 +754,18 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
     g.k_cam = -d;
     g.x_sensor = transverse(cam.r, g.k_cam);
     Sig sig;
-    bool prev_delta = false;
+    trace_from(w, vw, pix, smp, seed, max_depth, flags, P, o, d, 1, false, g, sig);
+    g.sig = sig.h;
+}
+
+// The vertices b_start, b_start + 1, ... (1-based vertex numbers, which key the random numbers) of a
+// path entering along the ray (o, d), appended to g.v; prev_delta: the vertex before b_start was a
+// delta vertex (it decides whether an emitter hit at b_start counts).
+static void trace_from(const World& w, const View& vw, uint32_t pix, int smp, uint64_t seed, int max_depth,
+                       uint32_t flags, const PAcc<double>& P, V3 o, V3 d, int b_start, bool prev_delta, PathGeom& g,
+                       Sig& sig) {
     int nt = (int)w.v0.size();
-    for (int b = 1; b <= max_depth; ++b) {
+    for (int b = b_start; b <= max_depth; ++b) {
         Hit h;
         if (!trace(w, o, d, 1e30, false, false, h)) { sig.add(0xffffffffu); break; }
         Vtx x{};
@@ -900,7 +922,6 @@ static void trace_path(const World& w, const View& vw, int px, int py, int smp, 
         o = spawn(x.p, x.ng, x.wi);
         d = x.wi;
     }
-    g.sig = sig.h;
 }
 
 // ============================================================================ differentiated values
@@ -1176,7 +1197,7 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
     const int B = (int)g.v.size();
     std::memset(C, 0, sizeof(double) * 48);
 
-    if (A.mode == 0 || A.mode == 2 || A.mode == 3 || A.mode == 4) {
+    if (A.mode == 0 || A.mode == 2 || A.mode == 3 || A.mode == 4 || A.mode == 5) {
         // primal: per-vertex W_b, E_b; forward sum and backward fold
         std::vector<VEval<double>> ev(B);
         for (int b = 0; b < B; ++b) eval_vertex(w, g.v[b], PVd, ev[b]);
@@ -1254,6 +1275,23 @@ static void run_path(const RunArgs& A, const View& vw, int px, int py, int s, co
             std::array<S4<double>, 3> Lnext;
             if (A.mode == 2) {
                 Lnext = L[b + 1];
+            } else if (A.mode == 5) {
+                // P-RB: an independent estimate of the suffix beyond vertex b, a new path from the ray
+                // leaving it under its own key (the vertices keep their numbers)
+                for (int ch = 0; ch < 3; ++ch) Lnext[ch] = szero<double>();
+                if (b + 1 < B2) {
+                    const Vtx& xb = g2.v[b];
+                    PathGeom gs;
+                    Sig ss;
+                    trace_from(w, vw, (uint32_t)(py * vw.width + px), s, prb_seed(A.seed, (uint32_t)(b + 2)),
+                               A.max_depth, A.flags, PP, spawn(xb.p, xb.ng, xb.wi), xb.wi, b + 2,
+                               is_delta(w.mats[xb.mat].type), gs, ss);
+                    for (int v = (int)gs.v.size() - 1; v >= 0; --v) {
+                        VEval<double> es;
+                        eval_vertex(w, gs.v[v], PVd, es);
+                        for (int ch = 0; ch < 3; ++ch) Lnext[ch] = sadd(es.E[ch], mvec(es.W[ch], Lnext[ch]));
+                    }
+                }
             } else if (A.mode == 4) {
                 const int nb = b + 1;
                 if (b % K == 0) {  // block start: its checkpoint holds the suffix L[s]
@@ -1455,7 +1493,7 @@ int ppto_run(void* scene, const double* const* params_path, const double* const*
     const View* views = (const View*)views_;
     if (!sc || n_slots != (int)sc->slot_numel.size()) { set_err(err, errlen, "slot count mismatch"); return -1; }
     if (max_depth < 1 || max_depth > 200) { set_err(err, errlen, "max_depth out of range"); return -1; }
-    if (mode < 0 || mode > 4 || (mode > 0 && !d_image)) { set_err(err, errlen, "bad mode"); return -1; }
+    if (mode < 0 || mode > 5 || (mode > 0 && !d_image)) { set_err(err, errlen, "bad mode"); return -1; }
     if (mode == 4 && ckpt_interval < 1) { set_err(err, errlen, "checkpoint interval must be >= 1"); return -1; }
     std::vector<int64_t> img_off(n_views + 1, 0), path_off(n_views + 1, 0);
     for (int v = 0; v < n_views; ++v) {

@@ -60,16 +60,17 @@ class Plan:
     checkpoint_interval k > 0 selects the hybrid cached replay for the backward pass; with
     hybrid_rule (a (gamma, eps) pair) it recovers suffixes inside a block by Eq. 3's decision rule.
     pprb_sigma selects the noise-regularised P-PRB comparator for the backward pass (Sec. 4.2), tape
-    the conventional-AD baseline (stored tape of every vertex's loop state, reverse sweep)."""
+    the conventional-AD baseline (stored tape of every vertex's loop state, reverse sweep), prb the P-RB
+    comparator (independent suffix estimates, Sec. 5.1)."""
 
     def __init__(self, scene: Scene, views, max_depth: int, flags: int = 0, chunk_paths: int = 0,
-                 checkpoint_interval: int = 0, hybrid_rule=None, pprb_sigma=None, tape=False):
+                 checkpoint_interval: int = 0, hybrid_rule=None, pprb_sigma=None, tape=False, prb=False):
         self.scene = scene
         self.views = np.ascontiguousarray(views, VIEW_DTYPE)
         self.max_depth = int(max_depth)
         self.flags = int(flags)
         rule = (0, 0.0, 0.0) if hybrid_rule is None else (1, float(hybrid_rule[0]), float(hybrid_rule[1]))
-        adj = (2, 0.0) if tape else (0, 0.0) if pprb_sigma is None else (1, float(pprb_sigma))
+        adj = (2, 0.0) if tape else (3, 0.0) if prb else (0, 0.0) if pprb_sigma is None else (1, float(pprb_sigma))
         opts = PlanOpts(int(chunk_paths), int(checkpoint_interval), *rule, *adj)
         h = ctypes.c_void_p()
         check(lib().ppt_plan_create(scene.handle, self.views.ctypes.data_as(ctypes.c_void_p), len(self.views),

@@ -469,6 +469,7 @@ struct WsLayout {
     size_t table, stats, counts, gacc, total;
     int lds_nd = 0, lds_nf = 0;
     size_t ray, shd, acc, cache, hits, ckpt, q0, q1, sq, hq, hf;
+    size_t ray2, shd2, acc2, q0_2, q1_2, sq2, hq2, hf2, counts2;  // P-RB sub-path state
     int64_t gacc_n;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -491,12 +492,28 @@ static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     L.hits = take(hybrid ? (size_t)p->max_depth * 16 * Q : 0);
     L.ckpt = take(hybrid ? (size_t)((p->max_depth + p->ckpt - 1) / p->ckpt) * CKPT_F4 * 16 * Q : 0);
     L.q0 = take(4 * Q); L.q1 = take(4 * Q); L.sq = take(4 * Q); L.hq = take(4 * Q); L.hf = take(Q);
+    const bool prb = op == 1 && p->adjoint == PPT_ADJOINT_PRB;
+    const size_t Q2 = prb ? Q : 0;
+    L.counts2 = take(prb ? 32 : 0);
+    L.ray2 = take(RAY_F4 * 16 * Q2); L.shd2 = take(SHD_F4 * 16 * Q2); L.acc2 = take(ACC_F4 * 16 * Q2);
+    L.q0_2 = take(4 * Q2); L.q1_2 = take(4 * Q2); L.sq2 = take(4 * Q2); L.hq2 = take(4 * Q2); L.hf2 = take(Q2);
     L.gacc_n = 0;
     if (op == 1)
         for (int64_t n : p->scene->slot_numel) L.gacc_n += n;
     L.gacc = take((size_t)L.gacc_n * 8);
     L.total = at;
     return L;
+}
+static PathState path_state2(void* ws, const WsLayout& L) {
+    char* w = (char*)ws;
+    PathState S{};
+    S.ray = (float4*)(w + L.ray2);
+    S.shd = (float4*)(w + L.shd2);
+    S.acc = (float4*)(w + L.acc2);
+    S.queue0 = (int*)(w + L.q0_2); S.queue1 = (int*)(w + L.q1_2); S.squeue = (int*)(w + L.sq2); S.hqueue = (int*)(w + L.hq2);
+    S.hflag = (uint8_t*)(w + L.hf2);
+    S.counts = (int*)(w + L.counts2);
+    return S;
 }
 static PathState path_state(void* ws, const WsLayout& L) {
     char* w = (char*)ws;
@@ -655,10 +672,16 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
     if (opts && opts->adjoint) {
         const bool ok_pprb = opts->adjoint == PPT_ADJOINT_PPRB && opts->pprb_sigma >= 0.0f && std::isfinite(opts->pprb_sigma);
         const bool ok_tape = opts->adjoint == PPT_ADJOINT_TAPE;
-        if (!(ok_pprb || ok_tape) || P->ckpt != 0) {
+        const bool ok_prb = opts->adjoint == PPT_ADJOINT_PRB;
+        if (!(ok_pprb || ok_tape || ok_prb) || P->ckpt != 0) {
             delete P;
-            return fail(PPT_EINVAL, "adjoint must be PPT_ADJOINT_CACHED, PPT_ADJOINT_PPRB (finite pprb_sigma >= 0) or "
-                                    "PPT_ADJOINT_TAPE, the latter two without checkpoints");
+            return fail(PPT_EINVAL, "adjoint must be PPT_ADJOINT_CACHED, PPT_ADJOINT_PPRB (finite pprb_sigma >= 0), "
+                                    "PPT_ADJOINT_TAPE or PPT_ADJOINT_PRB, the last three without checkpoints");
+        }
+        if (ok_prb && sc->has_ext) {
+            delete P;
+            return fail(PPT_EUNSUPPORTED, "the P-RB comparator does not support normal maps, specular maps or "
+                                          "circularly polarized emitters");
         }
         if (ok_tape && sc->has_ext) {
             delete P;
@@ -842,6 +865,8 @@ static int backward_impl(const ppt_plan* p, const float* const* params, int32_t 
     a.hyb_stats = a.stats ? ((Stats*)((char*)ws + L.stats))->hyb : nullptr;
     a.pprb = p->adjoint == PPT_ADJOINT_PPRB;
     a.tape = p->adjoint == PPT_ADJOINT_TAPE;
+    a.prb = p->adjoint == PPT_ADJOINT_PRB;
+    if (a.prb) a.S2 = path_state2(ws, L);
     a.pprb_sigma = p->pprb_sigma;
     const LaunchMarker M = op_timer >= 0 ? marker(p, op_timer) : LaunchMarker{nullptr, nullptr};
     if (op_timer >= 0 && p->timing) p->timer[op_timer].begin();

@@ -168,6 +168,8 @@ struct WArgs {
     float hyb_eps;          // inversion above this determinant of the normalised block throughput
     unsigned long long* hyb_stats;  // NULL or 3 counters of the rule's branches
     int32_t tape;           // backward by the conventional-AD baseline (stored tape, reverse sweep)
+    int32_t prb;            // backward by the P-RB comparator (independent suffix estimates)
+    PathState S2;           // P-RB: state of the sub-paths
     int32_t pprb;           // backward by the noise-regularised P-PRB comparator (Sec. 4.2)
     float pprb_sigma;       // its noise deviation
     int32_t ext;            // the scene uses normal maps, specular maps or circular emitters

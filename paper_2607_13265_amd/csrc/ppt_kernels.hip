@@ -1192,6 +1192,79 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     flush_lds_grads(A, K);
 }
 
+// ============================================================================ P-RB comparator
+// Polarized radiative backpropagation (the comparator of Sec. 5.1): the replay reads, for each vertex
+// b1, an independent estimate of the suffix beyond it instead of the cached one.  Pass b1 traces,
+// for every path with more than b1 vertices, a new path from the ray leaving vertex b1 (state S2,
+// key prb_seed(seed, b1 + 1), vertex numbers continuing at b1 + 1) through the usual bounce kernels,
+// and stores its radiance over the cached suffix in the vertex's record.
+DEV uint64_t prb_seed(uint64_t seed, uint32_t v_first) { return seed + (uint64_t)v_first * 0x9E3779B97F4A7C15ull; }
+
+// The ray leaving vertex b1 of each path: its prefix is replayed from the camera ray (written by the
+// fold) and the hit records, with the path's own key; the sub-path starts there with an identity
+// throughput and no radiance.  Paths with b1 or fewer vertices start nothing.
+__global__ void __launch_bounds__(BLOCK) k_prb_start(WArgs A, PathState S2, int b1) {
+    const PathState& S = A.S;
+    const int Q = A.Q;
+    Call K{A.table, nullptr};
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
+        const float4* R = ray_rec(S, i);
+        const float4 r3 = R[3];
+        const int info = __float_as_int(r3.x);
+        const int B = (info & INFO_DEAD) ? 0 : (info & 255);
+        const int view = info >> 12;
+        float4* R2 = ray_rec(S2, i);
+        if (B <= b1) {
+            R2[3] = f4(__int_as_float(info_make(b1, false, view) | INFO_DEAD), r3.y, r3.z, r3.w);
+            S2.hflag[i] = 2;
+            continue;
+        }
+        const DevView V = gval(A.views, (size_t)view);
+        const DevWorld W = world_of(A, V);
+        const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
+        v3 o, d;
+        ray_od(R, o, d);
+        bool prev_delta = false;
+        for (int b = 1; b <= b1; ++b) {
+            const float4* C = cache_rec(S, Q, b - 1, i);
+            const float4 c2 = C[2], c3 = C[3];
+            const uint32_t hw = __float_as_uint(c2.w);
+            Hit h;
+            h.prim = (int)(hw & ((1u << 26) - 1));
+            h.u = c3.x; h.t = c3.x; h.v = c3.y;
+            Vtx x;
+            surface(W, h, o, d, x);
+            v3 so, sd;
+            float stmax;
+            vertex_setup<false>(W, K, V.view_id, A.seed, pix, smp, b, A.max_depth, A.flags, prev_delta, d, x, so, sd, stmax);
+            prev_delta = is_delta(gval(W.mats, (size_t)x.mat).type);
+            o = spawn(x.p, x.ng, x.wi);
+            d = x.wi;
+        }
+        ray_set(R2, o, d);
+        R2[2] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+        R2[3] = f4(__int_as_float(info_make(b1, prev_delta, view)), r3.y, r3.z, r3.w);
+        float4* AC = acc_rec(S2, i);
+        AC[0] = f4(1.0f, 0.0f, 0.0f, 0.0f); AC[1] = f4(0.0f, 1.0f, 0.0f, 0.0f);
+        AC[2] = f4(0.0f, 0.0f, 1.0f, 0.0f); AC[3] = f4(0.0f, 0.0f, 0.0f, 1.0f);
+        AC[4] = f4(1.0f, 1.0f, 1.0f, 0.0f);
+        AC[5] = AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+        S2.hflag[i] = 0;
+    }
+}
+// The sub-path radiance of pass b1 over the cached suffix beyond vertex b1.
+__global__ void __launch_bounds__(BLOCK) k_prb_store(WArgs A, PathState S2, int b1) {
+    const PathState& S = A.S;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
+        const int info = __float_as_int(ray_rec(S, i)[3].x);
+        const int B = (info & INFO_DEAD) ? 0 : (info & 255);
+        if (B <= b1) continue;
+        float Lo[12];
+        ld12(acc_rec(S2, i) + 5, Lo);
+        st12(cache_rec(S, A.Q, b1 - 1, i) + 4, Lo);
+    }
+}
+
 // ============================================================================ tape AD baseline: reverse sweep
 // Conventional reverse-mode AD of the path loop (the "Conv. AD" the paper compares against, Sec. 5.1,
 // 5.4): the forward pass stored every vertex's loop state on the tape (prefix throughput beta_b,
@@ -1383,6 +1456,7 @@ hipError_t noalloc_scratch(void** ptr) {
 }
 
 // ============================================================================ launchers
+static uint64_t prb_seed_host(uint64_t seed, uint32_t v_first) { return seed + (uint64_t)v_first * 0x9E3779B97F4A7C15ull; }
 static int blocks_for(int64_t n, int cap) {
     int64_t b = (n + BLOCK - 1) / BLOCK;
     if (b < 1) b = 1;
@@ -1487,6 +1561,41 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         else if (a.ckpt > 0) hipLaunchKernelGGL((k_fold<true, false>), dim3(fg), dim3(BLOCK), 0, s, a);
         else if (a.pprb) hipLaunchKernelGGL((k_fold<false, false, true>), dim3(fg), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL((k_fold<false, false>), dim3(fg), dim3(BLOCK), 0, s, a);
+        if (a.prb) {  // P-RB: independent suffix estimates, one sub-path pass per vertex index
+            WArgs b2 = a;
+            b2.S = a.S2;
+            b2.stats = nullptr;
+            b2.sig = nullptr;
+            b2.mask = nullptr;
+            b2.out = nullptr;
+            for (int b1 = 1; b1 < a.max_depth; ++b1) {
+                M(KF_OTHER, s);
+                hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, s, b2.S.counts);
+                hipLaunchKernelGGL(k_prb_start, dim3(gb), dim3(BLOCK), 0, s, a, a.S2, b1);
+                b2.seed = prb_seed_host(a.seed, (uint32_t)(b1 + 1));
+                b2.qin = 0;
+                b2.first = 1;
+                M(KF_EXTEND, s);
+                hipLaunchKernelGGL(k_extend<-1>, dim3(xg), dim3(BLOCK), lds, s, b2);
+                for (int bb = b1 + 1; bb <= a.max_depth; ++bb) {
+                    const int it = bb - b1;
+                    b2.qin = (it - 1) & 1;
+                    b2.first = it == 1;
+                    M(KF_COMPACT, s);
+                    hipLaunchKernelGGL(k_compact<0>, dim3(gb), dim3(BLOCK), 0, s, b2);
+                    M(KF_SHADE, s);
+                    hipLaunchKernelGGL((k_shade<0, false>), dim3(blocks_for(a.n_chunk, G.shade)), dim3(BLOCK), 0, s, b2);
+                    if (bb < a.max_depth) {
+                        b2.qin = it & 1;
+                        b2.first = 0;
+                        M(KF_EXTEND, s);
+                        hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, b2);
+                    }
+                }
+                M(KF_OTHER, s);
+                hipLaunchKernelGGL(k_prb_store, dim3(gb), dim3(BLOCK), 0, s, a, a.S2, b1);
+            }
+        }
         M(KF_REPLAY, s);
         // the persistent replay grid: as many workgroups per compute unit as this call's
         // accumulator size and the variant's registers allow

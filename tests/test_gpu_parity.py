@@ -318,3 +318,18 @@ def test_tape_ad_baseline_equals_cached_replay_and_needs_more_memory():
     ls = sg.lightstage(res=16, spp=1)
     with pytest.raises(ppt.PPTError, match="EUNSUPPORTED"):
         ppt.Plan(ppt.Scene(ls.scene.to_blob()), ls.views, ls.max_depth, tape=True)
+
+
+# the P-RB comparator (independent suffix estimates, one sub-path pass per vertex index) against the
+# oracle's; the sub-paths draw from their own keys, identically on both sides
+def test_prb_comparator_parity_c1():
+    wl = sg.config1()
+    _check(run(wl, d=loss_delta_c1(wl), oracle_mode=oracle.MODE_PRB_INDEPENDENT, plan_kw={"prb": True}))
+
+
+def test_prb_comparator_parity_c2_crop():
+    wl = sg.config2()
+    wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+    res = run(wl, oracle_mode=oracle.MODE_PRB_INDEPENDENT, plan_kw={"prb": True},
+              pixel_grad_slots=("roughness", "ior"), max_pixels=32)
+    _check(res, gate_groups=("albedo_tex", "light_Le"))
