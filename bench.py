@@ -95,12 +95,15 @@ def parse():
     ap.add_argument("--bounded-chunk", type=int, default=1 << 22,
                     help="chunk size of the memory-bounded measurement (0: skip)")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
-    ap.add_argument("--workload", choices=("batched128", "uneven8", "lightstage", "optimise", "depth_sweep"),
+    ap.add_argument("--workload", choices=("batched128", "uneven8", "lightstage", "optimise", "depth_sweep",
+                                           "comparators"),
                     default="batched128",
                     help="batched128: 128 views of one scene (the headline); uneven8: eight worlds of uneven size; "
                          "lightstage: 8 views with circular lights, four analyzers and normal/specular maps; "
                          "optimise: Adam recovery of textures and lights through the autograd wrapper; "
-                         "depth_sweep: time and memory against the maximum depth behind an 85-sheet polarizer stack")
+                         "depth_sweep: time and memory against the maximum depth behind an 85-sheet polarizer stack; "
+                         "comparators: gradient relative error of every backward method against FP64 conventional AD, "
+                         "and their time and memory")
     ap.add_argument("--opt-steps", type=int, default=200)
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--spp", type=int, default=32)
@@ -285,6 +288,104 @@ def depth_sweep(args, torch, ppt, sg, dev):
             f.write(line + "\n")
 
 
+# the backward methods: the paper's cached suffix replay, its hybrid variant with Eq. 3's rule, and the
+# comparators of its evaluation (Sec. 4.2, 5.1): noise-regularised P-PRB, P-RB and conventional AD
+METHODS = (("ours (cached suffix replay)", {}),
+           ("ours hybrid k=2, Eq. 3 rule (gamma 0.5, eps 1e-3)", {"checkpoint_interval": 2, "hybrid_rule": (0.5, 1e-3)}),
+           ("P-PRB sigma 0.01", {"pprb_sigma": 0.01}),
+           ("P-PRB sigma 0.1", {"pprb_sigma": 0.1}),
+           ("P-PRB sigma 1", {"pprb_sigma": 1.0}),
+           ("P-RB", {"prb": True}),
+           ("conventional AD (GPU tape)", {"tape": True}))
+
+
+def comparators(args, torch, ppt, sg, dev):
+    """Relative error (RE, ||g - g_ref|| / ||g_ref||, the metric of the paper's gradient analysis) of every
+    backward method's gradient per parameter group against the FP64 oracle's conventional AD of the same
+    paths, on the config-1 scene (its L2 loss to a target at 45 degrees) and a config-2 window (random
+    dL/dI); then the time and peak memory of one backward of each method on the 128-view batch and on
+    the 85-sheet stack at depth 128."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import loss_delta_c1
+    tables = []
+    for name, wl, d in (("config 1 (32x32, 4 spp, depth 3, L2 loss)", sg.config1(), None),
+                        ("config 2 window (13x11 of 256x256, 64 spp, depth 8, random dL/dI)", sg.config2(), None)):
+        if wl.name == "c1_tiny":
+            d = loss_delta_c1(wl)
+        else:
+            wl.views = sg.crop_views(wl.views, 96, 112, 13, 11)
+            d = np.random.default_rng(12345).normal(size=sg.image_numel(wl.views)).astype(np.float32)
+        osc = oracle.OracleScene.from_scene(wl.scene)
+        p64 = [p.astype(np.float64) for p in wl.scene.params()]
+        ref = osc.run(p64, wl.views, wl.max_depth, wl.seed, flags=wl.flags, mode=oracle.MODE_TAPE_AD,
+                      d_image=d.astype(np.float64))["grads"]
+        scene = ppt.Scene(wl.scene.to_blob())
+        params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
+        dt = torch.from_numpy(d).to(dev)
+        rows = {}
+        for label, kw in METHODS:
+            plan = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, **kw)
+            g = plan.backward(params, wl.seed, dt)
+            re = {}
+            for i, n in enumerate(wl.scene.slot_names):
+                gg = g[i].double().cpu().numpy()
+                nr = float(np.linalg.norm(ref[i]))
+                if nr > 0:
+                    re[n] = float(np.linalg.norm(gg - ref[i]) / nr) if np.all(np.isfinite(gg)) else float("nan")
+            rows[label] = re
+            log(f"[comparators] {name} / {label}: {re}")
+        tables.append({"scene": name, "reference": "FP64 oracle, conventional AD (stored tape), same paths",
+                       "relative_error": rows})
+    # time and memory of one backward
+    perf = []
+    for name, wl, chunk in (("128 views, 128x128, 32 spp, depth 6", sg.config3(), 1 << 24),
+                            ("85-sheet stack, 1280x720, 1 spp, depth 128", sg.polarizer_stack(max_depth=128), 0)):
+        scene = ppt.Scene(wl.scene.to_blob())
+        params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
+        want = [n in wl.grad_slots for n in wl.scene.slot_names]
+        n_paths = int(wl.n_paths())
+        d = torch.from_numpy(np.random.default_rng(7).standard_normal(sg.image_numel(wl.views), dtype=np.float32)).to(dev)
+        for label, kw in METHODS:
+            if "P-PRB sigma 0.01" in label or "P-PRB sigma 1" == label:
+                continue
+            ck = ((n_paths + 63) // 64) * 64 if kw.get("tape") else (chunk or ((n_paths + 63) // 64) * 64)
+            try:
+                plan = ppt.Plan(scene, wl.views, wl.max_depth, wl.flags, chunk_paths=ck, **kw)
+                plan.set_stats(False)
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+                torch.cuda.reset_peak_memory_stats(dev)
+                base = torch.cuda.memory_allocated(dev)
+                plan.backward(params, wl.seed, d, want=want)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ts = []
+                for _ in range(3):
+                    e0.record()
+                    plan.backward(params, wl.seed, d, want=want)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                row = {"workload": name, "method": label, "chunk_paths": plan.launch_info()["chunk_paths"],
+                       "backward_ms": round(float(np.median(ts)), 3),
+                       "workspace_gb": round(plan.workspace_bytes(1) / 1e9, 3),
+                       "peak_gb": round((torch.cuda.max_memory_allocated(dev) - base) / 1e9, 3)}
+                del plan
+            except Exception as e:  # noqa: BLE001 (reported: e.g. a workspace beyond the device memory)
+                row = {"workload": name, "method": label, "error": str(e)[:200]}
+            torch.cuda.empty_cache()
+            perf.append(row)
+            log(f"[comparators] {row}")
+    res = {"metric": "gradient relative error against conventional AD, and backward time and memory, per method",
+           "tables": tables, "backward_cost": perf}
+    line = json.dumps(res)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -310,6 +411,8 @@ def main():
         return optimise(args, torch, ppt, sg, dev)
     if args.workload == "depth_sweep":
         return depth_sweep(args, torch, ppt, sg, dev)
+    if args.workload == "comparators":
+        return comparators(args, torch, ppt, sg, dev)
     if args.workload == "batched128":
         wl = sg.config3(res=args.res, spp=args.spp)
         desc = (f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), {args.res}x{args.res}, "
