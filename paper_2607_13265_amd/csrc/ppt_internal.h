@@ -17,8 +17,9 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 // kernel writes cache and shadow records whole, unused words included: records written in part
 // measured slower even where whole ones move more bytes.
 //   ray record, RAY_F4 = 4 vectors (64 B):
-//     [0] ro.x ro.y ro.z rd.x   [1] rd.y rd.z t u   [2] v prim Cs Ss   [3] info pix smp view-id
-//     (Cs, Ss: sensor rotation of the camera ray; view-id: the view's sampling identity)
+//     [0] ro.x ro.y ro.z rd.x   [1] rd.y rd.z Cs Ss   [2] t u v prim   [3] info pix smp view-id
+//     (Cs, Ss: sensor rotation of the camera ray; view-id: the view's sampling identity; the hit is
+//     one aligned vector, written by traversal in one 16-byte store)
 //   shadow record, SHD_F4 = 8 vectors (128 B):
 //     [0] so.x so.y so.z tmax   [1] sd.x sd.y sd.z -   [2..4] 12 Stokes words: the pending next-event
 //     contribution (forward passes), then the adjoint rows of the replay (backward)

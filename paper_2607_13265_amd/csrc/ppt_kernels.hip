@@ -197,9 +197,9 @@ DEV void ray_od(const float4* R, v3& o, v3& d) {
     o = mk(a.x, a.y, a.z);
     d = mk(a.w, b.x, b.y);
 }
-DEV void ray_set(float4* R, v3 o, v3 d) {
+DEV void ray_set(float4* R, v3 o, v3 d, float Cs = 0.0f, float Ss = 0.0f) {
     R[0] = f4(o.x, o.y, o.z, d.x);
-    R[1] = f4(d.y, d.z, 0.0f, 0.0f);
+    R[1] = f4(d.y, d.z, Cs, Ss);
 }
 
 constexpr int INFO_DEAD = 1 << 9;
@@ -236,8 +236,8 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
         float Cs, Ss;
         rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
         float4* R = ray_rec(S, i);
-        ray_set(R, o, d);
-        R[2] = f4(0.0f, 0.0f, Cs, Ss);  // the whole record is written
+        ray_set(R, o, d, Cs, Ss);
+        R[2] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // the whole record is written
         S.hflag[i] = live ? 0 : 2;
         R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
                   __uint_as_float(id.smp), __uint_as_float(V.view_id));  // (the view's sampling identity)
@@ -341,8 +341,8 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                 if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
             } else {
                 float4* R = ray_rec(S, slot);
-                ((float2*)(R + 1))[1] = make_float2(T.tb, T.h.u);  // (a hit's distance is the final tb)
-                ((float2*)(R + 2))[0] = make_float2(T.h.v, __int_as_float(T.h.prim));
+                // the hit in one aligned 16-byte store (a hit's distance is the final tb)
+                R[2] = f4(T.tb, T.h.u, T.h.v, __int_as_float(T.h.prim));
                 S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
             }
         }
@@ -414,8 +414,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
             const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
             const DevWorld W = world_of(A, v);
             Hit h;
-            h.prim = __float_as_int(r2.y);
-            h.t = r1.z; h.u = r1.w; h.v = r2.x;
+            h.prim = __float_as_int(r2.w);
+            h.t = r2.x; h.u = r2.y; h.v = r2.z;
             v3 o = mk(r0.x, r0.y, r0.z), d = mk(r0.w, r1.x, r1.y);
             {  // every queued ray hit a surface
                 int b = nb + 1;
@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     else H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 float4* Rw = ray_rec(S, slot);
-                if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi);
+                if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi, r1.z, r1.w);  // (keeps the sensor rotation)
                 Rw[3].x = __int_as_float(info_make(b, is_delta(gval(W.mats, (size_t)x.mat).type), v));
             }
         }
@@ -587,8 +587,8 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             lx = px - V.crop_x0; ly = py - V.crop_y0;
             key = ((int64_t)v << 32) | (int64_t)pix;
             if (!(info & INFO_DEAD) && (info & 255) != 0) {  // a camera ray that escaped has no radiance
-                const float4 r2 = R[2];
-                const float Cs = r2.z, Ss = r2.w;  // sensor rotation of the camera ray
+                const float4 r1 = R[1];
+                const float Cs = r1.z, Ss = r1.w;  // sensor rotation of the camera ray
                 float Lo[12];
                 ld12(acc_rec(S, i) + 5, Lo);
 #pragma unroll
