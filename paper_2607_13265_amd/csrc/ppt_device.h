@@ -82,6 +82,25 @@ DEV uint32_t wave_sum_u(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
 }
+// Sums of N values over the active lanes of the wavefront (act: their mask, taken where the caller
+// runs), returned to every active lane; usable under divergence.  Butterfly over aligned blocks: a
+// lane adds the partial sum of the block next to its own, read from that block's lowest active lane
+// (every active lane of a block holds the block's sum), and nothing for a block without active lanes.
+template <int N>
+DEV void wave_sum_active(float* v, uint64_t act) {
+    const unsigned lane = (unsigned)lane_id();
+#pragma unroll 1
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const unsigned base = (lane ^ (unsigned)d) & ~(unsigned)(d - 1);
+        const uint64_t in = act & (((1ull << d) - 1ull) << base);
+        const int q = in ? __ffsll((long long)in) - 1 : (int)lane;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const float t = __shfl(v[j], q, WAVE);
+            v[j] += in ? t : 0.0f;
+        }
+    }
+}
 // maximum over the wavefront, returned wave-uniform (every lane must be active)
 DEV int wave_max_i(int v) {
 #pragma unroll
@@ -279,12 +298,19 @@ DEV T gval(const T* p, size_t i) {
     return r;
 }
 
+// the four texels of a bilinear lookup (element offsets) and their weights
+struct Bilin { int i[4]; float w[4]; };
+
 struct Call {
     const CallTable* tab;
     double* gacc;
     double* lds_d = nullptr;
     float* lds_f = nullptr;
+    bool coherent = false;  // this lane's vertex is its path's first (texture scatters group such lanes)
     DEV float p(int slot, int idx) const { return gval(tab->p[slot], (size_t)idx); }
+    // Bilinear scatter of CH channels: g[c] w_k to element off + B.i[k] + c of a slot.
+    template <int CH>
+    DEV void gb(int slot, int off, const Bilin& B, const float* g) const;
     DEV void g(int slot, int idx, float v) const {
         if (v == 0.0f) return;
         if (lds_d) {
@@ -321,6 +347,92 @@ struct Call {
     }
 };
 
+// Grouped bilinear scatter into the global accumulator: adds g[c] w_k to texel k, channel c, through
+// add(k, c, value).  Among
+// the lanes that flag themselves coherent (a path's first vertex: the samples of one pixel land in
+// one or two texel cells), lanes whose four texels are the same (key: texel 0's address and the
+// offsets of texels 1 and 3, which fix texel 2 = 0 + 3 - 1) are found group by group from the first
+// pending lane; a group of at least GROUP_MIN lanes has its 4 CH values summed and added by one lane.
+// Every other lane adds its own values.  (Textures in the workgroup accumulators keep per-lane LDS
+// atomics: grouping there measured slower, the replay of the 128-view batch 6.3 -> 7.0 ms.)
+constexpr int GROUP_MIN = 2, GROUP_ROUNDS = 8;
+template <int CH, class Add>
+DEV void bilin_grouped(uint64_t key, const Bilin& B, const float* g, bool coherent, Add add) {
+    const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+    const int d1 = B.i[1] - B.i[0], d3 = B.i[3] - B.i[0];
+    const uint64_t act = __ballot(1);
+    bool pending = coherent, done = false;
+#pragma unroll 1
+    for (int r = 0; r < GROUP_ROUNDS; ++r) {
+        const uint64_t pend = __ballot(pending);
+        if (__popcll(pend) < GROUP_MIN) break;
+        const int lead = __ffsll((long long)pend) - 1;
+        const bool match = pending && klo == (uint32_t)__builtin_amdgcn_readlane((int)klo, lead) &&
+                           khi == (uint32_t)__builtin_amdgcn_readlane((int)khi, lead) &&
+                           d1 == __builtin_amdgcn_readlane(d1, lead) && d3 == __builtin_amdgcn_readlane(d3, lead);
+        pending = pending && !match;
+        if (__popcll(__ballot(match)) < GROUP_MIN) continue;
+        done = done || match;
+        // one channel at a time (four sums in flight keep the register count down)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            float t[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t[k] = match ? g[c] * B.w[k] : 0.0f;
+            wave_sum_active<4>(t, act);
+            if ((int)lane_id() == lead) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (t[k] != 0.0f) add(k, c, t[k]);
+            }
+        }
+    }
+    if (!done) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const float v = g[c] * B.w[k];
+                if (v != 0.0f) add(k, c, v);
+            }
+    }
+}
+template <int CH>
+DEV void Call::gb(int slot, int off, const Bilin& B, const float* g) const {
+    if (lds_d) {
+        int o = tab->lds_d[slot];
+        if (o >= 0) {
+            double* a = lds_d + o + off;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const float v = g[c] * B.w[k];
+                    if (v != 0.0f) atomicAdd(a + B.i[k] + c, (double)v);
+                }
+            return;
+        }
+        o = tab->lds_f[slot];
+        if (o >= 0) {
+            float* a = lds_f + o + off;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const float v = g[c] * B.w[k];
+                    if (v != 0.0f) atomicAdd(a + B.i[k] + c, v);
+                }
+            return;
+        }
+    }
+    const int64_t o = tab->goff[slot];
+    if (o >= 0) {
+        double* a = gacc + o + off;
+        bilin_grouped<CH>((uint64_t)(a + B.i[0]), B, g, coherent,
+                          [&](int k, int c, float v) { unsafeAtomicAdd(a + B.i[k] + c, (double)v); });
+    }
+}
+
 // Per-vertex gradient of the parameters a vertex reads, combined over its next-event and
 // continuation terms before it is scattered (one bilinear scatter per texture).
 struct GradVtx {
@@ -334,7 +446,6 @@ struct GradVtx {
 };
 
 // bilinear, clamp to edge, texel centres at (i + 1/2)/N, layout [th][tw][ch]
-struct Bilin { int i[4]; float w[4]; };
 DEV void bilin(float u, float v, int tw, int th, int ch, Bilin& B) {
     float x = u * (float)tw - 0.5f, y = v * (float)th - 0.5f;
     float x0f = floorf(x), y0f = floorf(y);
@@ -364,10 +475,7 @@ DEV void albedo_scatter(const Call& K, const DevMaterial& m, float u, float v, c
     }
     Bilin B;
     bilin(u, v, m.alb_tw, m.alb_th, 3, B);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) K.g(m.alb_slot, m.alb_off + B.i[k] + c, g[c] * B.w[k]);
+    K.gb<3>(m.alb_slot, m.alb_off, B, g);
 }
 // roughness, clamped to [1e-3, 1]; *inside tells whether the clamp is inactive
 DEV float rough(const Call& K, const DevMaterial& m, float u, float v, bool* inside) {
@@ -390,8 +498,7 @@ DEV void rough_scatter(const Call& K, const DevMaterial& m, float u, float v, fl
     if (m.alpha_tw == 0) { K.g(m.alpha_slot, m.alpha_off, g); return; }
     Bilin B;
     bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) K.g(m.alpha_slot, m.alpha_off + B.i[k], g * B.w[k]);
+    K.gb<1>(m.alpha_slot, m.alpha_off, B, &g);
 }
 // channel c of a constant (tw = 0) or bilinear texture with ch channels, and its scatter
 DEV float tex_read(const Call& K, int slot, int off, int tw, int th, int ch, int c, float u, float v) {
@@ -412,10 +519,7 @@ DEV void tex_scatter(const Call& K, int slot, int off, int tw, int th, float u, 
     }
     Bilin B;
     bilin(u, v, tw, th, CH, B);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int c = 0; c < CH; ++c) K.g(slot, off + B.i[k] + c, g[c] * B.w[k]);
+    K.gb<CH>(slot, off, B, g);
 }
 // specular map: scale of the GGX lobe (1 without a map)
 DEV float spec_scale(const Call& K, const DevMaterial& m, float u, float v) {
@@ -1190,19 +1294,20 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
             break;
     }
     if (GRAD) {
-        // one scatter per parameter the vertex read
-        albedo_scatter(K, m, x.u, x.v, gv.rho);
-        if (m.alpha_slot >= 0) rough_scatter(K, m, x.u, x.v, gv.alpha);
+        // one scatter per parameter the vertex read (the single values first, so that fewer
+        // values stay live across the texture scatters)
         if (m.eta_slot >= 0) K.g(m.eta_slot, m.eta_off, gv.eta);
         if (m.kap_slot >= 0) K.g(m.kap_slot, m.kap_off, gv.kap);
-        if (EXT && m.spec_slot >= 0 && gv.ks != 0.0f)
-            tex_scatter<1>(K, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, x.u, x.v, &gv.ks);
         if (x.nee == NEE_VISIBLE || x.nee == NEE_PENDING) {
             const DevLight L = gval(W.lights, (size_t)x.light);
             for (int c = 0; c < 3; ++c) K.g(L.le_slot, L.le_off + c, gv.le[c]);
         }
         if (m.emit_slot >= 0)
             for (int c = 0; c < 3; ++c) K.g(m.emit_slot, m.emit_off + c, gv.emit[c]);
+        albedo_scatter(K, m, x.u, x.v, gv.rho);
+        if (m.alpha_slot >= 0) rough_scatter(K, m, x.u, x.v, gv.alpha);
+        if (EXT && m.spec_slot >= 0 && gv.ks != 0.0f)
+            tex_scatter<1>(K, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, x.u, x.v, &gv.ks);
         if (nm) {
             // ns = il (t T + b B + n N): d/d(t, b, n) = (T, B, N) . il (I - ns ns^T) g
             v3 tg, bt;

@@ -1093,12 +1093,14 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
                     ld12(ckpt_rec(S, Q, v0 / A.ckpt, slot) + 2, Lb);
                     block_fold(S, Q, slot, e0 - v0, Lb, true);
                 }
-                if (RULE && v0 == s0) {  // block start: beta = I, Lrem = the suffix at the block's first vertex
+                if constexpr (RULE) {
+                    if (v0 == s0) {  // block start: beta = I, Lrem = the suffix at the block's first vertex
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) Mb[k] = (k % 5 == 0) ? 1.0f : 0.0f;
-                    bs[0] = bs[1] = bs[2] = 1.0f;
-                    ld12(s0 == 0 ? shd_rec(S, slot) + 5 : ckpt_rec(S, Q, s0 / A.ckpt - 1, slot) + 2, Lrem);
-                    rec_from = 0x7fffffff;
+                        for (int k = 0; k < 16; ++k) Mb[k] = (k % 5 == 0) ? 1.0f : 0.0f;
+                        bs[0] = bs[1] = bs[2] = 1.0f;
+                        ld12(s0 == 0 ? shd_rec(S, slot) + 5 : ckpt_rec(S, Q, s0 / A.ckpt - 1, slot) + 2, Lrem);
+                        rec_from = 0x7fffffff;
+                    }
                 }
                 const float4 hr = *hit_rec(S, Q, v0, slot);
                 hw = __float_as_uint(hr.x); hu = hr.y; hv = hr.z;
@@ -1158,6 +1160,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             }
             WC w;
             float Ee[12], En[12];
+            K.coherent = b == 1;
             eval_vertex<true, EXT>(W, K, x, w, Ee, En, av, Ln);
             if (b >= B || x.lobe == LOBE_NONE || x.lobe == LOBE_INVALID) {
                 slot = -1;
@@ -1363,6 +1366,7 @@ __global__ void __launch_bounds__(BLOCK) k_tape_reverse(WArgs A) {
             if (x.nee == NEE_PENDING) x.nee = (int)((hw >> 26) & 7);
             WC w;
             float Ee[12], En[12];
+            K.coherent = b == 1;
             eval_vertex<true, false, true>(W, K, x, w, Ee, En, Eb, Wb);
             // betabar_b = a0 E_b^T + betabar_{b+1} W_b^T (the stored weight)
 #pragma unroll
