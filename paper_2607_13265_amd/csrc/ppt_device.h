@@ -587,7 +587,9 @@ DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
     return true;
 }
 
-// Resumable traversal state of one ray (the stack lives in LDS, entry k at stack[k * BLOCK]).
+// Resumable traversal state of one ray.  The stack lives in LDS, entry k at stack[(k + 2) * BLOCK]:
+// two entries of padding below the bottom let the node step read the two top entries and write the
+// next one at fixed offsets from one address (the padding is read and never used).
 constexpr int TRAV_DONE = 0x7fffffff;
 struct Trav {
     v3 o, d, id, ood;
@@ -621,9 +623,10 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
     while (T.ref != TRAV_DONE && T.ref >= 0) {
         ++n_nodes;
         // the two top stack entries, read while the node is in flight (below the bottom of the
-        // stack entry 0 is read and not used)
+        // stack the padding is read and not used)
         const int sp = T.sp;
-        const int top1 = stack[max(sp - 1, 0) * BLOCK], top2 = stack[max(sp - 2, 0) * BLOCK];
+        int* const sb = stack + sp * BLOCK;
+        const int top1 = sb[BLOCK], top2 = sb[0];
         __builtin_amdgcn_sched_barrier(0);
         const float4* nd = T.nodes + 2 * T.ref;
         const float4 q0 = ldg4(nd, 0), q1 = ldg4(nd, 1);
@@ -645,14 +648,17 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         // top of the stack; a leaf is parked (when none is) and the descent goes on past it.  The
         // two pops this can need were read above (pushing and at once popping the farther child
         // of a parked nearer leaf is skipped).
-        const bool goR = hR && (!hL || tnR < tnL);
+        const bool goR = hR & (!hL | (tnR < tnL));  // (bitwise: no branch)
         const int near = goR ? rR : rL, far = goR ? rL : rR;
         const bool both = hL && hR, none = !hL && !hR, free_slot = T.leaf == 0;
         const int pop1 = sp > 0 ? top1 : TRAV_DONE, pop2 = sp > 1 ? top2 : TRAV_DONE;
         const bool park_near = !none && near < 0 && free_slot;
         const bool park_pop = none && pop1 < 0 && free_slot;
         const bool push = both && !park_near;
-        if (push) stack[sp * BLOCK] = far;
+        // written whether or not it is pushed: entry sp is above the top unless this pushes, and it
+        // is in the stack (at an inner node of depth d at most d entries are held, d < BVH depth,
+        // and the capacity is the BVH depth + 2 entries, padding included)
+        sb[2 * BLOCK] = far;
         int ref = park_near ? (both ? far : pop1) : near;
         ref = none ? (park_pop ? pop2 : pop1) : ref;
         T.ref = ref;
@@ -680,7 +686,7 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         T.leaf = 0;
         if (T.ref < 0) {  // the node loop stopped on a second leaf
             T.leaf = T.ref;
-            T.ref = T.sp ? stack[(--T.sp) * BLOCK] : TRAV_DONE;
+            T.ref = T.sp ? stack[(--T.sp + 2) * BLOCK] : TRAV_DONE;
         }
     }
     return T.ref == TRAV_DONE;
