@@ -95,15 +95,18 @@ def parse():
     ap.add_argument("--bounded-chunk", type=int, default=1 << 22,
                     help="chunk size of the memory-bounded measurement (0: skip)")
     ap.add_argument("--timing-steps", type=int, default=3, help="eager steps with per-kernel event timing")
-    ap.add_argument("--workload", choices=("batched128", "uneven8", "lightstage", "optimise", "depth_sweep",
+    ap.add_argument("--workload", choices=("batched128", "config2", "uneven8", "lightstage", "optimise", "depth_sweep",
                                            "comparators"),
                     default="batched128",
-                    help="batched128: 128 views of one scene (the headline); uneven8: eight worlds of uneven size; "
+                    help="batched128: 128 views of one scene (the headline); config2: one 256x256 view at 64 spp, "
+                         "depth 8; uneven8: eight worlds of uneven size; "
                          "lightstage: 8 views with circular lights, four analyzers and normal/specular maps; "
                          "optimise: Adam recovery of textures and lights through the autograd wrapper; "
                          "depth_sweep: time and memory against the maximum depth behind an 85-sheet polarizer stack; "
                          "comparators: gradient relative error of every backward method against FP64 conventional AD, "
                          "and their time and memory")
+    ap.add_argument("--no-deep", action="store_true",
+                    help="skip the deep-path point (85-sheet stack at depth 128) of the headline run")
     ap.add_argument("--opt-steps", type=int, default=200)
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--spp", type=int, default=32)
@@ -418,6 +421,10 @@ def main():
         desc = (f"batched views: {len(wl.views)} views (4 ring poses x 32 polarizer angles), {args.res}x{args.res}, "
                 f"{args.spp} spp, depth {wl.max_depth}, 20.5k-triangle icosphere scene, render + PRB backward, "
                 "HIP-graph replay")
+    elif args.workload == "config2":
+        wl = sg.config2()
+        desc = ("config 2 at full size: one view, 256x256, 64 spp, depth 8, polarizer, 20.5k-triangle icosphere "
+                "scene (GGX dielectric, conductor, textured Lambertian), render + PRB backward, HIP-graph replay")
     elif args.workload == "lightstage":
         wl = sg.lightstage()
         desc = (f"light stage: {len(wl.views)} views on a ring, {int(wl.views[0]['width'])}^2, "
@@ -644,6 +651,11 @@ def main():
                           "kernels": {KERNEL_SYMBOL[f]: v for f, v in fams.items()},
                           "counters": {"render": st_r, "backward": st_b}}
 
+    # deep paths: the same step on the 85-sheet stack at depth 128 (a throughput point beside the
+    # shallow headline, whose paths average under one vertex)
+    if args.workload == "batched128" and not args.no_deep:
+        result["deep_stack"] = deep_stack(torch, ppt, sg, dev)
+
     # CPU baseline and accuracy of the timed configuration: the FP64 oracle (render + cached-suffix
     # replay) on a bounded sample of the workload, whose image and gradients are also the reference
     # for the timed plan's output on the same paths
@@ -655,6 +667,39 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(line + "\n")
+
+
+def deep_stack(torch, ppt, sg, dev, depth=128, steps=3):
+    """Render + cached-suffix-replay backward (gradient of the floor albedo) of the 1280x720, 1 spp
+    scene behind 85 polarizer sheets at maximum depth 128, all paths in one chunk: throughput in path
+    vertices per second, time per step and backward workspace."""
+    wl = sg.polarizer_stack(max_depth=depth)
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = [torch.from_numpy(p).to(dev) for p in wl.scene.params()]
+    want = [n in wl.grad_slots for n in wl.scene.slot_names]
+    plan = ppt.Plan(scene, wl.views, depth, chunk_paths=wl.n_paths())
+    d = torch.from_numpy(np.random.default_rng(depth).standard_normal(plan.image_numel, dtype=np.float32)).to(dev)
+    ws_r, ws_b = plan.workspace(0), plan.workspace(1)
+    grads = [torch.empty_like(p) if w else None for p, w in zip(params, want)]
+    plan.render(params, wl.seed, ws=ws_r)
+    plan.backward(params, wl.seed, d, grads=grads, ws=ws_b)
+    torch.cuda.synchronize()
+    verts = plan.stats(0)["vertices"]
+    plan.set_stats(False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.render(params, wl.seed, ws=ws_r)
+        plan.backward(params, wl.seed, d, grads=grads, ws=ws_b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": "1280x720, 1 spp, 85 polarizer sheets, depth 128, floor-albedo gradient, cached suffix replay, "
+                       "one chunk", "vertices_per_step": verts, "paths_per_step": wl.n_paths(),
+           "value": round(verts / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-vertices/s", "ms_per_step": round(ms, 3),
+           "backward_workspace_gb": round(plan.workspace_bytes(1) / 1e9, 3)}
+    log(f"[bench] deep stack: {res}")
+    return res
 
 
 def cpu_model() -> str:
