@@ -29,7 +29,10 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [0] rgb0 rgb1 rgb2 A   [1] B C D Cin   [2] Sin Cout Sout hitword   [3] u-or-t v - -
 //     [4..6] E_b (12 words), overwritten by the fold with the suffix radiance beyond the vertex,
 //     L[b+1], which is what the replay of vertex b reads (not stored for a path's last vertex)
-//   hitword = prim | next-event state << 26 | weight kind << 29
+//     [7] x: the next-event visibility written by the shadow-ray traversal (in the sector of E_b's
+//     last words, which that traversal updates anyway)
+//   hitword = prim | next-event state << 26 | weight kind << 29 (the state as sampled: pending for a
+//   light sample; its visibility goes to [7])
 //   hybrid replay (checkpoint interval k): per vertex a hit record [hitword, u-or-t, v, -] (16 B);
 //   per block of k vertices a checkpoint record, CKPT_F4 = 5 vectors (80 B):
 //     [0] o.x o.y o.z prev-delta   [1] d.x d.y d.z -   (the ray into the block's first vertex)

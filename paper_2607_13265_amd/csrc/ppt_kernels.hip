@@ -330,9 +330,13 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                         }
                     }
                 }
-                if (SMODE != 0) {  // record the visibility in the hit word of the vertex whose light sample this is
-                    float* hwp = SMODE == 1 ? &cache_rec(S, Q, (info & 255) - 1, slot)[2].w
-                               : SMODE == 3 ? &tape_rec(S, Q, (info & 255) - 1, slot)[2].w
+                if (SMODE == 1) {
+                    // the visibility in the record's last vector, which shares its 32-byte sector with
+                    // the E words written above (the hit word's sector is not touched)
+                    cache_rec(S, Q, (info & 255) - 1, slot)[7] =
+                        f4(__int_as_float(occ ? NEE_OCCLUDED : NEE_VISIBLE), 0.0f, 0.0f, 0.0f);
+                } else if (SMODE != 0) {  // in the hit word of the vertex whose light sample this is
+                    float* hwp = SMODE == 3 ? &tape_rec(S, Q, (info & 255) - 1, slot)[2].w
                                             : &hit_rec(S, Q, (info & 255) - 1, slot)->x;
                     uint32_t hw = (uint32_t)__float_as_int(*hwp);
                     hw = (hw & ~(7u << 26)) | ((uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE) << 26);
@@ -1112,7 +1116,9 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             }
             Hit h;
             h.prim = (int)(hw & ((1u << 26) - 1));
-            int rec_nee = (int)((hw >> 26) & 7);
+            // the next-event visibility: in the hit record's word (hybrid), in the cache record's
+            // last vector (cached)
+            const int rec_nee = HYB ? (int)((hw >> 26) & 7) : __float_as_int(C[7].x);
             h.u = hu; h.t = hu; h.v = hv;
             Vtx x;
             surface(W, h, o, d, x);
