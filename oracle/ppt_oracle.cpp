@@ -1432,7 +1432,12 @@ static void set_err(char* err, int n, const char* msg) {
 
 struct Reader {
     const uint8_t* p; size_t n, at = 0;
-    bool get(void* dst, size_t k) { if (at + k > n) return false; std::memcpy(dst, p + at, k); at += k; return true; }
+    bool get(void* dst, size_t k) {
+        if (at + k > n) return false;
+        if (k) std::memcpy(dst, p + at, k);  // (an empty array may have no storage: no copy at all)
+        at += k;
+        return true;
+    }
 };
 
 extern "C" {
