@@ -458,14 +458,39 @@ DEV void bilin(float u, float v, int tw, int th, int ch, Bilin& B) {
     B.i[2] = (yb * tw + xa) * ch; B.w[2] = (1.0f - fx) * fy;
     B.i[3] = (yb * tw + xb) * ch; B.w[3] = fx * fy;
 }
-DEV float albedo(const Call& K, const DevMaterial& m, int c, float u, float v) {
-    if (m.alb_tw == 0) return K.p(m.alb_slot, m.alb_off + c);
-    Bilin B;
-    bilin(u, v, m.alb_tw, m.alb_th, 3, B);
-    float r = 0.0f;
+// The CH channels of the four texels of a bilinear lookup: every load is issued before any is used
+// (one round trip; left to itself the register allocator chained them, one texel at a time), then
+// out[c] = sum_k w_k t_kc in tap order.
+template <int CH>
+DEV void bilin_fetch(const Call& K, int slot, int off, const Bilin& B, float* out) {
+    float t[4 * CH];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) r += K.p(m.alb_slot, m.alb_off + B.i[k] + c) * B.w[k];
-    return r;
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) t[CH * k + c] = K.p(slot, off + B.i[k] + c);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        float r = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r += t[CH * k + c] * B.w[k];
+        out[c] = r;
+    }
+}
+// the CH channels of a constant (tw = 0) or bilinear texture
+template <int CH>
+DEV void tex_read(const Call& K, int slot, int off, int tw, int th, float u, float v, float* out) {
+    if (tw == 0) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) out[c] = K.p(slot, off + c);
+        return;
+    }
+    Bilin B;
+    bilin(u, v, tw, th, CH, B);
+    bilin_fetch<CH>(K, slot, off, B, out);
+}
+DEV void albedo3(const Call& K, const DevMaterial& m, float u, float v, float* rho) {
+    tex_read<3>(K, m.alb_slot, m.alb_off, m.alb_tw, m.alb_th, u, v, rho);
 }
 DEV void albedo_scatter(const Call& K, const DevMaterial& m, float u, float v, const float* g) {
     if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) return;
@@ -480,15 +505,7 @@ DEV void albedo_scatter(const Call& K, const DevMaterial& m, float u, float v, c
 // roughness, clamped to [1e-3, 1]; *inside tells whether the clamp is inactive
 DEV float rough(const Call& K, const DevMaterial& m, float u, float v, bool* inside) {
     float a;
-    if (m.alpha_tw == 0) {
-        a = K.p(m.alpha_slot, m.alpha_off);
-    } else {
-        Bilin B;
-        bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
-        a = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a += K.p(m.alpha_slot, m.alpha_off + B.i[k]) * B.w[k];
-    }
+    tex_read<1>(K, m.alpha_slot, m.alpha_off, m.alpha_tw, m.alpha_th, u, v, &a);
     bool in = a >= 1e-3f && a <= 1.0f;
     if (inside) *inside = in;
     return fminf(fmaxf(a, 1e-3f), 1.0f);
@@ -500,16 +517,7 @@ DEV void rough_scatter(const Call& K, const DevMaterial& m, float u, float v, fl
     bilin(u, v, m.alpha_tw, m.alpha_th, 1, B);
     K.gb<1>(m.alpha_slot, m.alpha_off, B, &g);
 }
-// channel c of a constant (tw = 0) or bilinear texture with ch channels, and its scatter
-DEV float tex_read(const Call& K, int slot, int off, int tw, int th, int ch, int c, float u, float v) {
-    if (tw == 0) return K.p(slot, off + c);
-    Bilin B;
-    bilin(u, v, tw, th, ch, B);
-    float r = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r += K.p(slot, off + B.i[k] + c) * B.w[k];
-    return r;
-}
+// the scatter of a constant or bilinear texture's gradient
 template <int CH>
 DEV void tex_scatter(const Call& K, int slot, int off, int tw, int th, float u, float v, const float* g) {
     if (tw == 0) {
@@ -523,7 +531,10 @@ DEV void tex_scatter(const Call& K, int slot, int off, int tw, int th, float u, 
 }
 // specular map: scale of the GGX lobe (1 without a map)
 DEV float spec_scale(const Call& K, const DevMaterial& m, float u, float v) {
-    return m.spec_slot < 0 ? 1.0f : tex_read(K, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, 1, 0, u, v);
+    if (m.spec_slot < 0) return 1.0f;
+    float k;
+    tex_read<1>(K, m.spec_slot, m.spec_off, m.spec_tw, m.spec_th, u, v, &k);
+    return k;
 }
 DEV cf ior(const Call& K, const DevMaterial& m) {
     return cf{K.p(m.eta_slot, m.eta_off), m.kap_slot >= 0 ? K.p(m.kap_slot, m.kap_off) : 0.0f};
@@ -774,8 +785,7 @@ DEV void tangent_frame(const DevWorld& W, const Vtx& x, v3& tg, v3& bt) {
 DEV v3 mapped_normal(const DevWorld& W, const Call& K, const DevMaterial& m, const Vtx& x, v3& tg, v3& bt, float& il) {
     tangent_frame(W, x, tg, bt);
     float c[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) c[k] = tex_read(K, m.nrm_slot, m.nrm_off, m.nrm_tw, m.nrm_th, 3, k, x.u, x.v);
+    tex_read<3>(K, m.nrm_slot, m.nrm_off, m.nrm_tw, m.nrm_th, x.u, x.v, c);
     v3 n = mk(c[0] * tg.x + c[1] * bt.x + c[2] * x.ng.x, c[0] * tg.y + c[1] * bt.y + c[2] * x.ng.y,
               c[0] * tg.z + c[1] * bt.z + c[2] * x.ng.z);
     il = 1.0f / sqrtf(dot(n, n));
@@ -1144,9 +1154,11 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
         else if (m.type == MAT_GGX_DIELECTRIC || m.type == MAT_GGX_CONDUCTOR) wg = 1.0f;
         if (wd != 0.0f) {
             float jl = 0.0f;  // this term's share of the loss (linear in cos_x)
+            float rho3[3];
+            albedo3(K, m, x.u, x.v, rho3);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                float rho = albedo(K, m, c, x.u, x.v);
+                const float rho = rho3[c];
                 Enee[4 * c] += wd * rho * (1.0f / PI_F) * gs * le[c];
                 if (GRAD) {
                     gv.rho[c] += a[4 * c] * wd * gs * le[c] * (1.0f / PI_F);
@@ -1208,9 +1220,9 @@ DEV void eval_vertex(const DevWorld& W, const Call& K, const Vtx& x, WC& w, floa
         case LOBE_DIFFUSE: {
             w.kind = 1;
             float jw = 0.0f;
+            albedo3(K, m, x.u, x.v, w.rgb);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                w.rgb[c] = albedo(K, m, c, x.u, x.v);
                 if (GRAD && FULL) gv.rho[c] += Ln[16 * c];
                 if (GRAD && !FULL) {
                     gv.rho[c] += a[4 * c] * Ln[4 * c];
