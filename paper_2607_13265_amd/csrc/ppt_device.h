@@ -556,10 +556,13 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 DEV float half_lo(float w) { return (float)__builtin_bit_cast(f16x2, w).x; }
 DEV float half_hi(float w) { return (float)__builtin_bit_cast(f16x2, w).y; }
 
+// Reciprocal direction for the slab tests, by the hardware reciprocal (1 ulp): the node boxes are
+// rounded outward to half floats, a margin far wider than the reciprocal's error.
 DEV v3 safe_inv(v3 d) {
     const float e = 1e-20f;
-    return mk(1.0f / (fabsf(d.x) > e ? d.x : copysignf(e, d.x)), 1.0f / (fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
-              1.0f / (fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
+    return mk(__builtin_amdgcn_rcpf(fabsf(d.x) > e ? d.x : copysignf(e, d.x)),
+              __builtin_amdgcn_rcpf(fabsf(d.y) > e ? d.y : copysignf(e, d.y)),
+              __builtin_amdgcn_rcpf(fabsf(d.z) > e ? d.z : copysignf(e, d.z)));
 }
 
 // Intersection of primitive i (triangle or sphere) with the ray; accepted when 0 < t < tb, which
