@@ -17,10 +17,9 @@ HIPCC_FLAGS = [
     # address: that kept a few fields of the shading kernels' weight record in scratch memory
     # (shading 16.9 -> 15.9 ms per step without it)
     "-mllvm", "-simplifycfg-sink-common=false",
-    # FP32 division and square root by the hardware reciprocal and square-root sequences (a few ulp)
-    # instead of the correctly rounded expansions: about 80 divisions in the shading kernel and 120
-    # in the replay (replay 5.8 -> 5.5 ms per step); results move at FP32 rounding level
-    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    # (FP32 division and square root stay correctly rounded: the faster hardware sequences took the
+    # replay 5.8 -> 5.5 ms per step but doubled the error of the smooth dielectric's normal-map
+    # gradient, whose s/p rotators amplify rounding: light-stage glass map 4.8e-4 -> 9.4e-4 of 1e-3)
 ]
 
 
