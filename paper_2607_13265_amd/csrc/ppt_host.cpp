@@ -87,6 +87,7 @@ struct Builder {
     static constexpr int NB = 32;          // SAH bins per axis (16 measured 1% more node visits)
     static constexpr float C_TRAV = 0.5f;  // cost of a node visit relative to a primitive test
     static constexpr int MAX_LEAF = 8;     // primitives per leaf (the leaf reference holds count - 1 in 3 bits)
+    static constexpr int SWEEP_MAX = 512;  // nodes up to this size: exact SAH sweep instead of bins
     std::vector<BPrim> prims;
     std::vector<int> idx;
     std::vector<BNode> nodes;
@@ -114,6 +115,44 @@ struct Builder {
         nodes[id].left = nodes[id].right = -1;
         nodes[id].first = first; nodes[id].count = count;
         if (count <= 2) return id;
+        float leaf_cost0 = area(n.lo, n.hi) * count;
+        if (count <= SWEEP_MAX) {  // small nodes: every split of the centroid order on each axis
+            float bc_cost = 1e30f;
+            int bc_axis = -1, bc_at = -1;
+            std::vector<int> ord(idx.begin() + first, idx.begin() + first + count);
+            std::vector<float> racc((size_t)count);
+            for (int a = 0; a < 3; ++a) {
+                std::sort(ord.begin(), ord.end(), [&](int p, int q) {
+                    return prims[p].c[a] < prims[q].c[a] || (prims[p].c[a] == prims[q].c[a] && p < q);
+                });
+                float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+                for (int i = count - 1; i >= 1; --i) {
+                    const BPrim& p = prims[ord[i]];
+                    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], p.lo[k]); hi[k] = std::max(hi[k], p.hi[k]); }
+                    racc[i] = area(lo, hi) * (count - i);
+                }
+                for (int k = 0; k < 3; ++k) { lo[k] = 1e30f; hi[k] = -1e30f; }
+                for (int i = 0; i < count - 1; ++i) {
+                    const BPrim& p = prims[ord[i]];
+                    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], p.lo[k]); hi[k] = std::max(hi[k], p.hi[k]); }
+                    const float cost = area(lo, hi) * (i + 1) + racc[i + 1];
+                    if (cost < bc_cost) { bc_cost = cost; bc_axis = a; bc_at = i + 1; }
+                }
+            }
+            const float split_cost0 = bc_axis >= 0 ? C_TRAV * area(n.lo, n.hi) + bc_cost : 1e30f;
+            if (count <= MAX_LEAF && leaf_cost0 <= split_cost0) return id;
+            if (bc_axis >= 0) {
+                const int a = bc_axis;
+                std::sort(idx.begin() + first, idx.begin() + first + count, [&](int p, int q) {
+                    return prims[p].c[a] < prims[q].c[a] || (prims[p].c[a] == prims[q].c[a] && p < q);
+                });
+                const int mid = first + bc_at;
+                int l = build(first, mid - first, depth + 1);
+                int r = build(mid, first + count - mid, depth + 1);
+                nodes[id].left = l; nodes[id].right = r; nodes[id].count = 0;
+                return id;
+            }
+        }
         // binned SAH over the three axes
         float best_cost = 1e30f;
         int best_axis = -1, best_bin = -1;
