@@ -37,7 +37,8 @@ BYTES_FOLD_PATH = 96     # fold: keys read (16), adjoint rows (48) + camera ray 
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 64 lanes x FMA x packed)
 PEAK_HBM_GBS = 8000.0
 # files whose content decides whether stored hardware counters still describe the kernels
-KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_device.h",
+KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265_amd/csrc/ppt_kernels_ext.hip",
+                  "paper_2607_13265_amd/csrc/ppt_device.h",
                   "paper_2607_13265_amd/csrc/ppt_internal.h", "paper_2607_13265_amd/csrc/ppt_host.cpp",
                   "paper_2607_13265_amd/csrc/ppt_half.h",  # (the host builds the BVH the kernels traverse)
                   "paper_2607_13265_amd/build.py")  # (and the compiler flags)

@@ -214,6 +214,7 @@ DEV DevWorld world_of(const WArgs& A, int view) {
 DEV DevWorld world_of(const WArgs& A, const DevView& V) { return A.one_world ? A.world0 : gval(A.worlds, (size_t)V.world); }
 
 // ============================================================================ chunk start
+#ifndef PPT_EXT_TU  // (non-template kernels: in the main compilation unit only)
 __global__ void k_reset_counts(int* counts) {
     if (threadIdx.x < 8) counts[threadIdx.x] = 0;
 }
@@ -246,6 +247,8 @@ __global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
     }
     flush_stats(A.stats, cnt);
 }
+
+#endif  // PPT_EXT_TU
 
 // Closest hits of the rays of one bounce: a persistent kernel in which a lane takes the next queued
 // ray as soon as its own is finished.  SMODE >= 0: the same launch resolves the shadow rays of the
@@ -561,6 +564,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
     flush_stats(A.stats, cnt);
 }
 
+#ifndef PPT_EXT_TU  // (non-template kernel: in the main compilation unit only)
 // ============================================================================ render: pixel reduction
 // Every lane rotates its path's radiance into the sensor frame; the lanes of one pixel (adjacent,
 // samples fastest) are summed by a segmented wavefront scan, and the last lane of each segment
@@ -636,6 +640,8 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
         }
     }
 }
+
+#endif  // PPT_EXT_TU
 
 // W_c applied to a Stokes vector without branches on the weight's kind (the loads of a record
 // stay together ahead of the arithmetic): the Fresnel form is evaluated and then selected.
@@ -1201,6 +1207,7 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
     flush_lds_grads(A, K);
 }
 
+#ifndef PPT_EXT_TU  // (non-template kernels and the host side: in the main compilation unit only)
 // ============================================================================ P-RB comparator
 // Polarized radiative backpropagation (the comparator of Sec. 5.1): the replay reads, for each vertex
 // b1, an independent estimate of the suffix beyond it instead of the cached one.  Pass b1 traces,
@@ -1506,6 +1513,18 @@ static int resident_grid(const void* fn, size_t lds, int64_t n, const LaunchGrid
     return blocks_for(n, per_cu * G.cu);
 }
 
+// The variants for scenes with the light-stage features are compiled in their own unit
+// (ppt_kernels_ext.hip) with FP32 division and square root correctly rounded: they differentiate
+// the shading normal through the smooth dielectric's s/p rotators, which amplify rounding.
+extern template __global__ void k_shade<0, true>(WArgs);
+extern template __global__ void k_shade<1, true>(WArgs);
+extern template __global__ void k_shade<2, true>(WArgs);
+extern template __global__ void k_fold<true, true, false, false>(WArgs);
+extern template __global__ void k_replay<false, true, false, false>(WArgs);
+extern template __global__ void k_replay<true, true, false, false>(WArgs);
+extern template __global__ void k_replay<true, true, true, false>(WArgs);
+extern template __global__ void k_replay<false, true, false, true>(WArgs);
+
 // One chunk of paths through every bounce.  mode 0: render, 1: backward.  M is told the family
 // of every kernel before its launch (event timing).
 hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M) {
@@ -1656,4 +1675,5 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     return hipSuccess;
 }
 
+#endif  // PPT_EXT_TU
 }  // namespace ppt
