@@ -44,7 +44,7 @@ KERNEL_SOURCES = ("paper_2607_13265_amd/csrc/ppt_kernels.hip", "paper_2607_13265
                   "paper_2607_13265_amd/build.py")  # (and the compiler flags)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_{}.md")
 KERNEL_SYMBOL = {"extend": "ppt::k_extend", "shade": "ppt::k_shade", "compact": "ppt::k_compact",
-                 "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum", "camera": "ppt::k_gen"}
+                 "fold": "ppt::k_fold", "replay": "ppt::k_replay", "accum": "ppt::k_accum"}
 
 
 def one_or_list(xs):
@@ -761,14 +761,18 @@ def cpu_leg(args, torch, ppt, sg, wl, plan, params, d, out, want):
     # all threads: render (with the per-path signatures) + cached-suffix replay
     t0 = time.perf_counter()
     r = osc.run(p64, sample_views, wl.max_depth, wl.seed, want_sig=True, nthreads=nthreads)
+    tr = time.perf_counter() - t0
     r2 = osc.run(p64, sample_views, wl.max_depth, wl.seed, mode=oracle.MODE_CACHED_PRB, d_image=dd,
                  want_image=False, grad_slots=grad_slots, nthreads=nthreads)
     tc = time.perf_counter() - t0
     base = {"value": round(r["n_vertices"] / tc / 1e6, 4), "unit": "Mpath-vertices/s", "cores": nthreads,
             "kind": "oracle", "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
             "sample": f"{sample_desc} at full spp, depth {wl.max_depth} ({r['n_paths']} paths, {r['n_vertices']} "
-                      f"vertices): FP64 render + cached-suffix replay, {tc:.1f} s on {nthreads} threads"}
-    log(f"[bench] cpu oracle ({nthreads} threads): {base['value']} Mpath-vertices/s")
+                      f"vertices): FP64 render + cached-suffix replay, {tc:.1f} s on {nthreads} threads",
+            "render_only": {"value": round(r["n_vertices"] / tr / 1e6, 4), "cores": nthreads,
+                            "sample": f"the same paths, render alone, {tr:.1f} s"}}
+    log(f"[bench] cpu oracle ({nthreads} threads): {base['value']} Mpath-vertices/s "
+        f"(render alone {base['render_only']['value']})")
     # one thread on a smaller sample
     n1 = max(1, min(args.cpu_views_1t, len(sample_views)))
     v1 = sample_views[:n1]
@@ -782,6 +786,16 @@ def cpu_leg(args, torch, ppt, sg, wl, plan, params, d, out, want):
                           "sample": f"{n1} of the sampled views ({q['n_paths']} paths, {q['n_vertices']} vertices), "
                                     f"{t1:.1f} s"}
     log(f"[bench] cpu oracle (1 thread): {base['one_thread']['value']} Mpath-vertices/s")
+    # conventional AD (the oracle's stored tape: its own forward pass records every vertex, then the
+    # reverse sweep) on that smaller sample, all threads
+    t0 = time.perf_counter()
+    qt = osc.run(p64, v1, wl.max_depth, wl.seed, mode=oracle.MODE_TAPE_AD, d_image=d1, want_image=False,
+                 grad_slots=grad_slots, nthreads=nthreads)
+    tt = time.perf_counter() - t0
+    base["tape_ad"] = {"value": round(qt["n_vertices"] / tt / 1e6, 4), "cores": nthreads,
+                       "sample": f"{n1} of the sampled views ({qt['n_vertices']} vertices): FP64 tape forward + "
+                                 f"reverse sweep, {tt:.1f} s"}
+    log(f"[bench] cpu oracle, tape AD ({nthreads} threads): {base['tape_ad']['value']} Mpath-vertices/s")
     # parity of the timed plan on the sampled paths
     sig_g = plan.signatures(params, wl.seed).cpu().numpy().view(np.uint64)[gidx]
     agree = sig_g == r["sig"]
@@ -815,13 +829,6 @@ def cpu_leg(args, torch, ppt, sg, wl, plan, params, d, out, want):
                        and par["divergent_paths"] <= 0.01 * agree.size)
     log(f"[bench] parity of the timed configuration: {par}")
     return {"cpu_baseline": base, "parity": par}
-
-
-    line = json.dumps(result)
-    print(line, flush=True)
-    if args.json_out:
-        with open(args.json_out, "w") as f:
-            f.write(line + "\n")
 
 
 if __name__ == "__main__":

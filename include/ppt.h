@@ -248,9 +248,10 @@ int ppt_read_hybrid_stats(const void* ws, int64_t* out, void* stream);
  * records a HIP event on its stream before each kernel launch and one after its last launch.
  * ppt_plan_kernel_times waits for the most recent such call of `op` (0 render, 1 backward) and
  * writes, for kernel family k < n, the summed time between an event and the next (ms[k], in
- * milliseconds) and the number of launches (launches[k]).  Families: 0 camera rays,
- * 1 traversal (closest hits of a bounce's rays, from the second bounce on in the same launch as
- * the shadow rays of the previous bounce), 2 shading, 3 shadow rays launched alone (none at
+ * milliseconds) and the number of launches (launches[k]).  Families: 0 camera rays launched
+ * alone (none at present: the first traversal launch generates them), 1 traversal (closest hits
+ * of a bounce's rays, from the second bounce on in the same launch as the shadow rays of the
+ * previous bounce), 2 shading, 3 shadow rays launched alone (none at
  * present), 4 pixel reduction, 5 suffix fold, 6 adjoint replay, 7 setup / clearing /
  * finalization, 8 hit compaction.  Enabling or disabling clears the
  * records.  Not for use under stream capture; calls on one plan must not overlap while

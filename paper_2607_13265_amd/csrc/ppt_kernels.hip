@@ -139,17 +139,12 @@ DEV int find_view(const DevView* views, int n_views, int64_t g) {
     }
     return lo;
 }
-// Path keys of a global path index.  Lanes of a wavefront hold consecutive paths, so the view
-// of the wavefront's first lane is looked up once and a lane searches only when its path lies
-// beyond that view.  The index within a view fits 32 bits (checked when the plan is made).
+// Path keys of a global path index.  The lanes of a wavefront mostly hold consecutive paths, so
+// the view of a wave-uniform first index g_first is looked up once and a lane searches only when
+// its path lies outside [g_first, end of that view).  The index within a view fits 32 bits (checked
+// when the plan is made).
 struct PathId { int v, px, py, lx, ly; uint32_t smp, pix; };
-DEV PathId path_id(const DevView* views, int n_views, int64_t g, int64_t g_first) {
-    PathId r;
-    const int v0 = __builtin_amdgcn_readfirstlane(find_view(views, n_views, g_first));
-    r.v = v0;
-    const int64_t end0 = v0 + 1 < n_views ? gval(views, (size_t)(v0 + 1)).path_off : INT64_MAX;
-    if (g >= end0) r.v = find_view(views, n_views, g);
-    const DevView V = gval(views, (size_t)r.v);
+DEV void path_keys(const DevView& V, int64_t g, PathId& r) {
     const uint32_t local = (uint32_t)(g - V.path_off);
     const uint32_t spp = (uint32_t)V.spp, cw = (uint32_t)V.crop_w;
     const uint32_t pl = local / spp;
@@ -159,6 +154,15 @@ DEV PathId path_id(const DevView* views, int n_views, int64_t g, int64_t g_first
     r.px = V.crop_x0 + r.lx;
     r.py = V.crop_y0 + r.ly;
     r.pix = (uint32_t)(r.py * V.width + r.px);
+}
+DEV PathId path_id(const DevView* views, int n_views, int64_t g, int64_t g_first) {
+    PathId r;
+    const int v0 = __builtin_amdgcn_readfirstlane(find_view(views, n_views, g_first));
+    r.v = v0;
+    const int64_t end0 = v0 + 1 < n_views ? gval(views, (size_t)(v0 + 1)).path_off : INT64_MAX;
+    if (g >= end0 || g < g_first) r.v = find_view(views, n_views, g);
+    const DevView V = gval(views, (size_t)r.v);
+    path_keys(V, g, r);
     return r;
 }
 
@@ -219,41 +223,15 @@ __global__ void k_reset_counts(int* counts) {
     if (threadIdx.x < 8) counts[threadIdx.x] = 0;
 }
 
-// Camera rays of the chunk's paths (masked paths are marked and skipped by the first bounce).
-__global__ void __launch_bounds__(BLOCK) k_gen(WArgs A) {
-    PathState& S = A.S;
-    Count cnt;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < A.n_chunk; i += gridDim.x * BLOCK) {
-        int64_t g = A.g0 + i;
-        const int64_t g_first = __builtin_amdgcn_readfirstlane((uint32_t)(i - lane_id())) + A.g0;
-        PathId id = path_id(A.views, A.n_views, g, g_first);
-        const DevView V = gval(A.views, (size_t)id.v);
-        bool live = !(A.mask && !A.mask[g]);
-        v3 o, d;
-        camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
-        // rotation from the canonical frame of the light arriving along -d to the sensor frame,
-        // kept in the record's spare words for the pixel reduction
-        const v3 kc = -d;
-        float Cs, Ss;
-        rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
-        float4* R = ray_rec(S, i);
-        ray_set(R, o, d, Cs, Ss);
-        R[2] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // the whole record is written
-        S.hflag[i] = live ? 0 : 2;
-        R[3] = f4(__int_as_float(info_make(0, false, id.v) | (live ? 0 : INFO_DEAD)), __uint_as_float(id.pix),
-                  __uint_as_float(id.smp), __uint_as_float(V.view_id));  // (the view's sampling identity)
-        if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
-        if (live) ++cnt.c[ST_PATHS];
-    }
-    flush_stats(A.stats, cnt);
-}
-
 #endif  // PPT_EXT_TU
 
 // Closest hits of the rays of one bounce: a persistent kernel in which a lane takes the next queued
 // ray as soon as its own is finished.  SMODE >= 0: the same launch resolves the shadow rays of the
 // previous bounce (positions [0, n_s) of one work list, any hit; SMODE is that bounce's mode: 0
 // render, 1 backward, 2 hybrid replay), so the two kinds of rays share one launch and its tail.
+// SMODE -1: the first bounce of rays whose records are written (P-RB sub-paths); SMODE -2: the
+// first bounce of a chunk's camera paths, each lane generating the camera ray of the path it takes
+// (no separate ray-generation pass writing records that this launch would read back).
 template <int SMODE>
 __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
     extern __shared__ int lds_stack[];
@@ -288,6 +266,29 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                            mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
                 alive = true;
                 ++cnt.c[ST_SHADOW_RAYS];
+            } else if (SMODE == -2) {
+                // the camera ray of path slot, generated here (its record is written when the ray
+                // is finished; a masked path's keys at once, and it is not traversed)
+                slot = idx;
+                const int64_t g = A.g0 + idx;
+                const int64_t g_first = A.g0 + __builtin_amdgcn_readfirstlane(idx);
+                const PathId id = path_id(A.views, A.n_views, g, g_first);
+                const DevView V = gval(A.views, (size_t)id.v);
+                const bool live = !(A.mask && !A.mask[g]);
+                v3 o, d;
+                camera_ray(V, id.px, id.py, id.smp, A.seed, o, d);
+                info = info_make(0, false, id.v) | (live ? 0 : INFO_DEAD);
+                trav_begin(T, world_of(A, V), o, d, 3.0e38f);
+                alive = live;
+                if (A.sig) A.sig[g] = live ? 1469598103934665603ull : 0ull;
+                if (live) {
+                    ++cnt.c[ST_PATHS];
+                    ++cnt.c[ST_RAYS];
+                } else {
+                    ray_rec(S, slot)[3] = f4(__int_as_float(info), __uint_as_float(id.pix), __uint_as_float(id.smp),
+                                             __uint_as_float(V.view_id));
+                    S.hflag[slot] = 2;
+                }
             } else {
                 slot = A.first ? idx : q[idx - ns];
                 const float4* R = ray_rec(S, slot);
@@ -346,6 +347,26 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
                     *hwp = __int_as_float((int)hw);
                 }
                 if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(occ ? NEE_OCCLUDED : NEE_VISIBLE));
+            } else if (SMODE == -2) {
+                // the camera ray's record: the whole record for a hit (ray, sensor rotation, hit,
+                // keys), the keys alone for a ray that escaped (nothing else of it is read); the
+                // keys again from the slot and the view in the info word
+                float4* R = ray_rec(S, slot);
+                const DevView V = gval(A.views, (size_t)(info >> 12));
+                PathId id;
+                path_keys(V, A.g0 + slot, id);
+                if (T.h.prim >= 0) {
+                    // rotation from the canonical frame of the light arriving along -d to the
+                    // sensor frame, kept in the record's spare words for the pixel reduction
+                    const v3 kc = -T.d;
+                    float Cs, Ss;
+                    rot_cs(kc, canon_x(kc), normalize(ld3(V.r) - kc * dot(ld3(V.r), kc)), Cs, Ss);
+                    ray_set(R, T.o, T.d, Cs, Ss);
+                    R[2] = f4(T.tb, T.h.u, T.h.v, __int_as_float(T.h.prim));
+                }
+                R[3] = f4(__int_as_float(info), __uint_as_float(id.pix), __uint_as_float(id.smp),
+                          __uint_as_float(V.view_id));
+                S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
             } else {
                 float4* R = ray_rec(S, slot);
                 // the hit in one aligned 16-byte store (a hit's distance is the final tb)
@@ -1532,13 +1553,11 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     M(KF_OTHER, s);
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, s, a.S.counts);
     int gb = blocks_for(a.n_chunk, G.other);
-    M(KF_GEN, s);
-    hipLaunchKernelGGL(k_gen, dim3(gb), dim3(BLOCK), 0, s, a);
     const int xg = blocks_for(a.n_chunk, G.extend);
     a.qin = 0;
     a.first = 1;
     M(KF_EXTEND, s);
-    hipLaunchKernelGGL(k_extend<-1>, dim3(xg), dim3(BLOCK), lds, s, a);
+    hipLaunchKernelGGL(k_extend<-2>, dim3(xg), dim3(BLOCK), lds, s, a);  // (camera rays generated in the launch)
     for (int b = 1; b <= a.max_depth; ++b) {
         a.qin = (b - 1) & 1;
         a.first = b == 1;
@@ -1666,7 +1685,7 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1, false>, BLOCK, 0)) != hipSuccess) return r;
     size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay<false, false>, BLOCK, glds)) != hipSuccess) return r;
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_gen, BLOCK, 0)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_compact<0>, BLOCK, 0)) != hipSuccess) return r;
     G->extend = (e > 0 ? e : 1) * cu;
     G->shade = (sh > 0 ? sh : 1) * cu;
     G->adjoint = (ad > 0 ? ad : 1) * cu;
