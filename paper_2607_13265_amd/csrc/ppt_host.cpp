@@ -274,6 +274,7 @@ struct ppt_plan {
     int32_t hyb_rule = 0;       // hybrid replay decision rule (Eq. 3) and its thresholds
     float hyb_gamma = 0.0f, hyb_eps = 0.0f;
     int32_t adjoint = 0;        // PPT_ADJOINT_*
+    bool all_polarizer = false;  // every view has a linear-polarizer sensor (the render's rank-one record)
     float pprb_sigma = 0.0f;
     mutable KTimer timer[2];  // most recent render / backward call while timing is enabled
 };
@@ -693,6 +694,8 @@ int ppt_plan_create(const ppt_scene* sc, const ppt_view* views, int32_t n_views,
     }
     P->image_numel = out_off;
     P->num_paths = path_off;
+    P->all_polarizer = n_views > 0;
+    for (int32_t v = 0; v < n_views; ++v) P->all_polarizer = P->all_polarizer && views[v].sensor == PPT_SENSOR_POLARIZER;
     // chunk of paths in flight: all paths up to 16M by default, a multiple of the wavefront size
     if (opts && (opts->checkpoint_interval < 0 || opts->checkpoint_interval > MAX_DEPTH)) {
         delete P;
@@ -815,6 +818,7 @@ static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayou
     a.Q = Q;
     a.mask = p->mask;
     a.ext = p->scene->has_ext ? 1 : 0;  // kernels with normal/specular maps and circular emitters
+    a.r1 = p->all_polarizer && !p->scene->has_ext ? 1 : 0;  // rank-one render
     if (p->scene->worlds.size() == 1) {
         a.one_world = 1;
         a.world0 = p->scene->worlds[0]->dev;

@@ -25,6 +25,9 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     contribution (forward passes), then the adjoint rows of the replay (backward)
 //   accumulator record (render), ACC_F4 = 8 vectors (128 B):
 //     [0..3] prefix Mueller product beta (16)   [4] beta RGB scales (3)   [5..7] radiance Lo (12)
+//     rank-one render (every view a linear polarizer): [0] rho = q^T R_s beta   [1] RGB scales
+//     [2] shadow ray origin, tmax   [3] its direction   [4] y_c = q^T R_s Lo_c (3)   [5] the pending
+//     next-event part of y (3)   [6..7] unused (the shadow record is not used)
 //   cache record (backward), one per (vertex b, slot), CACHE_F4 = 8 vectors (128 B):
 //     [0] rgb0 rgb1 rgb2 A   [1] B C D Cin   [2] Sin Cout Sout hitword   [3] u-or-t v - -
 //     [4..6] E_b (12 words), overwritten by the fold with the suffix radiance beyond the vertex,
@@ -177,6 +180,7 @@ struct WArgs {
     int32_t pprb;           // backward by the noise-regularised P-PRB comparator (Sec. 4.2)
     float pprb_sigma;       // its noise deviation
     int32_t ext;            // the scene uses normal maps, specular maps or circular emitters
+    int32_t r1;             // render by the rank-one record (every view has a linear-polarizer sensor, no ext)
     float* out;             // render output
     const float* dout;      // backward: dL/dStokes
     double* gacc;           // backward: FP64 gradient accumulators

@@ -229,6 +229,8 @@ __global__ void k_reset_counts(int* counts) {
 // ray as soon as its own is finished.  SMODE >= 0: the same launch resolves the shadow rays of the
 // previous bounce (positions [0, n_s) of one work list, any hit; SMODE is that bounce's mode: 0
 // render, 1 backward, 2 hybrid replay), so the two kinds of rays share one launch and its tail.
+// SMODE 4: the render's mode for a linear-polarizer sensor (shadow rays and pending radiance in the
+// rank-one record of k_shade<4>).
 // SMODE -1: the first bounce of rays whose records are written (P-RB sub-paths); SMODE -2: the
 // first bounce of a chunk's camera paths, each lane generating the camera ray of the path it takes
 // (no separate ray-generation pass writing records that this launch would read back).
@@ -260,7 +262,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
             if (SMODE >= 0 && any) {
                 slot = S.squeue[idx];
                 info = __float_as_int(ray_rec(S, slot)[3].x);
-                const float4* H = shd_rec(S, slot);
+                const float4* H = SMODE == 4 ? acc_rec(S, slot) + 2 : shd_rec(S, slot);
                 const float4 s0 = H[0], s1 = H[1];
                 trav_begin(T, world_of(A, info >> 12),
                            mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
@@ -313,7 +315,16 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
         }
         if (done) {
             alive = false;
-            if (SMODE >= 0 && any) {
+            if (SMODE == 4 && any) {
+                // rank-one render: the three pending scalars join the path's radiance when visible
+                // (one 32-byte sector of the path's record)
+                if (T.h.prim < 0) {
+                    float4* AC = acc_rec(S, slot);
+                    const float4 y = AC[4], p = AC[5];
+                    AC[4] = f4(y.x + p.x, y.y + p.y, y.z + p.z, 0.0f);
+                }
+                if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(T.h.prim >= 0 ? NEE_OCCLUDED : NEE_VISIBLE));
+            } else if (SMODE >= 0 && any) {
                 const bool occ = T.h.prim >= 0;
                 const float4* H = shd_rec(S, slot);
                 if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
@@ -481,6 +492,60 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                         CK[0] = f4(o.x, o.y, o.z, prev_delta ? 1.0f : 0.0f);
                         CK[1] = f4(d.x, d.y, d.z, 0.0f);
                     }
+                } else if (MODE == 4) {
+                    // render with a linear-polarizer sensor: its analyzer is rank one, so the image
+                    // needs per channel only the scalar y_c = q^T R_s Lo_c (q: the analyzer's row, R_s:
+                    // the sensor rotation).  The path carries the row rho = q^T R_s beta (shared by
+                    // the channels, beside beta's RGB scales) instead of beta, and y instead of Lo:
+                    // one 128-byte record [rho | rgb | shadow ray o, tmax | d | y | pending | - | -]
+                    float4* AC = acc_rec(S, slot);
+                    float rho[4], brgb[3], y[3];
+                    if (nb == 0) {
+                        const DevView V = gval(A.views, (size_t)v);
+                        const float th = K.p(V.theta_slot, V.theta_off);
+                        const float C2 = cosf(2.0f * th), S2 = sinf(2.0f * th);
+                        const float Cs = r1.z, Ss = r1.w;  // sensor rotation of the camera ray
+                        rho[0] = 0.5f;
+                        rho[1] = 0.5f * (C2 * Cs - S2 * Ss);
+                        rho[2] = 0.5f * (C2 * Ss + S2 * Cs);
+                        rho[3] = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) { brgb[c] = 1.0f; y[c] = 0.0f; }
+                    } else {
+                        const float4 a0 = AC[0], a1 = AC[1], a4 = AC[4];
+                        rho[0] = a0.x; rho[1] = a0.y; rho[2] = a0.z; rho[3] = a0.w;
+                        brgb[0] = a1.x; brgb[1] = a1.y; brgb[2] = a1.z;
+                        y[0] = a4.x; y[1] = a4.y; y[2] = a4.z;
+                    }
+                    float pn[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        y[c] += brgb[c] * (rho[0] * Ee[4 * c] + rho[1] * Ee[4 * c + 1] + rho[2] * Ee[4 * c + 2] +
+                                           rho[3] * Ee[4 * c + 3]);
+                        pn[c] = brgb[c] * (rho[0] * En[4 * c] + rho[1] * En[4 * c + 1] + rho[2] * En[4 * c + 2] +
+                                           rho[3] * En[4 * c + 3]);
+                    }
+                    if (cont) {
+                        if (w.kind == 1) {
+                            rho[1] = rho[2] = rho[3] = 0.0f;
+                        } else {
+                            WC ws = w;
+                            ws.rgb[0] = 1.0f;
+                            float o4[4];
+                            w_row(ws, 0, rho, o4);
+                            rho[0] = o4[0]; rho[1] = o4[1]; rho[2] = o4[2]; rho[3] = o4[3];
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) brgb[c] *= w.rgb[c];
+                    }
+                    // the whole record (partial records measured slower)
+                    AC[0] = f4(rho[0], rho[1], rho[2], rho[3]);
+                    AC[1] = f4(brgb[0], brgb[1], brgb[2], 0.0f);
+                    AC[2] = shadow ? f4(so.x, so.y, so.z, stmax) : f4(0.0f, 0.0f, 0.0f, 0.0f);
+                    AC[3] = shadow ? f4(sd.x, sd.y, sd.z, 0.0f) : f4(0.0f, 0.0f, 0.0f, 0.0f);
+                    AC[4] = f4(y[0], y[1], y[2], 0.0f);
+                    AC[5] = f4(pn[0], pn[1], pn[2], 0.0f);
+                    AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 } else if (MODE == 0 || MODE == 3) {
                     float4* AC = acc_rec(S, slot);
                     float beta[16], brgb[3], Lo[12];
@@ -564,7 +629,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     C[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // a whole 128-byte record is written
                     if (shadow) st12(H + 2, En);
                 }
-                if (shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
+                if (MODE != 4 && shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
                     H[1] = f4(sd.x, sd.y, sd.z, 0.0f);
                     if (MODE == 3) st12(H + 5, En);  // (the tape's E_b takes the unweighted part)
@@ -585,14 +650,19 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
     flush_stats(A.stats, cnt);
 }
 
-#ifndef PPT_EXT_TU  // (non-template kernel: in the main compilation unit only)
+#ifndef PPT_EXT_TU  // (in the main compilation unit only)
 // ============================================================================ render: pixel reduction
 // Every lane rotates its path's radiance into the sensor frame; the lanes of one pixel (adjacent,
 // samples fastest) are summed by a segmented wavefront scan, and the last lane of each segment
 // applies the analyzers and adds the mean to the image.  A pixel whose samples span two
 // wavefronts or chunks receives several additions.
+// R1: the rank-one render of a linear-polarizer sensor, whose paths carry y_c = q^T R_s Lo_c (rotation
+// and analyzer row already applied): the scan sums three scalars and the output is (1, C, S, 0) y_c,
+// C = cos 2 theta, S = sin 2 theta (the polarizer's Mueller matrix is q' q'^T / 2 with q' = (1, C, S, 0)).
+template <bool R1>
 __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
     if (!A.out) return;  // signature-only runs produce no image
+    constexpr int NA = R1 ? 3 : 12;
     PathState& S = A.S;
     Call K{A.table, nullptr};
     const int lane = lane_id();
@@ -600,9 +670,9 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
         int i = base + lane;
         bool valid = i < A.n_chunk;
         int64_t key = -1 - lane;  // distinct per invalid lane
-        float acc[12];
+        float acc[NA];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
+        for (int k = 0; k < NA; ++k) acc[k] = 0.0f;
         int v = 0, lx = 0, ly = 0;
         if (valid) {
             // pixel of the path from its stored keys; the segment key is (view, pixel)
@@ -616,17 +686,22 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             lx = px - V.crop_x0; ly = py - V.crop_y0;
             key = ((int64_t)v << 32) | (int64_t)pix;
             if (!(info & INFO_DEAD) && (info & 255) != 0) {  // a camera ray that escaped has no radiance
-                const float4 r1 = R[1];
-                const float Cs = r1.z, Ss = r1.w;  // sensor rotation of the camera ray
-                float Lo[12];
-                ld12(acc_rec(S, i) + 5, Lo);
+                if constexpr (R1) {
+                    const float4 y = acc_rec(S, i)[4];
+                    acc[0] = y.x; acc[1] = y.y; acc[2] = y.z;
+                } else {
+                    const float4 r1 = R[1];
+                    const float Cs = r1.z, Ss = r1.w;  // sensor rotation of the camera ray
+                    float Lo[12];
+                    ld12(acc_rec(S, i) + 5, Lo);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float l1 = Lo[4 * c + 1], l2 = Lo[4 * c + 2];
-                    acc[4 * c] = Lo[4 * c];
-                    acc[4 * c + 1] = Cs * l1 + Ss * l2;
-                    acc[4 * c + 2] = -Ss * l1 + Cs * l2;
-                    acc[4 * c + 3] = Lo[4 * c + 3];
+                    for (int c = 0; c < 3; ++c) {
+                        float l1 = Lo[4 * c + 1], l2 = Lo[4 * c + 2];
+                        acc[4 * c] = Lo[4 * c];
+                        acc[4 * c + 1] = Cs * l1 + Ss * l2;
+                        acc[4 * c + 2] = -Ss * l1 + Cs * l2;
+                        acc[4 * c + 3] = Lo[4 * c + 3];
+                    }
                 }
             }
         }
@@ -636,7 +711,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             int64_t kup = __shfl_up(key, off, WAVE);
             bool take = lane >= off && kup == key;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
+            for (int k = 0; k < NA; ++k) {
                 float t = __shfl_up(acc[k], off, WAVE);
                 if (take) acc[k] += t;
             }
@@ -647,17 +722,28 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             const DevView V = gval(A.views, (size_t)v);
             float theta = V.sensor == SENSOR_POLARIZER ? K.p(V.theta_slot, V.theta_off) : 0.0f;
             float inv = 1.0f / (float)V.spp;
-            int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
             int64_t ob = V.out_off + ((int64_t)ly * V.crop_w + lx) * 12;
-            for (int a = 0; a < V.n_analyzers; ++a)
+            if constexpr (R1) {
+                const float C2 = cosf(2.0f * theta), S2 = sinf(2.0f * theta);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    float o4[4];
-                    analyzer_apply(V.sensor, theta, a, acc + 4 * c, o4);
+                    const float o4[3] = {acc[c], C2 * acc[c], S2 * acc[c]};
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (o4[k] != 0.0f) atomicAdd(A.out + ob + a * astride + 4 * c + k, o4[k] * inv);
+                    for (int k = 0; k < 3; ++k)
+                        if (o4[k] != 0.0f) atomicAdd(A.out + ob + 4 * c + k, o4[k] * inv);
                 }
+            } else {
+                int64_t astride = (int64_t)V.crop_w * V.crop_h * 12;
+                for (int a = 0; a < V.n_analyzers; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float o4[4];
+                        analyzer_apply(V.sensor, theta, a, acc + 4 * c, o4);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if (o4[k] != 0.0f) atomicAdd(A.out + ob + a * astride + 4 * c + k, o4[k] * inv);
+                    }
+            }
         }
     }
 }
@@ -1567,7 +1653,9 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
         M(KF_SHADE, s);
         // (a grid sized to each variant's own occupancy measured slower for the render variant)
         const int sg = blocks_for(a.n_chunk, G.shade);
-        if (mode == 1 && a.tape) {
+        if (mode == 0 && a.r1) {
+            hipLaunchKernelGGL((k_shade<4, false>), dim3(sg), dim3(BLOCK), 0, s, a);
+        } else if (mode == 1 && a.tape) {
             hipLaunchKernelGGL((k_shade<3, false>), dim3(sg), dim3(BLOCK), 0, s, a);
         } else if (a.ext) {
             if (mode == 0) hipLaunchKernelGGL((k_shade<0, true>), dim3(sg), dim3(BLOCK), 0, s, a);
@@ -1584,7 +1672,8 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
             a.qin = b & 1;
             a.first = 0;
             M(KF_EXTEND, s);
-            if (mode == 0) hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, a);
+            if (mode == 0 && a.r1) hipLaunchKernelGGL(k_extend<4>, dim3(xg), dim3(BLOCK), lds, s, a);
+            else if (mode == 0) hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, a);
             else if (a.tape) hipLaunchKernelGGL(k_extend<3>, dim3(xg), dim3(BLOCK), lds, s, a);
             else if (a.ckpt > 0) hipLaunchKernelGGL(k_extend<2>, dim3(xg), dim3(BLOCK), lds, s, a);
             else hipLaunchKernelGGL(k_extend<1>, dim3(xg), dim3(BLOCK), lds, s, a);
@@ -1593,7 +1682,8 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     if (mode == 0) {
         if (a.out) {
             M(KF_ACCUM, s);
-            hipLaunchKernelGGL(k_accum, dim3(gb), dim3(BLOCK), 0, s, a);
+            if (a.r1) hipLaunchKernelGGL(k_accum<true>, dim3(gb), dim3(BLOCK), 0, s, a);
+            else hipLaunchKernelGGL(k_accum<false>, dim3(gb), dim3(BLOCK), 0, s, a);
         }
     } else {
         size_t glds = (size_t)a.lds_nd * sizeof(double) + (size_t)a.lds_nf * sizeof(float);

@@ -71,6 +71,29 @@ def _small_batch(n_views=6, res=24, spp=4):
     return wl
 
 
+def test_rank_one_render_equals_full_render():
+    """A plan whose views all have a linear-polarizer sensor renders with the rank-one record (the
+    row q^T R_s beta and three scalars per path); one more view with no sensor makes the same
+    plan render with the full 4x4 throughput.  The polarizer views' paths are the same in both, so
+    their images agree to FP32 rounding of the reassociated products, in every Stokes component."""
+    ppt = _ppt()
+    wl = _small_batch(n_views=4, res=24, spp=4)
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = _params(wl.scene)
+    extra = wl.views[:1].copy()
+    extra["sensor"] = sg.SENSOR_NONE
+    extra["view_id"] = 999
+    both = np.concatenate([wl.views, extra])
+    a = ppt.Plan(scene, wl.views, wl.max_depth).render(params, 21).double().cpu().numpy()
+    b = ppt.Plan(scene, both, wl.max_depth).render(params, 21).double().cpu().numpy()[:a.size]
+    a4, b4 = a.reshape(-1, 4), b.reshape(-1, 4)
+    assert np.abs(b4).max() > 0
+    for k in range(3):  # s3 is zero behind a linear polarizer
+        nb = np.linalg.norm(b4[:, k])
+        assert np.linalg.norm(a4[:, k] - b4[:, k]) <= 1e-5 * nb, k
+    assert np.abs(a4[:, 3]).max() == 0.0 and np.abs(b4[:, 3]).max() == 0.0
+
+
 def test_batched_equals_per_view_and_chunk_invariance():
     ppt = _ppt()
     wl = _small_batch()
