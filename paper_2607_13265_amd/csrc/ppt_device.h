@@ -633,9 +633,12 @@ DEV void trav_begin(Trav& T, const DevWorld& W, v3 o, v3 d, float tmax) {
 // descending until every such lane holds a leaf (or, with refill, until fewer than a quarter of
 // the wavefront's lanes still descend), then the parked leaves are tested.  Returns true
 // when the ray is finished: closest hit in T.h (any = false), or the first hit (any = true).
+// CNT: count node visits and primitive tests into n_nodes, n_prims (their registers cost the
+// kernel a wavefront per SIMD, so launches without work counters leave them out).
+template <bool CNT>
 DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int* stack, bool refill) {
     while (T.ref != TRAV_DONE && T.ref >= 0) {
-        ++n_nodes;
+        if (CNT) ++n_nodes;
         // the two top stack entries, read while the node is in flight (below the bottom of the
         // stack the padding is read and not used)
         const int sp = T.sp;
@@ -690,7 +693,7 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         int enc = ~T.leaf;
         int first = enc >> 3, cnt = (enc & 7) + 1;
         for (int k = 0; k < cnt; ++k) {
-            ++n_prims;
+            if (CNT) ++n_prims;
             if (hit_prim(T.prims, first + k, T.o, T.d, T.tb, T.h) && any) {
                 T.leaf = 0;
                 T.ref = TRAV_DONE;

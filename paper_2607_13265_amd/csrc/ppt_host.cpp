@@ -266,7 +266,7 @@ struct ppt_plan {
     int64_t image_numel = 0, num_paths = 0;
     int32_t Q = 64;             // paths per chunk (slots of the path state)
     int32_t n_chunks = 1;
-    LaunchGrid grid{1, 1, 1, 1};
+    LaunchGrid grid{1, 1, 1, 1, 0, 1};
     const uint8_t* mask = nullptr;
     bool stats = true;
     bool timing = false;
@@ -514,6 +514,10 @@ struct WsLayout {
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Q: path-state slots of one chunk (the plan's chunk size, or less for the fixed scratch)
+// The render keeps each path's state in the rank-one record (no shadow record) when every view has a
+// linear-polarizer sensor and the scene has none of the light-stage features.
+static bool rank_one(const ppt_plan* p) { return p->all_polarizer && !p->scene->has_ext; }
+
 static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     WsLayout L{};
     const size_t Q = (size_t)Qslots;
@@ -523,7 +527,7 @@ static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     L.stats = take(sizeof(Stats));
     L.counts = take(32);
     L.ray = take(RAY_F4 * 16 * Q);
-    L.shd = take(SHD_F4 * 16 * Q);
+    L.shd = take(op == 0 && rank_one(p) ? 0 : SHD_F4 * 16 * Q);
     const bool tape = op == 1 && p->adjoint == PPT_ADJOINT_TAPE;  // (forward accumulator + per-vertex tape)
     L.acc = take(op == 0 || tape ? ACC_F4 * 16 * Q : 0);
     const bool hybrid = op == 1 && p->ckpt > 0;
@@ -818,7 +822,7 @@ static WArgs make_args(const ppt_plan* p, uint64_t seed, void* ws, const WsLayou
     a.Q = Q;
     a.mask = p->mask;
     a.ext = p->scene->has_ext ? 1 : 0;  // kernels with normal/specular maps and circular emitters
-    a.r1 = p->all_polarizer && !p->scene->has_ext ? 1 : 0;  // rank-one render
+    a.r1 = rank_one(p) ? 1 : 0;
     if (p->scene->worlds.size() == 1) {
         a.one_world = 1;
         a.world0 = p->scene->worlds[0]->dev;

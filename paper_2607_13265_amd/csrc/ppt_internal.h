@@ -190,7 +190,8 @@ struct WArgs {
     DevWorld world0;
 };
 
-struct LaunchGrid { int extend, shade, adjoint, other, cu; };  // workgroups per kernel family; compute units
+// workgroups per kernel family (extend_st: traversal with work counters); compute units
+struct LaunchGrid { int extend, shade, adjoint, other, cu, extend_st; };
 
 constexpr uint32_t FLAG_NO_NEE = 1u;
 

@@ -234,8 +234,10 @@ __global__ void k_reset_counts(int* counts) {
 // SMODE -1: the first bounce of rays whose records are written (P-RB sub-paths); SMODE -2: the
 // first bounce of a chunk's camera paths, each lane generating the camera ray of the path it takes
 // (no separate ray-generation pass writing records that this launch would read back).
-template <int SMODE>
-__global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
+// STATS: the launch adds to the work counters (A.stats set); without them a lane holds no counter
+// registers.
+template <int SMODE, bool STATS>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STATS ? 1 : 8, 8))) k_extend(WArgs A) {
     extern __shared__ int lds_stack[];
     int* stack = lds_stack + threadIdx.x;
     PathState& S = A.S;
@@ -307,11 +309,13 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
         if (!__any(alive) && !F.more()) break;
         const bool refill = F.more();
         uint32_t nn = 0, np = 0;
-        const bool done = alive && trav_round(T, SMODE >= 0 && any, nn, np, stack, refill);
-        if (SMODE >= 0 && any) {
-            cnt.c[ST_SHADOW_NODES] += nn; cnt.c[ST_SHADOW_PRIMS] += np;
-        } else {
-            cnt.c[ST_NODES] += nn; cnt.c[ST_PRIMS] += np;
+        const bool done = alive && trav_round<STATS>(T, SMODE >= 0 && any, nn, np, stack, refill);
+        if (STATS) {
+            if (SMODE >= 0 && any) {
+                cnt.c[ST_SHADOW_NODES] += nn; cnt.c[ST_SHADOW_PRIMS] += np;
+            } else {
+                cnt.c[ST_NODES] += nn; cnt.c[ST_PRIMS] += np;
+            }
         }
         if (done) {
             alive = false;
@@ -386,7 +390,7 @@ __global__ void __launch_bounds__(BLOCK) k_extend(WArgs A) {
             }
         }
     }
-    flush_stats(A.stats, cnt);
+    if (STATS) flush_stats(A.stats, cnt);
 }
 
 // ============================================================================ hit compaction
@@ -1632,6 +1636,13 @@ extern template __global__ void k_replay<true, true, false, false>(WArgs);
 extern template __global__ void k_replay<true, true, true, false>(WArgs);
 extern template __global__ void k_replay<false, true, false, true>(WArgs);
 
+// A traversal launch, with or without the work counters.
+template <int SMODE>
+static void launch_extend(const WArgs& a, int grid, size_t lds, hipStream_t s) {
+    if (a.stats) hipLaunchKernelGGL((k_extend<SMODE, true>), dim3(grid), dim3(BLOCK), lds, s, a);
+    else hipLaunchKernelGGL((k_extend<SMODE, false>), dim3(grid), dim3(BLOCK), lds, s, a);
+}
+
 // One chunk of paths through every bounce.  mode 0: render, 1: backward.  M is told the family
 // of every kernel before its launch (event timing).
 hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M) {
@@ -1639,11 +1650,11 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
     M(KF_OTHER, s);
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, s, a.S.counts);
     int gb = blocks_for(a.n_chunk, G.other);
-    const int xg = blocks_for(a.n_chunk, G.extend);
+    const int xg = blocks_for(a.n_chunk, a.stats ? G.extend_st : G.extend);
     a.qin = 0;
     a.first = 1;
     M(KF_EXTEND, s);
-    hipLaunchKernelGGL(k_extend<-2>, dim3(xg), dim3(BLOCK), lds, s, a);  // (camera rays generated in the launch)
+    launch_extend<-2>(a, xg, lds, s);  // (camera rays generated in the launch)
     for (int b = 1; b <= a.max_depth; ++b) {
         a.qin = (b - 1) & 1;
         a.first = b == 1;
@@ -1672,11 +1683,11 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
             a.qin = b & 1;
             a.first = 0;
             M(KF_EXTEND, s);
-            if (mode == 0 && a.r1) hipLaunchKernelGGL(k_extend<4>, dim3(xg), dim3(BLOCK), lds, s, a);
-            else if (mode == 0) hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, a);
-            else if (a.tape) hipLaunchKernelGGL(k_extend<3>, dim3(xg), dim3(BLOCK), lds, s, a);
-            else if (a.ckpt > 0) hipLaunchKernelGGL(k_extend<2>, dim3(xg), dim3(BLOCK), lds, s, a);
-            else hipLaunchKernelGGL(k_extend<1>, dim3(xg), dim3(BLOCK), lds, s, a);
+            if (mode == 0 && a.r1) launch_extend<4>(a, xg, lds, s);
+            else if (mode == 0) launch_extend<0>(a, xg, lds, s);
+            else if (a.tape) launch_extend<3>(a, xg, lds, s);
+            else if (a.ckpt > 0) launch_extend<2>(a, xg, lds, s);
+            else launch_extend<1>(a, xg, lds, s);
         }
     }
     if (mode == 0) {
@@ -1714,7 +1725,7 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
                 b2.qin = 0;
                 b2.first = 1;
                 M(KF_EXTEND, s);
-                hipLaunchKernelGGL(k_extend<-1>, dim3(xg), dim3(BLOCK), lds, s, b2);
+                launch_extend<-1>(b2, xg, lds, s);
                 for (int bb = b1 + 1; bb <= a.max_depth; ++bb) {
                     const int it = bb - b1;
                     b2.qin = (it - 1) & 1;
@@ -1727,7 +1738,7 @@ hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, c
                         b2.qin = it & 1;
                         b2.first = 0;
                         M(KF_EXTEND, s);
-                        hipLaunchKernelGGL(k_extend<0>, dim3(xg), dim3(BLOCK), lds, s, b2);
+                        launch_extend<0>(b2, xg, lds, s);
                     }
                 }
                 M(KF_OTHER, s);
@@ -1771,12 +1782,15 @@ hipError_t occupancy_grid(int cu, int stack_cap, LaunchGrid* G) {
     int e = 0, sh = 0, ad = 0, ot = 0;
     size_t lds = (size_t)stack_cap * BLOCK * sizeof(int);
     hipError_t r;
-    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend<1>, BLOCK, lds)) != hipSuccess) return r;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, k_extend<1, false>, BLOCK, lds)) != hipSuccess) return r;
+    int es = 0;
+    if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&es, k_extend<1, true>, BLOCK, lds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&sh, k_shade<1, false>, BLOCK, 0)) != hipSuccess) return r;
     size_t glds = (size_t)LDS_GRAD_D * sizeof(double) + (size_t)LDS_GRAD_F * sizeof(float);
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ad, k_replay<false, false>, BLOCK, glds)) != hipSuccess) return r;
     if ((r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ot, k_compact<0>, BLOCK, 0)) != hipSuccess) return r;
     G->extend = (e > 0 ? e : 1) * cu;
+    G->extend_st = (es > 0 ? es : 1) * cu;
     G->shade = (sh > 0 ? sh : 1) * cu;
     G->adjoint = (ad > 0 ? ad : 1) * cu;
     G->cu = cu;

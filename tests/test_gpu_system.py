@@ -71,6 +71,30 @@ def _small_batch(n_views=6, res=24, spp=4):
     return wl
 
 
+def test_launches_without_work_counters_match():
+    """With the work counters off, traversal runs its counter-free variants (fewer registers, one
+    more wavefront per SIMD): image and gradients equal those of the counting launches up to the
+    order of the atomic additions, and the counters are left untouched."""
+    ppt = _ppt()
+    wl = _small_batch()
+    scene = ppt.Scene(wl.scene.to_blob())
+    params = _params(wl.scene)
+    plan = ppt.Plan(scene, wl.views, wl.max_depth, chunk_paths=4096)
+    d = torch.randn(plan.image_numel, device="cuda")
+    img_a = plan.render(params, 13)
+    g_a = plan.backward(params, 13, d)
+    st_a = plan.stats(0)
+    plan.set_stats(False)
+    img_b = plan.render(params, 13)
+    g_b = plan.backward(params, 13, d)
+    plan.set_stats(True)
+    assert float((img_a - img_b).norm()) <= 1e-6 * float(img_a.norm())
+    for a, b in zip(g_a, g_b):
+        if a is not None:
+            assert float((a.double() - b.double()).norm()) <= 1e-6 * max(float(a.double().norm()), 1e-30)
+    assert st_a["nodes"] > 0 and st_a["vertices"] > 0
+
+
 def test_rank_one_render_equals_full_render():
     """A plan whose views all have a linear-polarizer sensor renders with the rank-one record (the
     row q^T R_s beta and three scalars per path); one more view with no sensor makes the same
