@@ -82,10 +82,12 @@ DEV void sig_add(uint64_t& h, uint32_t x) {
 
 // Work distribution of the persistent kernels.  Only the first ceil(n / BLOCK) workgroups take
 // part (fetch_active; the others leave at once).  Active wavefront w first takes the static batch
-// [w * s, (w + 1) * s) with s = n / active wavefronts rounded down to whole wavefronts and kept in
-// [FETCH_MIN, FETCH_BATCH]; positions beyond all static batches are handed out in batches of
-// FETCH_BATCH through one atomic on a counter that the previous kernel cleared.  A short queue is
-// thus covered by the static batches alone, with no atomic.  A wavefront gives its positions, in
+// [w * s, (w + 1) * s) with s = n / active wavefronts rounded up and kept in [FETCH_MIN,
+// FETCH_BATCH]; positions beyond all static batches are handed out in batches of FETCH_BATCH
+// through one atomic on a counter that the previous kernel cleared.  A queue of up to FETCH_BATCH
+// positions per wavefront is thus covered by the static batches alone, with no atomic (rounding s
+// down to whole wavefronts left up to half of a mid-sized queue to the atomic batches, whose
+// early round ends for refill made such launches slower).  A wavefront gives its positions, in
 // order, to its lanes that have no work; every lane of the wavefront must call take().
 constexpr int FETCH_MIN = WAVE, FETCH_BATCH = 4 * WAVE;
 DEV int fetch_blocks(int n) { return max(1, min((int)gridDim.x, (n + BLOCK - 1) / BLOCK)); }
@@ -97,7 +99,7 @@ struct WaveFetch {
     DEV explicit WaveFetch(int n) {
         const int waves = fetch_blocks(n) * (BLOCK / WAVE);
         const int w = blockIdx.x * (BLOCK / WAVE) + (int)(threadIdx.x / WAVE);
-        int sb = (n / waves) / WAVE * WAVE;
+        int sb = (n + waves - 1) / waves;
         sb = sb < FETCH_MIN ? FETCH_MIN : (sb > FETCH_BATCH ? FETCH_BATCH : sb);
         stat = waves * sb;
         c = min(w * sb, n);
