@@ -603,8 +603,10 @@ DEV bool hit_prim(const float4* prims, int i, v3 o, v3 d, float& tb, Hit& h) {
 
 // Resumable traversal state of one ray.  The stack lives in LDS, entry k at stack[(k + 2) * BLOCK]:
 // two entries of padding below the bottom let the node step read the two top entries and write the
-// next one at fixed offsets from one address (the padding is read and never used).
+// next one at fixed offsets from one address.  The padding holds TRAV_DONE (trav_stack_init, once
+// per lane; nothing writes it afterwards), so a pop below the bottom reads the end of traversal.
 constexpr int TRAV_DONE = 0x7fffffff;
+DEV void trav_stack_init(int* stack) { stack[0] = TRAV_DONE; stack[BLOCK] = TRAV_DONE; }
 struct Trav {
     v3 o, d, id, ood;
     float tb;
@@ -668,7 +670,7 @@ DEV bool trav_round(Trav& T, bool any, uint32_t& n_nodes, uint32_t& n_prims, int
         const bool goR = hR & (!hL | (tnR < tnL));  // (bitwise: no branch)
         const int near = goR ? rR : rL, far = goR ? rL : rR;
         const bool both = hL && hR, none = !hL && !hR, free_slot = T.leaf == 0;
-        const int pop1 = sp > 0 ? top1 : TRAV_DONE, pop2 = sp > 1 ? top2 : TRAV_DONE;
+        const int pop1 = top1, pop2 = top2;  // (below the bottom: the padding, which holds TRAV_DONE)
         const bool park_near = !none && near < 0 && free_slot;
         const bool park_pop = none && pop1 < 0 && free_slot;
         const bool push = both && !park_near;

@@ -242,6 +242,7 @@ template <int SMODE, bool STATS>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STATS ? 1 : 8, 8))) k_extend(WArgs A) {
     extern __shared__ int lds_stack[];
     int* stack = lds_stack + threadIdx.x;
+    trav_stack_init(stack);
     PathState& S = A.S;
     const int Q = A.Q;
     if (blockIdx.x == 0 && threadIdx.x == 0) {  // the queues the following kernels append to
