@@ -508,7 +508,7 @@ static int convert_world(ppt_scene* sc, const uint8_t*& p, const uint8_t* end, W
 struct WsLayout {
     size_t table, stats, counts, gacc, total;
     int lds_nd = 0, lds_nf = 0;
-    size_t ray, shd, acc, cache, hits, ckpt, q0, q1, sq, hq, hf;
+    size_t ray, shd, acc, cache, hits, ckpt, q0, q1, sq, hq, hf, nv, nv_bytes;
     size_t ray2, shd2, acc2, q0_2, q1_2, sq2, hq2, hf2, counts2;  // P-RB sub-path state
     int64_t gacc_n;
 };
@@ -530,6 +530,8 @@ static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     L.shd = take(op == 0 && rank_one(p) ? 0 : SHD_F4 * 16 * Q);
     const bool tape = op == 1 && p->adjoint == PPT_ADJOINT_TAPE;  // (forward accumulator + per-vertex tape)
     L.acc = take(op == 0 || tape ? ACC_F4 * 16 * Q : 0);
+    L.nv_bytes = op == 0 && rank_one(p) ? Q : 0;  // the rank-one render's vertex flags
+    L.nv = take(L.nv_bytes);
     const bool hybrid = op == 1 && p->ckpt > 0;
     const size_t records = hybrid ? (size_t)std::min(p->ckpt, p->max_depth) : (size_t)p->max_depth;
     L.cache = take(op == 1 ? records * (tape ? TAPE_F4 : CACHE_F4) * 16 * Q : 0);
@@ -565,6 +567,7 @@ static PathState path_state(void* ws, const WsLayout& L) {
     S.ray = (float4*)(w + L.ray);
     S.shd = (float4*)(w + L.shd);
     S.acc = (float4*)(w + L.acc);
+    S.nv = L.nv_bytes ? (uint8_t*)(w + L.nv) : nullptr;
     S.cache = (float4*)(w + L.cache);
     S.hits = (float4*)(w + L.hits);
     S.ckpt = (float4*)(w + L.ckpt);

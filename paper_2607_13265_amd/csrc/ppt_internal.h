@@ -139,6 +139,8 @@ struct PathState {
     float4* ray;    // [Q][RAY_F4]
     float4* shd;    // [Q][SHD_F4]
     float4* acc;    // [Q][ACC_F4] (render)
+    uint8_t* nv;    // [Q] rank-one render: 1 if the path has a vertex (a radiance record), written by
+                    // the first traversal, so that the pixel reduction reads no ray record (else NULL)
     float4* cache;  // [max_depth or k][Q][CACHE_F4] (backward; per block scratch in the hybrid replay)
     float4* hits;   // [max_depth][Q] hit records (hybrid replay)
     float4* ckpt;   // [ceil(max_depth / k)][Q][CKPT_F4] checkpoint records (hybrid replay)

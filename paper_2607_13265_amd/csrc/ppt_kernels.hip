@@ -295,6 +295,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                     ray_rec(S, slot)[3] = f4(__int_as_float(info), __uint_as_float(id.pix), __uint_as_float(id.smp),
                                              __uint_as_float(V.view_id));
                     S.hflag[slot] = 2;
+                    if (A.r1) S.nv[slot] = 0;  // (no radiance)
                 }
             } else {
                 slot = A.first ? idx : q[idx - ns];
@@ -324,7 +325,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
             alive = false;
             if (SMODE == 4 && any) {
                 // rank-one render: the three pending scalars join the path's radiance when visible
-                // (one 32-byte sector of the path's record)
                 if (T.h.prim < 0) {
                     float4* AC = acc_rec(S, slot);
                     const float4 y = AC[4], p = AC[5];
@@ -385,6 +385,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 R[3] = f4(__int_as_float(info), __uint_as_float(id.pix), __uint_as_float(id.smp),
                           __uint_as_float(V.view_id));
                 S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
+                // rank-one render: whether the path has a vertex, hence a radiance record
+                if (A.r1) S.nv[slot] = T.h.prim >= 0 ? 1 : 0;
             } else {
                 float4* R = ray_rec(S, slot);
                 // the hit in one aligned 16-byte store (a hit's distance is the final tb)
@@ -681,7 +683,18 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k] = 0.0f;
         int v = 0, lx = 0, ly = 0;
-        if (valid) {
+        if (R1 && valid) {
+            // the keys from the path's index (the wavefront holds consecutive paths), and y from the
+            // path's record when the path has a vertex (one byte per path says so): no ray record
+            // is read, and no record of a path without radiance
+            const PathId id = path_id(A.views, A.n_views, A.g0 + i, A.g0 + base);
+            v = id.v; lx = id.lx; ly = id.ly;
+            key = ((int64_t)v << 32) | (int64_t)id.pix;
+            if (S.nv[i]) {
+                const float4 y = acc_rec(S, i)[4];
+                acc[0] = y.x; acc[1] = y.y; acc[2] = y.z;
+            }
+        } else if (valid) {
             // pixel of the path from its stored keys; the segment key is (view, pixel)
             const float4* R = ray_rec(S, i);
             const float4 r3 = R[3];
@@ -693,10 +706,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             lx = px - V.crop_x0; ly = py - V.crop_y0;
             key = ((int64_t)v << 32) | (int64_t)pix;
             if (!(info & INFO_DEAD) && (info & 255) != 0) {  // a camera ray that escaped has no radiance
-                if constexpr (R1) {
-                    const float4 y = acc_rec(S, i)[4];
-                    acc[0] = y.x; acc[1] = y.y; acc[2] = y.z;
-                } else {
+                if constexpr (!R1) {
                     const float4 r1 = R[1];
                     const float Cs = r1.z, Ss = r1.w;  // sensor rotation of the camera ray
                     float Lo[12];
@@ -1649,6 +1659,7 @@ static void launch_extend(const WArgs& a, int grid, size_t lds, hipStream_t s) {
 // One chunk of paths through every bounce.  mode 0: render, 1: backward.  M is told the family
 // of every kernel before its launch (event timing).
 hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M) {
+    if (mode != 0 || !a.S.nv) a.r1 = 0;  // (the rank-one record is the render's, with its vertex flags)
     size_t lds = (size_t)a.stack_cap * BLOCK * sizeof(int);
     M(KF_OTHER, s);
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, s, a.S.counts);
