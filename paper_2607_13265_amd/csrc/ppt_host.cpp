@@ -530,7 +530,7 @@ static WsLayout ws_layout(const ppt_plan* p, int op, int32_t Qslots) {
     L.shd = take(op == 0 && rank_one(p) ? 0 : SHD_F4 * 16 * Q);
     const bool tape = op == 1 && p->adjoint == PPT_ADJOINT_TAPE;  // (forward accumulator + per-vertex tape)
     L.acc = take(op == 0 || tape ? ACC_F4 * 16 * Q : 0);
-    L.nv_bytes = op == 0 && rank_one(p) ? Q : 0;  // the rank-one render's vertex flags
+    L.nv_bytes = (op == 0 && rank_one(p)) || op == 1 ? Q : 0;  // vertex counts (rank-one render, backward)
     L.nv = take(L.nv_bytes);
     const bool hybrid = op == 1 && p->ckpt > 0;
     const size_t records = hybrid ? (size_t)std::min(p->ckpt, p->max_depth) : (size_t)p->max_depth;

@@ -139,8 +139,9 @@ struct PathState {
     float4* ray;    // [Q][RAY_F4]
     float4* shd;    // [Q][SHD_F4]
     float4* acc;    // [Q][ACC_F4] (render)
-    uint8_t* nv;    // [Q] rank-one render: 1 if the path has a vertex (a radiance record), written by
-                    // the first traversal, so that the pixel reduction reads no ray record (else NULL)
+    uint8_t* nv;    // [Q] vertices of the path: the first traversal writes 0 or 1, the backward's shading
+                    // kernels the count; read by the rank-one pixel reduction (has the path a radiance
+                    // record) and by the fold, so that neither reads a ray record (NULL: not kept)
     float4* cache;  // [max_depth or k][Q][CACHE_F4] (backward; per block scratch in the hybrid replay)
     float4* hits;   // [max_depth][Q] hit records (hybrid replay)
     float4* ckpt;   // [ceil(max_depth / k)][Q][CKPT_F4] checkpoint records (hybrid replay)

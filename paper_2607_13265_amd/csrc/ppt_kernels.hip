@@ -145,7 +145,7 @@ DEV int find_view(const DevView* views, int n_views, int64_t g) {
 // the view of a wave-uniform first index g_first is looked up once and a lane searches only when
 // its path lies outside [g_first, end of that view).  The index within a view fits 32 bits (checked
 // when the plan is made).
-struct PathId { int v, px, py, lx, ly; uint32_t smp, pix; };
+struct PathId { int v, px, py, lx, ly; uint32_t smp, pix, view_id; };
 DEV void path_keys(const DevView& V, int64_t g, PathId& r) {
     const uint32_t local = (uint32_t)(g - V.path_off);
     const uint32_t spp = (uint32_t)V.spp, cw = (uint32_t)V.crop_w;
@@ -156,6 +156,7 @@ DEV void path_keys(const DevView& V, int64_t g, PathId& r) {
     r.px = V.crop_x0 + r.lx;
     r.py = V.crop_y0 + r.ly;
     r.pix = (uint32_t)(r.py * V.width + r.px);
+    r.view_id = V.view_id;
 }
 DEV PathId path_id(const DevView* views, int n_views, int64_t g, int64_t g_first) {
     PathId r;
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                     ray_rec(S, slot)[3] = f4(__int_as_float(info), __uint_as_float(id.pix), __uint_as_float(id.smp),
                                              __uint_as_float(V.view_id));
                     S.hflag[slot] = 2;
-                    if (A.r1) S.nv[slot] = 0;  // (no radiance)
+                    if (S.nv) S.nv[slot] = 0;  // (no vertex)
                 }
             } else {
                 slot = A.first ? idx : q[idx - ns];
@@ -385,8 +386,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 R[3] = f4(__int_as_float(info), __uint_as_float(id.pix), __uint_as_float(id.smp),
                           __uint_as_float(V.view_id));
                 S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
-                // rank-one render: whether the path has a vertex, hence a radiance record
-                if (A.r1) S.nv[slot] = T.h.prim >= 0 ? 1 : 0;
+                // whether the path has a vertex (the shading kernels of the backward then count them)
+                if (S.nv) S.nv[slot] = T.h.prim >= 0 ? 1 : 0;
             } else {
                 float4* R = ray_rec(S, slot);
                 // the hit in one aligned 16-byte store (a hit's distance is the final tb)
@@ -468,6 +469,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
             {  // every queued ray hit a surface
                 int b = nb + 1;
                 ++cnt.c[ST_VERTICES];
+                if (MODE == 1 || MODE == 2 || MODE == 3) S.nv[slot] = (uint8_t)b;  // (the fold reads these)
                 Vtx x;
                 surface(W, h, o, d, x);
                 v3 so, sd;
@@ -894,14 +896,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
     for (int base = r0; base < r1; base += BLOCK) {
         const int i = base + threadIdx.x;
         bool push = false;
-        const float4 r3 = i < r1 ? ray_rec(S, i)[3] : f4(__int_as_float(INFO_DEAD), 0.0f, 0.0f, 0.0f);
-        const int info = __float_as_int(r3.x);
-        const int B = (info & INFO_DEAD) ? 0 : (info & 255);
-        const int v = info >> 12;
+        // the path's vertex count from the dense byte array and its keys from its index (no read of
+        // its ray record, which would cost a 128-byte line for 16 bytes)
+        const int B = i < r1 ? (int)S.nv[i] : 0;
         float gt = 0.0f;
         if (B > 0) {
             push = true;
-            const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
+            // (keys before the fold only where the fold needs them: fewer registers live across it)
+            const int64_t gw = A.g0 + base + (int)(threadIdx.x & ~(WAVE - 1));
+            PathId id{};
+            if (HYB || PPRB) id = path_id(A.views, A.n_views, A.g0 + i, gw);
             // fold over records B-1 .. 0 (record r holds vertex r+1): the record's E words receive
             // the suffix beyond its vertex, L[r+2], so the replay of a vertex reads one record (the
             // last vertex's suffix is zero and is not stored)
@@ -911,14 +915,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
             if (HYB) {
                 // blocks from the last to the first: re-evaluate from the block's checkpoint ray,
                 // store the suffix beyond the block, fold back to the block's first vertex
-                const DevView Vh = gval(A.views, (size_t)v);
+                const DevView Vh = gval(A.views, (size_t)id.v);
                 const DevWorld Wh = world_of(A, Vh);
                 const int kc = A.ckpt;
                 for (int j = (B + kc - 1) / kc - 1; j >= 0; --j) {
                     const int s0 = j * kc, e0 = min(B, s0 + kc);
                     float4* CK = ckpt_rec(S, Q, j, i);
                     const float4 k0 = CK[0], k1 = CK[1];
-                    block_eval<EXT>(A, K, Vh, Wh, i, pix, smp, s0, e0, mk(k0.x, k0.y, k0.z), mk(k1.x, k1.y, k1.z),
+                    block_eval<EXT>(A, K, Vh, Wh, i, id.pix, id.smp, s0, e0, mk(k0.x, k0.y, k0.z), mk(k1.x, k1.y, k1.z),
                                k0.w != 0.0f);
                     st12(CK + 2, L);
                     block_fold(S, Q, i, e0 - s0, L, false);
@@ -933,7 +937,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                 float e[12];
                 ld12(C + 4, e);
                 if (!PPRB && b < B - 1) st12(C + 4, L);
-                const float u = PPRB ? pprb_noise(A, pix, smp, __float_as_uint(r3.w), b + 1) : 0.0f;
+                const float u = PPRB ? pprb_noise(A, id.pix, id.smp, id.view_id, b + 1) : 0.0f;
                 WC w;
                 w.rgb[0] = c0.x; w.rgb[1] = c0.y; w.rgb[2] = c0.z;
                 w.A = c0.w; w.B = c1.x; w.C = c1.y; w.D = c1.z;
@@ -948,7 +952,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                 }
             }
             if (PPRB) st12(shd_rec(S, i) + 5, L);
-            // pixel of the path from its stored keys (no index arithmetic over the batch)
+            if (!(HYB || PPRB)) id = path_id(A.views, A.n_views, A.g0 + i, gw);
+            const int v = id.v;
+            const uint32_t pix = id.pix, smp = id.smp;
             const DevView V = gval(A.views, (size_t)v);
             const int py = (int)(pix / (uint32_t)V.width), px = (int)(pix - (uint32_t)py * (uint32_t)V.width);
             const int lx = px - V.crop_x0, ly = py - V.crop_y0;
