@@ -267,9 +267,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
             any = idx < ns;
             if (SMODE >= 0 && any) {
                 slot = S.squeue[idx];
-                info = __float_as_int(ray_rec(S, slot)[3].x);
+                // the shadow ray and its vertex's info word in one record (no read of the ray
+                // record, whose line would be fetched for its 16-byte key word)
                 const float4* H = SMODE == 4 ? acc_rec(S, slot) + 2 : shd_rec(S, slot);
                 const float4 s0 = H[0], s1 = H[1];
+                info = __float_as_int(s1.w);
                 trav_begin(T, world_of(A, info >> 12),
                            mk(s0.x, s0.y, s0.z), mk(s1.x, s1.y, s1.z), s0.w);
                 alive = true;
@@ -335,9 +337,18 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
             } else if (SMODE >= 0 && any) {
                 const bool occ = T.h.prim >= 0;
                 const float4* H = shd_rec(S, slot);
-                if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
+                if (SMODE == 1) {
+                    // the cache record's E words hold E_b plus the next-event part (k_shade<1>); an
+                    // occluded light sample sets them back to E_b, kept in the shadow record's words
+                    // 5..7 (a visible one reads and writes nothing more)
+                    if (occ) {
+                        float4* dst = cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) dst[k] = H[5 + k];
+                    }
+                } else if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
                     // (the tape forward adds it to both the radiance and the vertex's E_b)
-                    float4* dst = SMODE == 0 || SMODE == 3 ? acc_rec(S, slot) + 5 : cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+                    float4* dst = acc_rec(S, slot) + 5;
                     if (!occ)
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
@@ -494,6 +505,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 cont = x.lobe != LOBE_NONE && x.lobe != LOBE_INVALID;
                 shadow = x.nee == NEE_PENDING;
                 float4* H = shd_rec(S, slot);
+                // the info word of the continuing ray, also carried by the shadow ray's record
+                const int info_next = info_make(b, is_delta(gval(W.mats, (size_t)x.mat).type), v);
                 if (MODE == 2) {
                     // hybrid replay: the hit record, and at a block start the ray into this vertex
                     const bool sphere = !x.tri;
@@ -553,7 +566,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     AC[0] = f4(rho[0], rho[1], rho[2], rho[3]);
                     AC[1] = f4(brgb[0], brgb[1], brgb[2], 0.0f);
                     AC[2] = shadow ? f4(so.x, so.y, so.z, stmax) : f4(0.0f, 0.0f, 0.0f, 0.0f);
-                    AC[3] = shadow ? f4(sd.x, sd.y, sd.z, 0.0f) : f4(0.0f, 0.0f, 0.0f, 0.0f);
+                    AC[3] = shadow ? f4(sd.x, sd.y, sd.z, __int_as_float(info_next)) : f4(0.0f, 0.0f, 0.0f, 0.0f);
                     AC[4] = f4(y[0], y[1], y[2], 0.0f);
                     AC[5] = f4(pn[0], pn[1], pn[2], 0.0f);
                     AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -636,19 +649,30 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     C[1] = f4(w.B, w.C, w.D, w.ci);
                     C[2] = f4(w.si, w.co, w.so, __int_as_float(h.prim | (x.nee << 26) | (w.kind << 29)));
                     C[3] = f4(sphere ? h.t : h.u, h.v, 0.0f, 0.0f);
-                    st12(C + 4, Ee);
+                    // E_b with the next-event part as if its light sample were visible, so that traversal
+                    // writes nothing here for a visible one (an occluded one restores E_b from the
+                    // shadow record's words 5..7)
+                    if (shadow) {
+                        float EN[12];
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) EN[k] = Ee[k] + En[k];
+                        st12(C + 4, EN);
+                    } else {
+                        st12(C + 4, Ee);
+                    }
                     C[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // a whole 128-byte record is written
                     if (shadow) st12(H + 2, En);
                 }
                 if (MODE != 4 && shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
-                    H[1] = f4(sd.x, sd.y, sd.z, 0.0f);
+                    H[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_next));
                     if (MODE == 3) st12(H + 5, En);  // (the tape's E_b takes the unweighted part)
+                    else if (MODE == 1) st12(H + 5, Ee);  // (E_b for an occluded light sample)
                     else H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 float4* Rw = ray_rec(S, slot);
                 if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi, r1.z, r1.w);  // (keeps the sensor rotation)
-                Rw[3].x = __int_as_float(info_make(b, is_delta(gval(W.mats, (size_t)x.mat).type), v));
+                Rw[3].x = __int_as_float(info_next);
             }
         }
         bq_push(qn, cont, slot);
