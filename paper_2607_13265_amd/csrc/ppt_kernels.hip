@@ -327,11 +327,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
         if (done) {
             alive = false;
             if (SMODE == 4 && any) {
-                // rank-one render: the three pending scalars join the path's radiance when visible
-                if (T.h.prim < 0) {
+                // rank-one render: the path's radiance words already hold the next-event part
+                // (k_shade<4>); an occluded light sample restores them from word 5
+                if (T.h.prim >= 0) {
                     float4* AC = acc_rec(S, slot);
-                    const float4 y = AC[4], p = AC[5];
-                    AC[4] = f4(y.x + p.x, y.y + p.y, y.z + p.z, 0.0f);
+                    AC[4] = AC[5];
                 }
                 if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(T.h.prim >= 0 ? NEE_OCCLUDED : NEE_VISIBLE));
             } else if (SMODE >= 0 && any) {
@@ -505,8 +505,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 cont = x.lobe != LOBE_NONE && x.lobe != LOBE_INVALID;
                 shadow = x.nee == NEE_PENDING;
                 float4* H = shd_rec(S, slot);
-                // the info word of the continuing ray, also carried by the shadow ray's record
-                const int info_next = info_make(b, is_delta(gval(W.mats, (size_t)x.mat).type), v);
+                // the vertex's info word carried by its shadow ray's record (vertex count and view;
+                // the delta bit is the continuing ray's and is not read for a shadow ray)
+                const int info_shd = info_make(b, false, v);
                 if (MODE == 2) {
                     // hybrid replay: the hit record, and at a block start the ray into this vertex
                     const bool sphere = !x.tri;
@@ -521,7 +522,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     // needs per channel only the scalar y_c = q^T R_s Lo_c (q: the analyzer's row, R_s:
                     // the sensor rotation).  The path carries the row rho = q^T R_s beta (shared by
                     // the channels, beside beta's RGB scales) instead of beta, and y instead of Lo:
-                    // one 128-byte record [rho | rgb | shadow ray o, tmax | d | y | pending | - | -]
+                    // one 128-byte record [rho | rgb | shadow ray o, tmax | d, info | y | y before the next-event part | - | -]
                     float4* AC = acc_rec(S, slot);
                     float rho[4], brgb[3], y[3];
                     if (nb == 0) {
@@ -566,9 +567,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     AC[0] = f4(rho[0], rho[1], rho[2], rho[3]);
                     AC[1] = f4(brgb[0], brgb[1], brgb[2], 0.0f);
                     AC[2] = shadow ? f4(so.x, so.y, so.z, stmax) : f4(0.0f, 0.0f, 0.0f, 0.0f);
-                    AC[3] = shadow ? f4(sd.x, sd.y, sd.z, __int_as_float(info_next)) : f4(0.0f, 0.0f, 0.0f, 0.0f);
-                    AC[4] = f4(y[0], y[1], y[2], 0.0f);
-                    AC[5] = f4(pn[0], pn[1], pn[2], 0.0f);
+                    AC[3] = shadow ? f4(sd.x, sd.y, sd.z, __int_as_float(info_shd)) : f4(0.0f, 0.0f, 0.0f, 0.0f);
+                    // y with the next-event part as if its light sample were visible (traversal then
+                    // writes nothing for a visible one, and restores y from word 5 for an occluded one)
+                    if (shadow)
+                        AC[4] = f4(y[0] + pn[0], y[1] + pn[1], y[2] + pn[2], 0.0f);
+                    else
+                        AC[4] = f4(y[0], y[1], y[2], 0.0f);
+                    AC[5] = f4(y[0], y[1], y[2], 0.0f);
                     AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 } else if (MODE == 0 || MODE == 3) {
                     float4* AC = acc_rec(S, slot);
@@ -665,14 +671,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                 }
                 if (MODE != 4 && shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
-                    H[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_next));
+                    H[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_shd));
                     if (MODE == 3) st12(H + 5, En);  // (the tape's E_b takes the unweighted part)
                     else if (MODE == 1) st12(H + 5, Ee);  // (E_b for an occluded light sample)
                     else H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 float4* Rw = ray_rec(S, slot);
                 if (cont) ray_set(Rw, spawn(x.p, x.ng, x.wi), x.wi, r1.z, r1.w);  // (keeps the sensor rotation)
-                Rw[3].x = __int_as_float(info_next);
+                Rw[3].x = __int_as_float(info_make(b, is_delta(gval(W.mats, (size_t)x.mat).type), v));
             }
         }
         bq_push(qn, cont, slot);
