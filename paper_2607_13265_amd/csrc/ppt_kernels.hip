@@ -663,17 +663,20 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
 #pragma unroll
                         for (int k = 0; k < 12; ++k) EN[k] = Ee[k] + En[k];
                         st12(C + 4, EN);
+                        // the whole shadow record: ray, next-event part, E_b (for an occluded sample)
+                        H[0] = f4(so.x, so.y, so.z, stmax);
+                        H[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_shd));
+                        st12(H + 2, En);
+                        st12(H + 5, Ee);
                     } else {
                         st12(C + 4, Ee);
                     }
                     C[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // a whole 128-byte record is written
-                    if (shadow) st12(H + 2, En);
                 }
-                if (MODE != 4 && shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
+                if (MODE != 4 && MODE != 1 && shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
                     H[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_shd));
                     if (MODE == 3) st12(H + 5, En);  // (the tape's E_b takes the unweighted part)
-                    else if (MODE == 1) st12(H + 5, Ee);  // (E_b for an occluded light sample)
                     else H[5] = H[6] = H[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 float4* Rw = ray_rec(S, slot);
@@ -901,8 +904,8 @@ DEV void w_matrix(const WC& w, int c, float* m) {
 // Per path with at least one vertex: folds the cache into the suffix radiance
 // L[b] = E_b + W_b L[b+1] (L[b+1] written over E_b), adds the polarizer-angle term
 // delta^T (dP/dtheta) R_s L[1],
-// and sets up the replay: the adjoint rows a_c = (delta^T A / spp) R_s (into `pend`), the camera ray
-// (into ro/rd) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
+// and sets up the replay: the adjoint rows a_c = (delta^T A / spp) R_s, the camera ray's direction,
+// the path's keys and vertex count (all in the shadow record's words 0..4) and an entry of the replay queue (queue0, size counts[3]).  Each workgroup folds one
 // contiguous range of slots, so its lanes mostly see a single view and keep the angle term in a
 // register until the view changes.
 // PPRB (the noise-regularised comparator of Sec. 4.2): the fold uses W_b + u_b I, keeps the records'
@@ -1029,8 +1032,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
                 av[4 * c + 2] = Ss * a1 + Cs * a2;
                 av[4 * c + 3] = asens[4 * c + 3];
             }
-            st12(shd_rec(S, i) + 2, av);
-            ray_set(ray_rec(S, i), o, d);
+            // the replay's start in one record: the camera ray's direction (its origin is the view's),
+            // the info word (vertex count, view), the keys and the adjoint rows
+            float4* Hs = shd_rec(S, i);
+            Hs[0] = f4(d.x, d.y, d.z, __int_as_float(info_make((int)S.nv[i], false, v)));  // (B read again: fewer live registers)
+            Hs[1] = f4(__uint_as_float(pix), __uint_as_float(smp), 0.0f, 0.0f);
+            st12(Hs + 2, av);
             if (pol) {
                 if (tkey != v) {
                     if (tkey >= 0) K.g(A.views[tkey].theta_slot, A.views[tkey].theta_off, gtheta);
@@ -1234,18 +1241,20 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
         const int idx = F.take(slot < 0, n, &S.counts[4]);
         if (idx >= 0) {
             slot = S.queue0[idx];
-            const float4* R = ray_rec(S, slot);
-            const float4 r3 = R[3];
-            const int info = __float_as_int(r3.x);
+            // the path's start as the fold left it in the shadow record (one record per path)
+            const float4* H = shd_rec(S, slot);
+            const float4 h0 = H[0], h1 = H[1];
+            const int info = __float_as_int(h0.w);
             B = info & 255;
             v = info >> 12;
             b = 1;
             prev_delta = false;
-            pix = __float_as_uint(r3.y);
-            smp = __float_as_uint(r3.z);
-            ld12(shd_rec(S, slot) + 2, av);
-            if (PPRB) ld12(shd_rec(S, slot) + 5, Lcur);
-            ray_od(R, o, d);
+            pix = __float_as_uint(h1.x);
+            smp = __float_as_uint(h1.y);
+            ld12(H + 2, av);
+            if (PPRB) ld12(H + 5, Lcur);
+            d = mk(h0.x, h0.y, h0.z);
+            o = ld3(gval(A.views, (size_t)v).o);  // (a pinhole camera's rays leave the view's origin)
         }
         if (!__any(slot >= 0)) break;
         if (slot >= 0) {
@@ -1376,8 +1385,8 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
 // and stores its radiance over the cached suffix in the vertex's record.
 DEV uint64_t prb_seed(uint64_t seed, uint32_t v_first) { return seed + (uint64_t)v_first * 0x9E3779B97F4A7C15ull; }
 
-// The ray leaving vertex b1 of each path: its prefix is replayed from the camera ray (written by the
-// fold) and the hit records, with the path's own key; the sub-path starts there with an identity
+// The ray leaving vertex b1 of each path: its prefix is replayed from the camera ray (its direction
+// written by the fold) and the hit records, with the path's own key; the sub-path starts there with an identity
 // throughput and no radiance.  Paths with b1 or fewer vertices start nothing.
 __global__ void __launch_bounds__(BLOCK) k_prb_start(WArgs A, PathState S2, int b1) {
     const PathState& S = A.S;
@@ -1398,8 +1407,9 @@ __global__ void __launch_bounds__(BLOCK) k_prb_start(WArgs A, PathState S2, int 
         const DevView V = gval(A.views, (size_t)view);
         const DevWorld W = world_of(A, V);
         const uint32_t pix = __float_as_uint(r3.y), smp = __float_as_uint(r3.z);
-        v3 o, d;
-        ray_od(R, o, d);
+        // the camera ray: the view's origin and the direction the fold stored in the shadow record
+        const float4 h0 = shd_rec(S, i)[0];
+        v3 o = ld3(V.o), d = mk(h0.x, h0.y, h0.z);
         bool prev_delta = false;
         for (int b = 1; b <= b1; ++b) {
             const float4* C = cache_rec(S, Q, b - 1, i);
