@@ -21,19 +21,22 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     (Cs, Ss: sensor rotation of the camera ray; view-id: the view's sampling identity; the hit is
 //     one aligned vector, written by traversal in one 16-byte store)
 //   shadow record, SHD_F4 = 8 vectors (128 B):
-//     [0] so.x so.y so.z tmax   [1] sd.x sd.y sd.z -   [2..4] 12 Stokes words: the pending next-event
-//     contribution (forward passes), then the adjoint rows of the replay (backward)
+//     [0] so.x so.y so.z tmax   [1] sd.x sd.y sd.z info (of the vertex whose light sample it is)
+//     [2..4] 12 Stokes words: the pending next-event contribution   [5..7] the backward's E_b (restored
+//     into the cache record for an occluded sample), or zeros.  After the fold (backward): [0] the
+//     camera ray's direction, info   [1] pix smp - -   [2..4] the replay's adjoint rows
 //   accumulator record (render), ACC_F4 = 8 vectors (128 B):
 //     [0..3] prefix Mueller product beta (16)   [4] beta RGB scales (3)   [5..7] radiance Lo (12)
-//     rank-one render (every view a linear polarizer): [0] rho = q^T R_s beta   [1] RGB scales
-//     [2] shadow ray origin, tmax   [3] its direction   [4] y_c = q^T R_s Lo_c (3)   [5] the pending
-//     next-event part of y (3)   [6..7] unused (the shadow record is not used)
+//   rank-one render record (every view a linear polarizer), R1_F4 = 6 vectors (96 B, three whole
+//   32-byte sectors): [0] rho = q^T R_s beta   [1] RGB scales   [2] shadow ray origin, tmax   [3] its
+//   direction, info   [4] y_c = q^T R_s Lo_c (3), with a pending next-event part included as if
+//   visible   [5] y without that part (restored for an occluded sample); no shadow record
 //   cache record (backward), one per (vertex b, slot), CACHE_F4 = 8 vectors (128 B):
 //     [0] rgb0 rgb1 rgb2 A   [1] B C D Cin   [2] Sin Cout Sout hitword   [3] u-or-t v - -
-//     [4..6] E_b (12 words), overwritten by the fold with the suffix radiance beyond the vertex,
+//     [4..6] E_b (12 words; with the next-event part as if visible when a light sample is pending, set
+//     back to E_b by the shadow-ray traversal if occluded), overwritten by the fold with the suffix radiance beyond the vertex,
 //     L[b+1], which is what the replay of vertex b reads (not stored for a path's last vertex)
-//     [7] x: the next-event visibility written by the shadow-ray traversal (in the sector of E_b's
-//     last words, which that traversal updates anyway)
+//     [7] x: the next-event visibility written by the shadow-ray traversal
 //   hitword = prim | next-event state << 26 | weight kind << 29 (the state as sampled: pending for a
 //   light sample; its visibility goes to [7])
 //   hybrid replay (checkpoint interval k): per vertex a hit record [hitword, u-or-t, v, -] (16 B);
@@ -45,7 +48,7 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [0..7] as the cache record (E_b stays: the reverse sweep reads it)   [8..11] the prefix
 //     throughput beta_b (shared 4x4)   [12] its RGB scales, previous vertex delta   [13..14] the ray into
 //     the vertex (o, d)
-constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, CACHE_F4 = 8, CKPT_F4 = 5, TAPE_F4 = 15;
+constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, R1_F4 = 6, CACHE_F4 = 8, CKPT_F4 = 5, TAPE_F4 = 15;
 
 enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
                          MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };

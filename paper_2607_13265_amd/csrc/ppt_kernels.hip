@@ -181,6 +181,7 @@ DEV void table_to_lds(CallTable* dst, const CallTable* src) {
 DEV float4* ray_rec(const PathState& S, int i) { return S.ray + (size_t)i * RAY_F4; }
 DEV float4* shd_rec(const PathState& S, int i) { return S.shd + (size_t)i * SHD_F4; }
 DEV float4* acc_rec(const PathState& S, int i) { return S.acc + (size_t)i * ACC_F4; }
+DEV float4* r1_rec(const PathState& S, int i) { return S.acc + (size_t)i * R1_F4; }  // (rank-one render)
 DEV float4* cache_rec(const PathState& S, int Q, int b0, int i) {  // b0: 0-based vertex index
     return S.cache + ((size_t)b0 * Q + i) * CACHE_F4;
 }
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 slot = S.squeue[idx];
                 // the shadow ray and its vertex's info word in one record (no read of the ray
                 // record, whose line would be fetched for its 16-byte key word)
-                const float4* H = SMODE == 4 ? acc_rec(S, slot) + 2 : shd_rec(S, slot);
+                const float4* H = SMODE == 4 ? r1_rec(S, slot) + 2 : shd_rec(S, slot);
                 const float4 s0 = H[0], s1 = H[1];
                 info = __float_as_int(s1.w);
                 trav_begin(T, world_of(A, info >> 12),
@@ -304,10 +305,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 slot = A.first ? idx : q[idx - ns];
                 const float4* R = ray_rec(S, slot);
                 // the ray and its info word in one round trip (a dead ray's record is set up
-                // and not traversed)
+                // and not traversed); a queued continuing ray is live, so in a scene of one world
+                // its info word is not needed
                 v3 o, d;
                 ray_od(R, o, d);
-                info = __float_as_int(R[3].x);
+                const bool need_info = A.first || !A.one_world;
+                info = need_info ? __float_as_int(R[3].x) : 0;
                 trav_begin(T, world_of(A, info >> 12), o, d, 3.0e38f);
                 alive = !(info & INFO_DEAD);
                 if (alive) ++cnt.c[ST_RAYS];
@@ -330,7 +333,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 // rank-one render: the path's radiance words already hold the next-event part
                 // (k_shade<4>); an occluded light sample restores them from word 5
                 if (T.h.prim >= 0) {
-                    float4* AC = acc_rec(S, slot);
+                    float4* AC = r1_rec(S, slot);
                     AC[4] = AC[5];
                 }
                 if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(T.h.prim >= 0 ? NEE_OCCLUDED : NEE_VISIBLE));
@@ -522,8 +525,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     // needs per channel only the scalar y_c = q^T R_s Lo_c (q: the analyzer's row, R_s:
                     // the sensor rotation).  The path carries the row rho = q^T R_s beta (shared by
                     // the channels, beside beta's RGB scales) instead of beta, and y instead of Lo:
-                    // one 128-byte record [rho | rgb | shadow ray o, tmax | d, info | y | y before the next-event part | - | -]
-                    float4* AC = acc_rec(S, slot);
+                    // one 96-byte record [rho | rgb | shadow ray o, tmax | d, info | y | y before the next-event part]
+                    float4* AC = r1_rec(S, slot);
                     float rho[4], brgb[3], y[3];
                     if (nb == 0) {
                         const DevView V = gval(A.views, (size_t)v);
@@ -575,7 +578,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     else
                         AC[4] = f4(y[0], y[1], y[2], 0.0f);
                     AC[5] = f4(y[0], y[1], y[2], 0.0f);
-                    AC[6] = AC[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
                 } else if (MODE == 0 || MODE == 3) {
                     float4* AC = acc_rec(S, slot);
                     float beta[16], brgb[3], Lo[12];
@@ -726,7 +728,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             v = id.v; lx = id.lx; ly = id.ly;
             key = ((int64_t)v << 32) | (int64_t)id.pix;
             if (S.nv[i]) {
-                const float4 y = acc_rec(S, i)[4];
+                const float4 y = r1_rec(S, i)[4];
                 acc[0] = y.x; acc[1] = y.y; acc[2] = y.z;
             }
         } else if (valid) {
