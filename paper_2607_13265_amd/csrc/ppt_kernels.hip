@@ -341,13 +341,15 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 const bool occ = T.h.prim >= 0;
                 const float4* H = shd_rec(S, slot);
                 if (SMODE == 1) {
-                    // the cache record's E words hold E_b plus the next-event part (k_shade<1>); an
-                    // occluded light sample sets them back to E_b, kept in the shadow record's words
-                    // 5..7 (a visible one reads and writes nothing more)
+                    // the cache record holds E_b plus the next-event part and a visible sample
+                    // (k_shade<1>); an occluded light sample sets the E words back to E_b, kept in the
+                    // shadow record's words 5..7, and its visibility word (two whole 32-byte sectors);
+                    // a visible one writes nothing
                     if (occ) {
                         float4* dst = cache_rec(S, Q, (info & 255) - 1, slot) + 4;
 #pragma unroll
                         for (int k = 0; k < 3; ++k) dst[k] = H[5 + k];
+                        dst[3] = f4(__int_as_float(NEE_OCCLUDED), 0.0f, 0.0f, 0.0f);
                     }
                 } else if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
                     // (the tape forward adds it to both the radiance and the vertex's E_b)
@@ -367,12 +369,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                         }
                     }
                 }
-                if (SMODE == 1) {
-                    // the visibility in the record's last vector, which shares its 32-byte sector with
-                    // the E words written above (the hit word's sector is not touched)
-                    cache_rec(S, Q, (info & 255) - 1, slot)[7] =
-                        f4(__int_as_float(occ ? NEE_OCCLUDED : NEE_VISIBLE), 0.0f, 0.0f, 0.0f);
-                } else if (SMODE != 0) {  // in the hit word of the vertex whose light sample this is
+                if (SMODE != 0 && SMODE != 1) {  // in the hit word of the vertex whose light sample this is
                     float* hwp = SMODE == 3 ? &tape_rec(S, Q, (info & 255) - 1, slot)[2].w
                                             : &hit_rec(S, Q, (info & 255) - 1, slot)->x;
                     uint32_t hw = (uint32_t)__float_as_int(*hwp);
@@ -673,7 +670,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     } else {
                         st12(C + 4, Ee);
                     }
-                    C[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);  // a whole 128-byte record is written
+                    // a whole 128-byte record is written; a pending light sample's visibility as if
+                    // visible (traversal rewrites it for an occluded one)
+                    C[7] = f4(__int_as_float(shadow ? NEE_VISIBLE : 0), 0.0f, 0.0f, 0.0f);
                 }
                 if (MODE != 4 && MODE != 1 && shadow) {  // a whole record (the Stokes words are [2..4]; partial ones measured slower)
                     H[0] = f4(so.x, so.y, so.z, stmax);
