@@ -36,7 +36,8 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [4..6] E_b (12 words; with the next-event part as if visible when a light sample is pending, set
 //     back to E_b by the shadow-ray traversal if occluded), overwritten by the fold with the suffix radiance beyond the vertex,
 //     L[b+1], which is what the replay of vertex b reads (not stored for a path's last vertex)
-//     [7] x: the next-event visibility written by the shadow-ray traversal
+//     [7] x: the next-event visibility (written as visible by shading for a pending light sample,
+//     rewritten with E_b's words by the shadow-ray traversal when it is occluded)
 //   hitword = prim | next-event state << 26 | weight kind << 29 (the state as sampled: pending for a
 //   light sample; its visibility goes to [7])
 //   hybrid replay (checkpoint interval k): per vertex a hit record [hitword, u-or-t, v, -] (16 B);
