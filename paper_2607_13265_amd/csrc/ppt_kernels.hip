@@ -1039,6 +1039,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
             Hs[0] = f4(d.x, d.y, d.z, __int_as_float(info_make((int)S.nv[i], false, v)));  // (B read again: fewer live registers)
             Hs[1] = f4(__uint_as_float(pix), __uint_as_float(smp), 0.0f, 0.0f);
             st12(Hs + 2, av);
+            // the rest of the 128-byte record where nothing else fills it (a line written in part
+            // is the slower path)
+            if (!PPRB && !(HYB && A.hyb_rule)) Hs[5] = Hs[6] = Hs[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
             if (pol) {
                 if (tkey != v) {
                     if (tkey >= 0) K.g(A.views[tkey].theta_slot, A.views[tkey].theta_off, gtheta);
