@@ -182,6 +182,11 @@ DEV float4* ray_rec(const PathState& S, int i) { return S.ray + (size_t)i * RAY_
 DEV float4* shd_rec(const PathState& S, int i) { return S.shd + (size_t)i * SHD_F4; }
 DEV float4* acc_rec(const PathState& S, int i) { return S.acc + (size_t)i * ACC_F4; }
 DEV float4* r1_rec(const PathState& S, int i) { return S.acc + (size_t)i * R1_F4; }  // (rank-one render)
+// The cached backward's bounces use the shadow-record array as two dense arrays (the fold later
+// writes whole 128-byte records there): a 32-byte shadow ray per slot, four to a cache line, and
+// the 48-byte E_b of an emitting vertex behind them.
+DEV float4* shd1_rec(const PathState& S, int i) { return S.shd + (size_t)i * 2; }
+DEV float4* emit1_rec(const PathState& S, int Q, int i) { return S.shd + (size_t)Q * 2 + (size_t)i * 3; }
 DEV float4* cache_rec(const PathState& S, int Q, int b0, int i) {  // b0: 0-based vertex index
     return S.cache + ((size_t)b0 * Q + i) * CACHE_F4;
 }
@@ -211,6 +216,7 @@ DEV void ray_set(float4* R, v3 o, v3 d, float Cs = 0.0f, float Ss = 0.0f) {
 }
 
 constexpr int INFO_DEAD = 1 << 9;
+constexpr int INFO_EMIT = 1 << 10;  // (a cached-backward shadow ray's vertex emits: its E_b is kept)
 DEV int info_make(int nverts, bool prev_delta, int view) { return nverts | (prev_delta ? 256 : 0) | (view << 12); }
 
 // World of a view: in a scene of one world it comes from the launch arguments (wave-uniform
@@ -270,7 +276,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 slot = S.squeue[idx];
                 // the shadow ray and its vertex's info word in one record (no read of the ray
                 // record, whose line would be fetched for its 16-byte key word)
-                const float4* H = SMODE == 4 ? r1_rec(S, slot) + 2 : shd_rec(S, slot);
+                const float4* H = SMODE == 4 ? r1_rec(S, slot) + 2 : SMODE == 1 ? shd1_rec(S, slot) : shd_rec(S, slot);
                 const float4 s0 = H[0], s1 = H[1];
                 info = __float_as_int(s1.w);
                 trav_begin(T, world_of(A, info >> 12),
@@ -342,13 +348,19 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 const float4* H = shd_rec(S, slot);
                 if (SMODE == 1) {
                     // the cache record holds E_b plus the next-event part and a visible sample
-                    // (k_shade<1>); an occluded light sample sets the E words back to E_b, kept in the
-                    // shadow record's words 5..7, and its visibility word (two whole 32-byte sectors);
-                    // a visible one writes nothing
+                    // (k_shade<1>); an occluded light sample sets the E words back to E_b (zero unless
+                    // the vertex emits, when it was kept beside the shadow rays) and its visibility word
+                    // (two whole 32-byte sectors); a visible one writes nothing
                     if (occ) {
                         float4* dst = cache_rec(S, Q, (info & 255) - 1, slot) + 4;
+                        if (info & INFO_EMIT) {
+                            const float4* Eb = emit1_rec(S, Q, slot);
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) dst[k] = H[5 + k];
+                            for (int k = 0; k < 3; ++k) dst[k] = Eb[k];
+                        } else {  // (E_b is zero)
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) dst[k] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+                        }
                         dst[3] = f4(__int_as_float(NEE_OCCLUDED), 0.0f, 0.0f, 0.0f);
                     }
                 } else if (SMODE != 2) {  // the hybrid replay recomputes the next-event part from the visibility bit
@@ -662,11 +674,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
 #pragma unroll
                         for (int k = 0; k < 12; ++k) EN[k] = Ee[k] + En[k];
                         st12(C + 4, EN);
-                        // the whole shadow record: ray, next-event part, E_b (for an occluded sample)
-                        H[0] = f4(so.x, so.y, so.z, stmax);
-                        H[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_shd));
-                        st12(H + 2, En);
-                        st12(H + 5, Ee);
+                        // the shadow ray in its dense 32-byte record, and E_b where the vertex emits (an
+                        // occluded sample restores it; a non-emitting vertex's E_b is zero)
+                        float4* H1 = shd1_rec(S, slot);
+                        H1[0] = f4(so.x, so.y, so.z, stmax);
+                        H1[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_shd | (x.emit ? INFO_EMIT : 0)));
+                        if (x.emit) st12(emit1_rec(S, A.Q, slot), Ee);
                     } else {
                         st12(C + 4, Ee);
                     }
