@@ -27,10 +27,11 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     camera ray's direction, info   [1] pix smp - -   [2..4] the replay's adjoint rows
 //   accumulator record (render), ACC_F4 = 8 vectors (128 B):
 //     [0..3] prefix Mueller product beta (16)   [4] beta RGB scales (3)   [5..7] radiance Lo (12)
-//   rank-one render record (every view a linear polarizer), R1_F4 = 6 vectors (96 B, three whole
-//   32-byte sectors): [0] rho = q^T R_s beta   [1] RGB scales   [2] shadow ray origin, tmax   [3] its
-//   direction, info   [4] y_c = q^T R_s Lo_c (3), with a pending next-event part included as if
-//   visible   [5] y without that part (restored for an occluded sample); no shadow record
+//   rank-one render record (every view a linear polarizer), R1_F4 = 4 vectors (64 B, two to a cache
+//   line): [0] rho = q^T R_s beta   [1] RGB scales   [2] y_c = q^T R_s Lo_c (3), with a pending
+//   next-event part included as if visible   [3] y without that part (restored for an occluded
+//   sample); the shadow ray in a dense 32-byte record behind the chunk's rank-one records, [0] origin,
+//   tmax   [1] direction, info; no shadow record
 //   cache record (backward), one per (vertex b, slot), CACHE_F4 = 8 vectors (128 B):
 //     [0] rgb0 rgb1 rgb2 A   [1] B C D Cin   [2] Sin Cout Sout hitword   [3] u-or-t v - -
 //     [4..6] E_b (12 words; with the next-event part as if visible when a light sample is pending, set
@@ -49,7 +50,7 @@ constexpr int STACK = 64;       // BVH traversal stack entries per lane
 //     [0..7] as the cache record (E_b stays: the reverse sweep reads it)   [8..11] the prefix
 //     throughput beta_b (shared 4x4)   [12] its RGB scales, previous vertex delta   [13..14] the ray into
 //     the vertex (o, d)
-constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, R1_F4 = 6, CACHE_F4 = 8, CKPT_F4 = 5, TAPE_F4 = 15;
+constexpr int RAY_F4 = 4, SHD_F4 = 8, ACC_F4 = 8, R1_F4 = 4, CACHE_F4 = 8, CKPT_F4 = 5, TAPE_F4 = 15;
 
 enum MatType : int32_t { MAT_LAMBERT = 0, MAT_DIELECTRIC = 1, MAT_GGX_DIELECTRIC = 2, MAT_GGX_CONDUCTOR = 3,
                          MAT_SHEET = 4, MAT_EMITTER = 5, MAT_BLEND = 6 };

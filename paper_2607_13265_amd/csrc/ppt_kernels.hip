@@ -182,6 +182,9 @@ DEV float4* ray_rec(const PathState& S, int i) { return S.ray + (size_t)i * RAY_
 DEV float4* shd_rec(const PathState& S, int i) { return S.shd + (size_t)i * SHD_F4; }
 DEV float4* acc_rec(const PathState& S, int i) { return S.acc + (size_t)i * ACC_F4; }
 DEV float4* r1_rec(const PathState& S, int i) { return S.acc + (size_t)i * R1_F4; }  // (rank-one render)
+// the rank-one render's shadow rays: a dense 32-byte record per slot behind the rank-one records
+DEV float4* r1_shd(const PathState& S, int Q, int i) { return S.acc + (size_t)Q * R1_F4 + (size_t)i * 2; }
+static_assert(R1_F4 + 2 <= ACC_F4, "the rank-one records and their shadow rays fit in the accumulator array");
 // The cached backward's bounces use the shadow-record array as two dense arrays (the fold later
 // writes whole 128-byte records there): a 32-byte shadow ray per slot, four to a cache line, and
 // the 48-byte E_b of an emitting vertex behind them.
@@ -276,7 +279,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 slot = S.squeue[idx];
                 // the shadow ray and its vertex's info word in one record (no read of the ray
                 // record, whose line would be fetched for its 16-byte key word)
-                const float4* H = SMODE == 4 ? r1_rec(S, slot) + 2 : SMODE == 1 ? shd1_rec(S, slot) : shd_rec(S, slot);
+                const float4* H = SMODE == 4 ? r1_shd(S, Q, slot) : SMODE == 1 ? shd1_rec(S, slot) : shd_rec(S, slot);
                 const float4 s0 = H[0], s1 = H[1];
                 info = __float_as_int(s1.w);
                 trav_begin(T, world_of(A, info >> 12),
@@ -337,10 +340,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
             alive = false;
             if (SMODE == 4 && any) {
                 // rank-one render: the path's radiance words already hold the next-event part
-                // (k_shade<4>); an occluded light sample restores them from word 5
+                // (k_shade<4>); an occluded light sample restores them from word 3
                 if (T.h.prim >= 0) {
                     float4* AC = r1_rec(S, slot);
-                    AC[4] = AC[5];
+                    AC[2] = AC[3];
                 }
                 if (A.sig) sig_add(A.sig[A.g0 + slot], (uint32_t)(T.h.prim >= 0 ? NEE_OCCLUDED : NEE_VISIBLE));
             } else if (SMODE >= 0 && any) {
@@ -534,7 +537,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     // needs per channel only the scalar y_c = q^T R_s Lo_c (q: the analyzer's row, R_s:
                     // the sensor rotation).  The path carries the row rho = q^T R_s beta (shared by
                     // the channels, beside beta's RGB scales) instead of beta, and y instead of Lo:
-                    // one 96-byte record [rho | rgb | shadow ray o, tmax | d, info | y | y before the next-event part]
+                    // one 64-byte record [rho | rgb | y | y before the next-event part], the shadow ray
+                    // in a dense record of its own
                     float4* AC = r1_rec(S, slot);
                     float rho[4], brgb[3], y[3];
                     if (nb == 0) {
@@ -549,7 +553,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
 #pragma unroll
                         for (int c = 0; c < 3; ++c) { brgb[c] = 1.0f; y[c] = 0.0f; }
                     } else {
-                        const float4 a0 = AC[0], a1 = AC[1], a4 = AC[4];
+                        const float4 a0 = AC[0], a1 = AC[1], a4 = AC[2];
                         rho[0] = a0.x; rho[1] = a0.y; rho[2] = a0.z; rho[3] = a0.w;
                         brgb[0] = a1.x; brgb[1] = a1.y; brgb[2] = a1.z;
                         y[0] = a4.x; y[1] = a4.y; y[2] = a4.z;
@@ -578,15 +582,18 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE
                     // the whole record (partial records measured slower)
                     AC[0] = f4(rho[0], rho[1], rho[2], rho[3]);
                     AC[1] = f4(brgb[0], brgb[1], brgb[2], 0.0f);
-                    AC[2] = shadow ? f4(so.x, so.y, so.z, stmax) : f4(0.0f, 0.0f, 0.0f, 0.0f);
-                    AC[3] = shadow ? f4(sd.x, sd.y, sd.z, __int_as_float(info_shd)) : f4(0.0f, 0.0f, 0.0f, 0.0f);
                     // y with the next-event part as if its light sample were visible (traversal then
-                    // writes nothing for a visible one, and restores y from word 5 for an occluded one)
+                    // writes nothing for a visible one, and restores y from word 3 for an occluded one)
                     if (shadow)
-                        AC[4] = f4(y[0] + pn[0], y[1] + pn[1], y[2] + pn[2], 0.0f);
+                        AC[2] = f4(y[0] + pn[0], y[1] + pn[1], y[2] + pn[2], 0.0f);
                     else
-                        AC[4] = f4(y[0], y[1], y[2], 0.0f);
-                    AC[5] = f4(y[0], y[1], y[2], 0.0f);
+                        AC[2] = f4(y[0], y[1], y[2], 0.0f);
+                    AC[3] = f4(y[0], y[1], y[2], 0.0f);
+                    if (shadow) {  // the shadow ray in its dense 32-byte record
+                        float4* H4 = r1_shd(S, A.Q, slot);
+                        H4[0] = f4(so.x, so.y, so.z, stmax);
+                        H4[1] = f4(sd.x, sd.y, sd.z, __int_as_float(info_shd));
+                    }
                 } else if (MODE == 0 || MODE == 3) {
                     float4* AC = acc_rec(S, slot);
                     float beta[16], brgb[3], Lo[12];
@@ -740,7 +747,7 @@ __global__ void __launch_bounds__(BLOCK) k_accum(WArgs A) {
             v = id.v; lx = id.lx; ly = id.ly;
             key = ((int64_t)v << 32) | (int64_t)id.pix;
             if (S.nv[i]) {
-                const float4 y = r1_rec(S, i)[4];
+                const float4 y = r1_rec(S, i)[2];
                 acc[0] = y.x; acc[1] = y.y; acc[2] = y.z;
             }
         } else if (valid) {
