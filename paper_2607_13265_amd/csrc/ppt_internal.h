@@ -189,6 +189,7 @@ struct WArgs {
     float pprb_sigma;       // its noise deviation
     int32_t ext;            // the scene uses normal maps, specular maps or circular emitters
     int32_t r1;             // render by the rank-one record (every view has a linear-polarizer sensor, no ext)
+    int32_t r1adj;          // cached backward of such a batch: the replay start record's rank-one form
     float* out;             // render output
     const float* dout;      // backward: dL/dStokes
     double* gacc;           // backward: FP64 gradient accumulators

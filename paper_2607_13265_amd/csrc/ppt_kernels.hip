@@ -185,6 +185,11 @@ DEV float4* r1_rec(const PathState& S, int i) { return S.acc + (size_t)i * R1_F4
 // the rank-one render's shadow rays: a dense 32-byte record per slot behind the rank-one records
 DEV float4* r1_shd(const PathState& S, int Q, int i) { return S.acc + (size_t)Q * R1_F4 + (size_t)i * 2; }
 static_assert(R1_F4 + 2 <= ACC_F4, "the rank-one records and their shadow rays fit in the accumulator array");
+// The cached replay's start record in its rank-one form (every view a linear-polarizer sensor): the
+// adjoint rows are s_c r with one row r shared by the channels, so the record is 64 bytes, two to a
+// line, in the shadow-record array: [0] camera-ray direction, info  [1] pix, smp, r1, r2  [2] s_c
+// (r0 = 1, r3 = 0).
+DEV float4* rst_rec(const PathState& S, int i) { return S.shd + (size_t)i * 4; }
 // The cached backward's bounces use the shadow-record array as two dense arrays (the fold later
 // writes whole 128-byte records there): a 32-byte shadow ray per slot, four to a cache line, and
 // the 48-byte E_b of an emitting vertex behind them.
@@ -1055,13 +1060,25 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HYB 
             }
             // the replay's start in one record: the camera ray's direction (its origin is the view's),
             // the info word (vertex count, view), the keys and the adjoint rows
-            float4* Hs = shd_rec(S, i);
-            Hs[0] = f4(d.x, d.y, d.z, __int_as_float(info_make((int)S.nv[i], false, v)));  // (B read again: fewer live registers)
-            Hs[1] = f4(__uint_as_float(pix), __uint_as_float(smp), 0.0f, 0.0f);
-            st12(Hs + 2, av);
-            // the rest of the 128-byte record where nothing else fills it (a line written in part
-            // is the slower path)
-            if (!PPRB && !(HYB && A.hyb_rule)) Hs[5] = Hs[6] = Hs[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+            const int info_rs = info_make((int)S.nv[i], false, v);  // (B read again: fewer live registers)
+            if (!HYB && !PPRB && !TAPE && A.r1adj) {
+                // rank-one form: a linear polarizer's analyzer row is q' = (1, C, S, 0) and a_c = s_c q'^T
+                // rotated by R_s, with s_c = asens_c0
+                const float C2 = cosf(2.0f * theta), S2 = sinf(2.0f * theta);
+                float4* Hr = rst_rec(S, i);
+                Hr[0] = f4(d.x, d.y, d.z, __int_as_float(info_rs));
+                Hr[1] = f4(__uint_as_float(pix), __uint_as_float(smp), Cs * C2 - Ss * S2, Ss * C2 + Cs * S2);
+                Hr[2] = f4(asens[0], asens[4], asens[8], 0.0f);
+                Hr[3] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                float4* Hs = shd_rec(S, i);
+                Hs[0] = f4(d.x, d.y, d.z, __int_as_float(info_rs));
+                Hs[1] = f4(__uint_as_float(pix), __uint_as_float(smp), 0.0f, 0.0f);
+                st12(Hs + 2, av);
+                // the rest of the 128-byte record where nothing else fills it (a line written in part
+                // is the slower path)
+                if (!PPRB && !(HYB && A.hyb_rule)) Hs[5] = Hs[6] = Hs[7] = f4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
             if (pol) {
                 if (tkey != v) {
                     if (tkey >= 0) K.g(A.views[tkey].theta_slot, A.views[tkey].theta_off, gtheta);
@@ -1265,8 +1282,9 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
         const int idx = F.take(slot < 0, n, &S.counts[4]);
         if (idx >= 0) {
             slot = S.queue0[idx];
-            // the path's start as the fold left it in the shadow record (one record per path)
-            const float4* H = shd_rec(S, slot);
+            // the path's start as the fold left it in the shadow-record array (one record per path)
+            const bool r1s = !HYB && !PPRB && A.r1adj;  // (the 64-byte rank-one form)
+            const float4* H = r1s ? rst_rec(S, slot) : shd_rec(S, slot);
             const float4 h0 = H[0], h1 = H[1];
             const int info = __float_as_int(h0.w);
             B = info & 255;
@@ -1275,7 +1293,16 @@ __global__ void __launch_bounds__(BLOCK) k_replay(WArgs A) {
             prev_delta = false;
             pix = __float_as_uint(h1.x);
             smp = __float_as_uint(h1.y);
-            ld12(H + 2, av);
+            if (r1s) {
+                const float4 h2 = H[2];
+                const float sc[3] = {h2.x, h2.y, h2.z};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    av[4 * c] = sc[c]; av[4 * c + 1] = sc[c] * h1.z; av[4 * c + 2] = sc[c] * h1.w; av[4 * c + 3] = 0.0f;
+                }
+            } else {
+                ld12(H + 2, av);
+            }
             if (PPRB) ld12(H + 5, Lcur);
             d = mk(h0.x, h0.y, h0.z);
             o = ld3(gval(A.views, (size_t)v).o);  // (a pinhole camera's rays leave the view's origin)
@@ -1729,6 +1756,9 @@ static void launch_extend(const WArgs& a, int grid, size_t lds, hipStream_t s) {
 // One chunk of paths through every bounce.  mode 0: render, 1: backward.  M is told the family
 // of every kernel before its launch (event timing).
 hipError_t launch_chunk(WArgs a, int mode, const LaunchGrid& G, hipStream_t s, const LaunchMarker& M) {
+    // the backward's rank-one replay start (cached replay; the comparators and the hybrid keep the
+    // general record)
+    a.r1adj = mode == 1 && a.r1 && a.ckpt == 0 && !a.pprb && !a.tape && !a.prb ? 1 : 0;
     if (mode != 0 || !a.S.nv) a.r1 = 0;  // (the rank-one record is the render's, with its vertex flags)
     size_t lds = (size_t)a.stack_cap * BLOCK * sizeof(int);
     M(KF_OTHER, s);
