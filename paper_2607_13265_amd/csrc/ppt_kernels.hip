@@ -421,8 +421,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STAT
                 if (S.nv) S.nv[slot] = T.h.prim >= 0 ? 1 : 0;
             } else {
                 float4* R = ray_rec(S, slot);
-                // the hit in one aligned 16-byte store (a hit's distance is the final tb)
-                R[2] = f4(T.tb, T.h.u, T.h.v, __int_as_float(T.h.prim));
+                // the hit in one aligned 16-byte store (a hit's distance is the final tb); a miss
+                // writes only its outcome byte (its path ends: nothing reads the hit words)
+                if (T.h.prim >= 0) R[2] = f4(T.tb, T.h.u, T.h.v, __int_as_float(T.h.prim));
                 S.hflag[slot] = T.h.prim >= 0 ? 1 : 0;
             }
         }
