@@ -190,6 +190,8 @@ static_assert(R1_F4 + 2 <= ACC_F4, "the rank-one records and their shadow rays f
 // line, in the shadow-record array: [0] camera-ray direction, info  [1] pix, smp, r1, r2  [2] s_c
 // (r0 = 1, r3 = 0).
 DEV float4* rst_rec(const PathState& S, int i) { return S.shd + (size_t)i * 4; }
+static_assert(2 + 3 <= SHD_F4 && 4 <= SHD_F4,
+              "the dense shadow rays, emitting E_b and rank-one start records fit in the shadow-record array");
 // The cached backward's bounces use the shadow-record array as two dense arrays (the fold later
 // writes whole 128-byte records there): a 32-byte shadow ray per slot, four to a cache line, and
 // the 48-byte E_b of an emitting vertex behind them.
